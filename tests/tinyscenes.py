@@ -1,0 +1,67 @@
+"""Hand-built tiny scenes for closed-form pins (shared by CPU and GPU tests)."""
+import math
+
+import numpy as np
+
+from paper_1812_04719_amd.scenes import Scene, Topology
+
+
+def square_grid(n, size, theta, center, z):
+    """Triangulated planar square of n x n quads in the plane z = const,
+    rotated by theta about the z axis.  Returns (points [nv,3], Topology)."""
+    xs = (np.arange(n + 1) / n - 0.5) * size
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    c, s = math.cos(theta), math.sin(theta)
+    R = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+    pts = pts @ R.T + np.array([center[0], center[1], z])
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b = i * (n + 1) + j, i * (n + 1) + j + 1
+            c2, d2 = (i + 1) * (n + 1) + j + 1, (i + 1) * (n + 1) + j
+            tris.append((a, d2, c2))
+            tris.append((a, c2, b))
+    tri = np.array(tris, dtype=np.int32)
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0).astype(np.int32)
+    return pts, Topology(order=-(1000 + n), nv=pts.shape[0], tri=tri, edge=e)
+
+
+def two_body_scene(p0a, p1a, topo_a, p0b, p1b, topo_b, box_len=(0, 0, 0), d=0.01, eps=1.0, dt=0.1):
+    same = topo_a is topo_b
+    topos = [topo_a] if same else [topo_a, topo_b]
+    tid = np.array([0, 0 if same else 1], dtype=np.int32)
+    x0 = np.ascontiguousarray(np.concatenate([p0a, p0b]).T)
+    x1 = np.ascontiguousarray(np.concatenate([p1a, p1b]).T)
+    off = np.array([0, p0a.shape[0], p0a.shape[0] + p0b.shape[0]], dtype=np.int32)
+    return Scene(x0=x0, x1=x1, vtx_off=off, topo_id=tid, scene_off=np.array([0, 2], dtype=np.int32),
+                 box_len=np.asarray(box_len, dtype=np.float64).reshape(1, 3), topos=topos, d=d, eps=eps, dt=dt)
+
+
+def translating_planes(gap=0.05, closing=0.1, d=0.01, n=6, size=1.0, theta_deg=17.0, dt=0.1, eps=1.0):
+    """Two parallel squares, gap `gap`, the top one moving down by `closing`.
+
+    The distance between the planes is gap - closing * s, so every contact
+    (vertex-triangle or edge-edge) happens at s* = (gap - d) / closing.
+    """
+    pa, ta = square_grid(n, size, 0.0, (0.013, -0.007), 0.0)
+    pb, tb = square_grid(n, size, math.radians(theta_deg), (0.0, 0.0), gap)
+    mv = np.array([0.0, 0.0, -closing])
+    return two_body_scene(pa, pa.copy(), ta, pb, pb + mv, tb, d=d, eps=eps, dt=dt)
+
+
+def tetra(center, scale=1.0, rot=None):
+    pts = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64) * scale / math.sqrt(3)
+    if rot is not None:
+        pts = pts @ rot.T
+    pts = pts + np.asarray(center)
+    tri = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]], dtype=np.int32)
+    # orient outward
+    for k in range(4):
+        a, b, c = pts[tri[k]]
+        n = np.cross(b - a, c - a)
+        if np.dot(n, (a + b + c) / 3 - pts.mean(0)) < 0:
+            tri[k] = tri[k][[0, 2, 1]]
+    e = np.unique(np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1), axis=0)
+    return pts, Topology(order=-4, nv=4, tri=tri, edge=e.astype(np.int32))
