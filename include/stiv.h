@@ -1,0 +1,168 @@
+/*
+ * stiv.h -- C ABI of the MI355X (gfx950) contact-detection library.
+ *
+ * Computes, for vesicle surface meshes at t_n (X0) and at the candidate
+ * position t_{n+1} (X1), following Lu, Rahimian & Zorin, "Parallel
+ * contact-aware simulations of deformable particles in 3D Stokes flow":
+ *
+ *   - space-time bounding boxes of every vesicle (Sec. 3.3.1; Alg. 2,
+ *     getBoundingBox), inflated by d/2 per side;
+ *   - candidate vesicle pairs through a Morton-ordered implicit grid of check
+ *     points (Alg. 1: average box diagonal, check points, stable sort by
+ *     Morton ID, per-cell pair test, unique);
+ *   - primitive candidates inside each vesicle pair (vertex-triangle both
+ *     ways, edge-edge) whose space-time boxes intersect;
+ *   - the narrow phase: earliest s in [0,1] where a vertex comes within d of
+ *     a triangle's plane with its projection inside the triangle (Eq. 3.1,
+ *     linear trajectories), and the edge-edge analogue;
+ *   - each vertex-triangle contact's space-time interference volume
+ *     (Eq. 3.2, App. A) and its gradient with respect to X1 of the four
+ *     vertices, including the contact time's dependence on X1;
+ *   - one contact volume per vesicle pair, V = sum of V_k, and the rows of
+ *     the Jacobian J = dV/dX1 per (volume, vertex) (Sec. 3.1.2, 3.3.2).
+ *
+ * Conventions
+ *   - Every array pointer in stiv_scene and stiv_result is a DEVICE pointer
+ *     owned by the caller.  stiv_topology holds HOST pointers, copied by
+ *     stiv_set_topology.  The library owns only its context's scratch arena.
+ *   - Positions are FP64 SoA [3][n_vtx].  The narrow phase, volumes and
+ *     gradients are FP64; FP32 appears only in conservative pre-filters.
+ *   - Periodic image shifts sigma in Z^3 translate vesicle b by sigma*L.
+ *     Pairs are (a, b, sigma) with a < b, or a == b and sigma > 0
+ *     lexicographically (a vesicle against its own image).
+ *   - Sign: the exported volume is the nonnegative interference magnitude of
+ *     Eq. 3.2; the constraint of Eq. 2.5 / 3.4 is -V >= 0.
+ *   - Edge-edge contacts are detected and reported with their time but add
+ *     nothing to V or J (the paper sums vertex-triangle volumes only).
+ *   - Outputs are written in canonical order: pairs by (a, b, sigma),
+ *     contacts by (pair, kind, i, j), volumes by pair, J rows by (volume,
+ *     vertex).  Two runs on the same input are bit-identical.
+ *   - Errors: every entry point returns a stiv_status; stiv_last_error gives
+ *     a message.  On STIV_E_CAPACITY the n_* fields hold the required sizes
+ *     and the arrays are incomplete; reallocate and call again.
+ */
+#ifndef STIV_H
+#define STIV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stiv_ctx stiv_ctx;
+
+typedef enum {
+  STIV_OK = 0,
+  STIV_E_ARG = -1,      /* bad argument: d < 0, eps <= 0, dt <= 0, box_len < 0, bad offsets, no topology */
+  STIV_E_CAPACITY = -2, /* a caller-provided output array is too small (see n_* for the sizes needed) */
+  STIV_E_HIP = -3,      /* a HIP runtime call failed */
+  STIV_E_NUMERIC = -4,  /* a position is NaN or infinite */
+  STIV_E_STATE = -5     /* call order violated (e.g. detect before set_topology) */
+} stiv_status;
+
+/* Per-order mesh topology (HOST pointers), shared by all vesicles using it.
+ * Triangles are local vertex ids, oriented outward (counter-clockwise seen
+ * from outside); edges are (lo, hi) local ids.  Topology t owns triangles
+ * tri[tri_off[t] .. tri_off[t+1]) and edges edge[edge_off[t] .. edge_off[t+1]). */
+typedef struct {
+  int32_t n_topo;
+  const int32_t *nv;       /* [n_topo] vertices per vesicle of this topology */
+  const int32_t *tri;      /* [sum nt][3] */
+  const int32_t *tri_off;  /* [n_topo+1] */
+  const int32_t *edge;     /* [sum ne][2] */
+  const int32_t *edge_off; /* [n_topo+1] */
+} stiv_topology;
+
+/* A batch of independent scenes (DEVICE pointers).  Vesicle v owns global
+ * vertices [vtx_off[v], vtx_off[v+1]) and uses topology topo_id[v]; scene s
+ * owns vesicles [scene_off[s], scene_off[s+1]); pairs never cross scenes.
+ * box_len[s][c] > 0 makes axis c of scene s periodic with that period;
+ * 0 means free space on that axis. */
+typedef struct {
+  int32_t n_ves, n_vtx, n_scenes;
+  const int32_t *vtx_off;   /* [n_ves+1] */
+  const int32_t *topo_id;   /* [n_ves] */
+  const int32_t *scene_off; /* [n_scenes+1] */
+  const double *box_len;    /* [n_scenes][3] */
+  const double *x0;         /* [3][n_vtx] positions at t_n */
+  const double *x1;         /* [3][n_vtx] candidate positions at t_{n+1} */
+} stiv_scene;
+
+/* d: minimum separation of the triangle meshes, (1 + 2 alpha) d_m (Sec. 3.1.2);
+ * eps: velocity scale of the space-time metric (App. A), > 0; dt: time step, > 0. */
+enum { STIV_EMIT_CANDIDATES = 1u };
+typedef struct {
+  double d, eps, dt;
+  uint32_t flags;
+} stiv_params;
+
+/* Outputs.  The caller sets cap_* and the array pointers (DEVICE memory);
+ * the library writes the n_* counts (always the true count, also when it
+ * exceeds the capacity).
+ *   pair_ab [cap_pairs][2], pair_shift [cap_pairs][3]
+ *   cand    [cap_cand][4] = (pair, kind, i, j), written only with
+ *           STIV_EMIT_CANDIDATES (order unspecified)
+ *   ct_key  [cap_ct][4] = (pair, kind, i, j); kind 0: vertex i of a vs
+ *           triangle j of b; kind 1: vertex i of b vs triangle j of a;
+ *           kind 2: edge i of a vs edge j of b (local ids)
+ *   ct_tau  [cap_ct]    contact time tau = s* dt
+ *   ct_vol  [cap_ct]    V_k (0 for edge-edge)
+ *   ct_grad [cap_ct][12] dV_k/dX1 of (vertex, triangle corner 0, 1, 2)
+ *   vol_pair, vol_V [cap_vol]: contact volumes (pairs with >= 1 VT contact)
+ *   j_vol, j_vtx, j_g [cap_jrow] ([cap_jrow][3] for j_g): Jacobian rows
+ *           (volume index, global vertex id, dV/dX1 of that vertex) */
+typedef struct {
+  int64_t cap_pairs, n_pairs;
+  int32_t *pair_ab;
+  int32_t *pair_shift;
+  int64_t cap_cand, n_cand_vt, n_cand_ee;
+  int32_t *cand;
+  int64_t cap_ct, n_ct_vt, n_ct_ee;
+  int32_t *ct_key;
+  double *ct_tau, *ct_vol, *ct_grad;
+  int64_t cap_vol, n_vol;
+  int32_t *vol_pair;
+  double *vol_V;
+  int64_t cap_jrow, n_jrow;
+  int32_t *j_vol, *j_vtx;
+  double *j_g;
+  int64_t n_initially_within_d, n_degenerate_skipped;
+} stiv_result;
+
+/* Create a context on a HIP device.  *ctx is NULL on failure. */
+stiv_status stiv_create(stiv_ctx **ctx, int hip_device);
+stiv_status stiv_destroy(stiv_ctx *ctx);
+
+/* Copy the mesh topologies and build the library's patch tiling of each
+ * (groups of neighbouring triangles with their owned vertices and edges). */
+stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *topo);
+
+/* Pre-size the scratch arena for scenes of this shape (optional; detect
+ * grows it on demand). */
+stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p);
+
+/* Run the whole path on `stream` (a hipStream_t; NULL = default stream).
+ * All kernels are enqueued on the stream without host synchronisation; the
+ * call then synchronises the stream once to read the counts into *out. */
+stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out,
+                        void *stream);
+
+/* Milliseconds of the last detect, measured with HIP events on the call's
+ * stream: 0 box kernel, 1 vesicle broad phase (Morton grid), 2 patch-pair
+ * cull, 3 primitive candidates, 4 narrow phase with volumes and gradients,
+ * 5 aggregation, 6 whole call on the device.  Fills min(n, 7) values. */
+stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n);
+
+/* Device pointers to the library's internal Morton sort (tests only need
+ * it for the worked example of Alg. 1 / Table 3): stable sort of n 64-bit
+ * keys with 32-bit values, ascending, equal keys keep input order. */
+stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, void *stream);
+
+/* Message of the last error on this context (never NULL). */
+const char *stiv_last_error(const stiv_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STIV_H */

@@ -1,0 +1,376 @@
+// K1: vesicle broad phase on an implicit Morton-ordered grid (Alg. 1).
+//
+//   1. h_m = average diagonal of the scene's boxes (Alg. 1, first step); the
+//      uniform octree has depth ceil(log2(L / h_m)) (Sec. 3.3.1).
+//   2. Check points: per box and axis, points from lo to hi (both faces
+//      included) with spacing no larger than the cell edge, so every cell
+//      the box overlaps holds at least one of its points.  Each point is
+//      keyed by the Morton ID of its cell (wrapped on periodic axes) with the
+//      scene index in the high bits.
+//   3. Stable sort of the keys (ties keep the global check-point order,
+//      Table 3).
+//   4. For every run of equal keys, all pairs of distinct boxes are tested;
+//      every periodic image shift sigma with an overlap is inserted into a
+//      hash set (Alg. 1's "unique").
+//   5. The unique pairs are bucketed by their first vesicle and sorted
+//      inside each bucket, giving the canonical (a, b, sigma) order.
+// The overlap test is the exact FP64 closed-interval test on boxes shifted
+// by sigma * L; the grid only decides which pairs get tested.
+#include "stiv_common.h"
+
+namespace stiv {
+
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ inline uint64_t spread3(uint32_t x) {
+  uint64_t v = x & 0x3ffu;
+  v = (v | (v << 16)) & 0x30000ffull;
+  v = (v | (v << 8)) & 0x300f00full;
+  v = (v | (v << 4)) & 0x30c30c3ull;
+  v = (v | (v << 2)) & 0x9249249ull;
+  return v;
+}
+
+__device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+__device__ inline uint64_t pack_pair(int a, int b, const int s[3]) {
+  return ((uint64_t)(uint32_t)a << 36) | ((uint64_t)(uint32_t)b << 12) | ((uint64_t)(s[0] + 8) << 8) |
+         ((uint64_t)(s[1] + 8) << 4) | (uint64_t)(s[2] + 8);
+}
+
+__device__ inline uint64_t mix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ void hash_insert(uint64_t key, uint64_t *hash, int64_t cap, uint64_t *uniq, int64_t uniq_cap,
+                            Counters *cnt) {
+  uint64_t h = mix64(key) & (uint64_t)(cap - 1);
+  for (int64_t probe = 0; probe < cap; ++probe) {
+    uint64_t prev = atomicCAS((unsigned long long *)&hash[h], (unsigned long long)kEmpty,
+                              (unsigned long long)key);
+    if (prev == kEmpty) {
+      unsigned long long idx = atomicAdd(&cnt->n_pairs, 1ull);
+      if ((int64_t)idx < uniq_cap) uniq[idx] = key;
+      return;
+    }
+    if (prev == key) return;
+    h = (h + 1) & (uint64_t)(cap - 1);
+  }
+  atomicAdd(&cnt->hash_overflow, 1ull);
+}
+
+__device__ inline bool box_overlap_shifted(const double *A, const double *B, const double sh[3]) {
+  for (int c = 0; c < 3; ++c) {
+    double blo = B[c] + sh[c], bhi = B[3 + c] + sh[c];
+    if (!(A[c] <= bhi && blo <= A[3 + c])) return false;
+  }
+  return true;
+}
+
+// Insert every image shift of (a, b) whose shifted boxes overlap.
+__device__ void test_pair_all_shifts(int a, int b, const double *A, const double *B, const double *L,
+                                     uint64_t *hash, int64_t cap, uint64_t *uniq, int64_t uniq_cap,
+                                     Counters *cnt) {
+  int lo[3], hi[3];
+  for (int c = 0; c < 3; ++c) {
+    if (L[c] > 0.0) {
+      lo[c] = (int)floor((A[c] - B[3 + c]) / L[c]) - 1;
+      hi[c] = (int)ceil((A[3 + c] - B[c]) / L[c]) + 1;
+      if (lo[c] < -kMaxShift || hi[c] > kMaxShift) {
+        atomicAdd(&cnt->shift_overflow, 1ull);
+        lo[c] = lo[c] < -kMaxShift ? -kMaxShift : lo[c];
+        hi[c] = hi[c] > kMaxShift ? kMaxShift : hi[c];
+      }
+    } else {
+      lo[c] = hi[c] = 0;
+    }
+  }
+  int s[3];
+  for (s[0] = lo[0]; s[0] <= hi[0]; ++s[0])
+    for (s[1] = lo[1]; s[1] <= hi[1]; ++s[1])
+      for (s[2] = lo[2]; s[2] <= hi[2]; ++s[2]) {
+        if (a == b) {
+          // own image: keep sigma > 0 lexicographically
+          bool pos = s[0] > 0 || (s[0] == 0 && (s[1] > 0 || (s[1] == 0 && s[2] > 0)));
+          if (!pos) continue;
+        }
+        double sh[3];
+        for (int c = 0; c < 3; ++c) sh[c] = (double)s[c] * L[c];
+        if (box_overlap_shifted(A, B, sh)) hash_insert(pack_pair(a, b, s), hash, cap, uniq, uniq_cap, cnt);
+      }
+}
+
+__global__ void k_ves_scene(DevScene S, int *ves_scene) {
+  for (int sc = blockIdx.x * blockDim.x + threadIdx.x; sc < S.n_scenes; sc += gridDim.x * blockDim.x)
+    for (int v = S.scene_off[sc]; v < S.scene_off[sc + 1]; ++v) ves_scene[v] = sc;
+}
+
+__global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *box, SceneGrid *grid) {
+  __shared__ double sh_sum[256], sh_lo[3][256], sh_hi[3][256];
+  for (int sc = blockIdx.x; sc < S.n_scenes; sc += gridDim.x) {
+    const int v0 = S.scene_off[sc], v1 = S.scene_off[sc + 1];
+    double sum = 0.0, lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+      const double *B = box + 6 * (int64_t)v;
+      double dx = B[3] - B[0], dy = B[4] - B[1], dz = B[5] - B[2];
+      sum += sqrt(dx * dx + dy * dy + dz * dz);
+      for (int c = 0; c < 3; ++c) { lo[c] = fmin(lo[c], B[c]); hi[c] = fmax(hi[c], B[3 + c]); }
+    }
+    sh_sum[threadIdx.x] = sum;
+    for (int c = 0; c < 3; ++c) { sh_lo[c][threadIdx.x] = lo[c]; sh_hi[c][threadIdx.x] = hi[c]; }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+        sh_sum[threadIdx.x] += sh_sum[threadIdx.x + off];
+        for (int c = 0; c < 3; ++c) {
+          sh_lo[c][threadIdx.x] = fmin(sh_lo[c][threadIdx.x], sh_lo[c][threadIdx.x + off]);
+          sh_hi[c][threadIdx.x] = fmax(sh_hi[c][threadIdx.x], sh_hi[c][threadIdx.x + off]);
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      SceneGrid g;
+      const int n = v1 - v0;
+      const double hm = n > 0 ? sh_sum[0] / n : 1.0;
+      double ext[3], lmax = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        const double L = S.box_len[3 * sc + c];
+        g.periodic[c] = L > 0.0;
+        if (L > 0.0) {
+          g.org[c] = 0.0;
+          ext[c] = L;
+        } else {
+          g.org[c] = n > 0 ? sh_lo[c][0] : 0.0;
+          ext[c] = n > 0 ? sh_hi[c][0] - sh_lo[c][0] : 1.0;
+        }
+        lmax = fmax(lmax, ext[c]);
+      }
+      int depth = 0;
+      if (hm > 0.0 && lmax > hm) depth = (int)ceil(log2(lmax / hm));
+      depth = depth < 0 ? 0 : (depth > 10 ? 10 : depth);
+      g.depth = depth;
+      g.tiny = 1e-9 * fmax(lmax, 1.0);
+      for (int c = 0; c < 3; ++c) g.w[c] = fmax(ext[c], g.tiny) / (double)(1 << depth);
+      g.pad = 0;
+      grid[sc] = g;
+    }
+    __syncthreads();
+  }
+}
+
+// Number of check points of a box on one axis; full = every cell of a
+// periodic axis (box at least one period long).
+__device__ inline int axis_points(const SceneGrid &g, int c, double lo, double hi, bool *full) {
+  const double e = (hi - lo) + 2.0 * g.tiny;
+  const int ncell = 1 << g.depth;
+  *full = false;
+  if (g.periodic[c] && e >= g.w[c] * ncell) {
+    *full = true;
+    return ncell;
+  }
+  int n = (int)ceil(e / g.w[c]) + 1;
+  if (n < 2) n = 2;
+  if (n > ncell + 2) n = ncell + 2;
+  return n;
+}
+
+__device__ inline uint32_t axis_cell(const SceneGrid &g, int c, double lo, double hi, int k, int n, bool full) {
+  const int ncell = 1 << g.depth;
+  if (full) return (uint32_t)k;
+  const double a = lo - g.tiny, e = (hi - lo) + 2.0 * g.tiny;
+  const double x = (k == n - 1) ? (hi + g.tiny) : a + e * ((double)k / (double)(n - 1));
+  long long ci = (long long)floor((x - g.org[c]) / g.w[c]);
+  if (g.periodic[c]) {
+    ci %= ncell;
+    if (ci < 0) ci += ncell;
+  } else {
+    ci = ci < 0 ? 0 : (ci >= ncell ? ncell - 1 : ci);
+  }
+  return (uint32_t)ci;
+}
+
+__global__ void k_cp_count(DevScene S, const double *box, const int *ves_scene, const SceneGrid *grid,
+                           int64_t *cnt_out) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
+    const SceneGrid g = grid[ves_scene[v]];
+    const double *B = box + 6 * (int64_t)v;
+    int64_t tot = 1;
+    for (int c = 0; c < 3; ++c) {
+      bool full;
+      tot *= axis_points(g, c, B[c], B[3 + c], &full);
+    }
+    cnt_out[v] = tot;
+  }
+}
+
+__global__ void k_cp_emit(DevScene S, const double *box, const int *ves_scene, const SceneGrid *grid,
+                          const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
+    const int sc = ves_scene[v];
+    const SceneGrid g = grid[sc];
+    const double *B = box + 6 * (int64_t)v;
+    int n[3];
+    bool full[3];
+    for (int c = 0; c < 3; ++c) n[c] = axis_points(g, c, B[c], B[3 + c], &full[c]);
+    int64_t o = cp_off[v];
+    for (int kx = 0; kx < n[0]; ++kx) {
+      uint32_t cx = axis_cell(g, 0, B[0], B[3], kx, n[0], full[0]);
+      for (int ky = 0; ky < n[1]; ++ky) {
+        uint32_t cy = axis_cell(g, 1, B[1], B[4], ky, n[1], full[1]);
+        for (int kz = 0; kz < n[2]; ++kz) {
+          uint32_t cz = axis_cell(g, 2, B[2], B[5], kz, n[2], full[2]);
+          if (o < cap) {
+            keys[o] = ((uint64_t)sc << 30) | morton3(cx, cy, cz);
+            vals[o] = (uint32_t)v;
+          }
+          ++o;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_cell_pairs(DevScene S, const double *box, const int *ves_scene, const uint64_t *keys,
+                             const uint32_t *vals, const unsigned long long *n_cp, int64_t cap_cp, uint64_t *hash,
+                             int64_t cap,
+                             uint64_t *uniq, int64_t uniq_cap, Counters *cnt) {
+  int64_t n = (int64_t)*n_cp;
+  n = n < cap_cp ? n : cap_cp;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    const int vi = (int)vals[i];
+    for (int64_t j = i + 1; j < n && keys[j] == k; ++j) {
+      const int vj = (int)vals[j];
+      if (vi == vj) continue;
+      const int a = vi < vj ? vi : vj, b = vi < vj ? vj : vi;
+      const double *L = S.box_len + 3 * ves_scene[a];
+      test_pair_all_shifts(a, b, box + 6 * (int64_t)a, box + 6 * (int64_t)b, L, hash, cap, uniq, uniq_cap, cnt);
+    }
+  }
+}
+
+__global__ void k_self_pairs(DevScene S, const double *box, const int *ves_scene, uint64_t *hash, int64_t cap,
+                             uint64_t *uniq, int64_t uniq_cap, Counters *cnt) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
+    const double *L = S.box_len + 3 * ves_scene[v];
+    if (!(L[0] > 0.0 || L[1] > 0.0 || L[2] > 0.0)) continue;
+    const double *A = box + 6 * (int64_t)v;
+    test_pair_all_shifts(v, v, A, A, L, hash, cap, uniq, uniq_cap, cnt);
+  }
+}
+
+__global__ void k_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, const Counters *cnt) {
+  int64_t n = (int64_t)cnt->n_pairs;
+  n = n < uniq_cap ? n : uniq_cap;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt_a[(int)(uniq[i] >> 36)], 1);
+}
+
+__global__ void k_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const int64_t *off_a, int32_t *cursor,
+                                 uint64_t *sorted, const Counters *cnt) {
+  int64_t n = (int64_t)cnt->n_pairs;
+  n = n < uniq_cap ? n : uniq_cap;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = uniq[i];
+    const int a = (int)(k >> 36);
+    const int pos = atomicAdd(&cursor[a], 1);
+    sorted[off_a[a] + pos] = k;
+  }
+}
+
+__global__ void k_bucket_sort_emit(DevScene S, const int *ves_scene, const int64_t *off_a, uint64_t *sorted,
+                                   int n_ves, PairRec *pairs, int32_t *pair_ab, int32_t *pair_shift,
+                                   int64_t cap_pairs) {
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_ves; a += gridDim.x * blockDim.x) {
+    const int64_t p0 = off_a[a], p1 = off_a[a + 1];
+    for (int64_t i = p0 + 1; i < p1; ++i) {  // insertion sort (buckets hold a handful of pairs)
+      uint64_t k = sorted[i];
+      int64_t j = i - 1;
+      while (j >= p0 && sorted[j] > k) {
+        sorted[j + 1] = sorted[j];
+        --j;
+      }
+      sorted[j + 1] = k;
+    }
+    const double *L = S.box_len + 3 * ves_scene[a];
+    for (int64_t i = p0; i < p1; ++i) {
+      const uint64_t k = sorted[i];
+      PairRec r;
+      r.a = (int)(k >> 36);
+      r.b = (int)((k >> 12) & 0xffffffull);
+      r.s[0] = (int)((k >> 8) & 15u) - 8;
+      r.s[1] = (int)((k >> 4) & 15u) - 8;
+      r.s[2] = (int)(k & 15u) - 8;
+      r.pad = 0;
+      for (int c = 0; c < 3; ++c) r.sh[c] = (double)r.s[c] * L[c];
+      pairs[i] = r;
+      if (i < cap_pairs) {
+        pair_ab[2 * i] = r.a;
+        pair_ab[2 * i + 1] = r.b;
+        for (int c = 0; c < 3; ++c) pair_shift[3 * i + c] = r.s[c];
+      }
+    }
+  }
+}
+
+int grid1d(int64_t n, int threads, int maxg = 2048) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > maxg) g = maxg;
+  return (int)g;
+}
+
+}  // namespace
+
+void launch_ves_scene(const DevScene &S, int *ves_scene, hipStream_t st) {
+  k_ves_scene<<<grid1d(S.n_scenes, 256), 256, 0, st>>>(S, ves_scene);
+}
+void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, hipStream_t st) {
+  int g = S.n_scenes < 1024 ? S.n_scenes : 1024;
+  if (g < 1) return;
+  k_scene_grid<<<g, 256, 0, st>>>(S, ves_box, grid);
+}
+void launch_cp_count(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
+                     int64_t *cp_cnt, hipStream_t st) {
+  k_cp_count<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_box, ves_scene, grid, cp_cnt);
+}
+void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
+                    const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st) {
+  k_cp_emit<<<grid1d(S.n_ves, 64), 64, 0, st>>>(S, ves_box, ves_scene, grid, cp_off, keys, vals, cap);
+}
+void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
+                       const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
+                       int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st) {
+  k_cell_pairs<<<grid1d(n_cp_cap, 256), 256, 0, st>>>(S, ves_box, ves_scene, keys, vals, n_cp, n_cp_cap, hash,
+                                                       hash_cap, uniq, uniq_cap, cnt);
+}
+void launch_self_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, uint64_t *hash,
+                       int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st) {
+  k_self_pairs<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_box, ves_scene, hash, hash_cap, uniq, uniq_cap, cnt);
+}
+void launch_pair_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, Counters *cnt,
+                              hipStream_t st) {
+  k_bucket_count<<<grid1d(uniq_cap, 256), 256, 0, st>>>(uniq, uniq_cap, cnt_a, cnt);
+}
+void launch_pair_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const int64_t *off_a, int32_t *cursor_a,
+                                uint64_t *sorted, Counters *cnt, hipStream_t st) {
+  k_bucket_scatter<<<grid1d(uniq_cap, 256), 256, 0, st>>>(uniq, uniq_cap, off_a, cursor_a, sorted, cnt);
+}
+void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const int64_t *off_a, uint64_t *sorted,
+                                  int n_ves, PairRec *pairs, int32_t *pair_ab, int32_t *pair_shift,
+                                  int64_t cap_pairs, hipStream_t st) {
+  k_bucket_sort_emit<<<grid1d(n_ves, 64), 64, 0, st>>>(S, ves_scene, off_a, sorted, n_ves, pairs, pair_ab,
+                                                       pair_shift, cap_pairs);
+}
+
+}  // namespace stiv

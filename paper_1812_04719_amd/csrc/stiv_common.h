@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP translation units of libstiv.
+// Not part of the public ABI (see include/stiv.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stiv {
+
+// ---------------------------------------------------------------------------
+// Tiling limits.  A patch is a set of neighbouring triangles of one topology
+// together with the vertices and edges it owns (every vertex and edge of the
+// mesh is owned by exactly one patch), so a (patch, patch) work item yields
+// every primitive pair exactly once.
+// ---------------------------------------------------------------------------
+constexpr int kMaxPatchTri = 64;   // triangles per patch
+constexpr int kMaxPatchRef = 128;  // distinct vertices referenced by a patch's triangles
+constexpr int kMaxPatchOwnV = 128; // owned vertices per patch
+constexpr int kMaxPatchOwnE = 192; // owned edges per patch
+constexpr int kMaxPatchesPerVes = 1024;
+constexpr int kMaxShift = 7;       // |sigma_c| bound for periodic images (pair key packing)
+
+// Device copy of the topology tables (all arrays indexed by topology or by
+// global patch-table index).
+struct DevTopo {
+  int n_topo;
+  const int *nv, *nt, *ne;             // [n_topo]
+  const int *tri_off, *edge_off;       // [n_topo+1]
+  const int *tri;                      // [sum nt][3]
+  const int *edge;                     // [sum ne][2]
+  const int *patch_off;                // [n_topo+1] patch-table range of each topology
+  const int *ptri_off;                 // [n_ptab+1]
+  const int *ptri;                     // triangle ids (local to the topology)
+  const uint8_t *ptri_slot;            // [..][3] ref-slot of each corner
+  const int *pvtx_off, *pvtx;          // owned vertices (local ids)
+  const uint8_t *pvtx_slot;            // ref-slot of each owned vertex
+  const int *pedge_off, *pedge;        // owned edges (edge ids)
+  const uint8_t *pedge_slot;           // [..][2]
+  const int *pref_off, *pref;          // referenced vertices (local ids)
+};
+
+struct DevScene {
+  int n_ves, n_vtx, n_scenes;
+  const int *vtx_off, *topo_id, *scene_off;
+  const double *box_len, *x0, *x1;
+};
+
+// Per-scene implicit Morton grid (Alg. 1): origin, cell widths, depth.
+struct SceneGrid {
+  double org[3], w[3], tiny;
+  int depth, periodic[3], pad;
+};
+
+// One candidate vesicle pair, canonical order.
+struct PairRec {
+  int a, b;
+  int s[3];
+  int pad;
+  double sh[3];  // sigma * L, FP64
+};
+
+// Device counters read back once per detect.
+struct Counters {
+  unsigned long long n_cp;         // check points
+  unsigned long long n_raw_pairs;  // pair insertions (with duplicates)
+  unsigned long long n_pairs;
+  unsigned long long n_work;       // patch-pair work items
+  unsigned long long n_cand_vt, n_cand_ee, n_cand;
+  unsigned long long n_ct, n_ct_vt, n_ct_ee;
+  unsigned long long n_vol, n_jrow;
+  unsigned long long within_d, degenerate;
+  unsigned long long hash_overflow, shift_overflow, nonfinite, lds_fallback;
+  unsigned long long pad[4];
+};
+
+// Narrow-phase candidate record.
+struct Cand {
+  int pair, kind, i, j;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (host side), one per kernel.  Where a count lives on the device
+// (`*_dev`), the kernel reads it at run time and clamps it to the given
+// capacity, so the host never waits for an intermediate count.
+// ---------------------------------------------------------------------------
+// scan / sort / fill.  With n_dev != nullptr the length is min(*n_dev, n_host).
+void launch_scan_i64(const int64_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
+                     hipStream_t st);
+void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
+                            hipStream_t st);
+void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
+                           const unsigned long long *n_dev, int64_t n_host, int key_bits, hipStream_t st);
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+
+// K0
+void launch_ves_patch_count(const DevScene &S, const DevTopo &T, int64_t *cnt_out, hipStream_t st);
+void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off,
+                  double *ves_box, double *patch_box, Counters *cnt, hipStream_t st);
+
+// K1
+void launch_ves_scene(const DevScene &S, int *ves_scene, hipStream_t st);
+void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, hipStream_t st);
+void launch_cp_count(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
+                     int64_t *cp_cnt, hipStream_t st);
+void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
+                    const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st);
+void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
+                       const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
+                       int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st);
+void launch_self_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, uint64_t *hash,
+                       int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st);
+void launch_pair_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, Counters *cnt,
+                              hipStream_t st);
+void launch_pair_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const int64_t *off_a,
+                                int32_t *cursor_a, uint64_t *sorted, Counters *cnt, hipStream_t st);
+void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const int64_t *off_a,
+                                  uint64_t *sorted, int n_ves, PairRec *pairs, int32_t *pair_ab,
+                                  int32_t *pair_shift, int64_t cap_pairs, hipStream_t st);
+
+// K2
+void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
+                        const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
+                        uint64_t *work, int64_t work_cap, Counters *cnt, hipStream_t st);
+void launch_prim_cand(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
+                      const double *patch_box, const uint64_t *work, int64_t work_cap, double h, Cand *cand,
+                      int64_t cand_cap, Counters *cnt, hipStream_t st);
+
+// K3 + K4
+void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *cand, int64_t cand_cap,
+                   double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
+                   int64_t ct_cap, Counters *cnt, hipStream_t st);
+
+// K5
+void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st);
+void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
+                       int32_t *cursor, int32_t *perm, hipStream_t st);
+void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
+                              const Counters *cnt, const int64_t *pair_off, const int32_t *perm, const Cand *ct,
+                              const double *ct_s, const double *ct_vol, const double *ct_grad, double dt,
+                              uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_vol,
+                              double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
+                              int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp, hipStream_t st);
+void launch_write_volumes(const Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,
+                          const int64_t *row_off, const int32_t *pair_hasvt, const double *pair_V,
+                          const int32_t *pair_rows, const int32_t *row_vtx_tmp, const double *row_g_tmp,
+                          int32_t *vol_pair, double *vol_V, int64_t cap_vol, int32_t *j_vol, int32_t *j_vtx,
+                          double *j_g, int64_t cap_jrow, hipStream_t st);
+void launch_finalize(Counters *cnt, const int64_t *vol_off, const int64_t *row_off, int64_t pairs_cap,
+                     const int64_t *cp_total, hipStream_t st);
+
+}  // namespace stiv

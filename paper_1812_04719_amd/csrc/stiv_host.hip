@@ -1,0 +1,592 @@
+// Host side of libstiv: context, topology tiling, scratch arena, the detect
+// pipeline and the C ABI declared in include/stiv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/stiv.h"
+#include "stiv_common.h"
+
+using namespace stiv;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Device buffer helper
+// ---------------------------------------------------------------------------
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+hipError_t ensure(Buf &b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return hipSuccess;
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e == hipSuccess) b.bytes = bytes;
+  return e;
+}
+
+template <typename T>
+T *P(Buf &b) {
+  return reinterpret_cast<T *>(b.p);
+}
+
+int64_t pow2_at_least(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+struct stiv_ctx {
+  int device = 0;
+  std::string err;
+  bool have_topo = false;
+  // topology (device)
+  Buf t_nv, t_nt, t_ne, t_tri_off, t_edge_off, t_tri, t_edge, t_patch_off, t_ptri_off, t_ptri, t_ptri_slot,
+      t_pvtx_off, t_pvtx, t_pvtx_slot, t_pedge_off, t_pedge, t_pedge_slot, t_pref_off, t_pref;
+  DevTopo topo{};
+  std::vector<int> h_npatch;  // patches per topology
+  int max_patches = 0;
+  // arena
+  Buf counters, ves_box, ves_scene, grid, cp_cnt, cp_off, cp_keys, cp_vals, cp_tk, cp_tv, hash, uniq, sorted,
+      cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, ct, ct_s, ct_vol,
+      ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
+      row_off, row_vtx, row_g, sort_tk, sort_tv;
+  int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0;
+  Counters *h_cnt = nullptr;  // pinned
+  // last structurally validated scene (pointers + sizes); see check_structure
+  const void *val_ptr[4] = {};
+  int64_t val_size[3] = {-1, -1, -1};
+  hipEvent_t ev[9] = {};  // ev[8] marks the start, ev[0..7] stage boundaries
+  float stage_ms[8] = {};
+};
+
+namespace {
+
+stiv_status fail(stiv_ctx *c, stiv_status s, const std::string &m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(ctx, STIV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+template <typename T>
+hipError_t upload(Buf &b, const std::vector<T> &v) {
+  hipError_t e = ensure(b, std::max<size_t>(v.size() * sizeof(T), 16));
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+stiv_status stiv_create(stiv_ctx **out, int dev) {
+  if (!out) return STIV_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || dev < 0 || dev >= n) return STIV_E_ARG;
+  if (hipSetDevice(dev) != hipSuccess) return STIV_E_HIP;
+  stiv_ctx *ctx = new stiv_ctx();
+  ctx->device = dev;
+  if (hipHostMalloc((void **)&ctx->h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return STIV_E_HIP;
+  }
+  for (auto &e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete ctx;
+      return STIV_E_HIP;
+    }
+  *out = ctx;
+  return STIV_OK;
+}
+
+stiv_status stiv_destroy(stiv_ctx *ctx) {
+  if (!ctx) return STIV_E_ARG;
+  hipSetDevice(ctx->device);
+  Buf *all[] = {&ctx->t_nv, &ctx->t_nt, &ctx->t_ne, &ctx->t_tri_off, &ctx->t_edge_off, &ctx->t_tri, &ctx->t_edge,
+                &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
+                &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
+                &ctx->t_pref_off, &ctx->t_pref, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
+                &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
+                &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->ct,
+                &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
+                &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
+                &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv};
+  for (Buf *b : all)
+    if (b->p) hipFree(b->p);
+  for (auto &e : ctx->ev)
+    if (e) hipEventDestroy(e);
+  if (ctx->h_cnt) hipHostFree(ctx->h_cnt);
+  delete ctx;
+  return STIV_OK;
+}
+
+const char *stiv_last_error(const stiv_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// ---------------------------------------------------------------------------
+// Topology: copy and tile into patches of neighbouring triangles.
+// ---------------------------------------------------------------------------
+stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
+  if (!ctx || !tp || tp->n_topo <= 0 || !tp->nv || !tp->tri || !tp->tri_off || !tp->edge || !tp->edge_off)
+    return fail(ctx, STIV_E_ARG, "set_topology: null or empty topology");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int nt_topo = tp->n_topo;
+  std::vector<int> nv(nt_topo), ntv(nt_topo), nev(nt_topo), tri_off(nt_topo + 1), edge_off(nt_topo + 1);
+  for (int t = 0; t <= nt_topo; ++t) { tri_off[t] = tp->tri_off[t]; edge_off[t] = tp->edge_off[t]; }
+  std::vector<int> tri(3 * (size_t)tri_off[nt_topo]), edge(2 * (size_t)edge_off[nt_topo]);
+  std::memcpy(tri.data(), tp->tri, tri.size() * sizeof(int));
+  std::memcpy(edge.data(), tp->edge, edge.size() * sizeof(int));
+  std::vector<int> patch_off(1, 0), ptri_off(1, 0), ptri, pvtx_off(1, 0), pvtx, pedge_off(1, 0), pedge,
+      pref_off(1, 0), pref;
+  std::vector<uint8_t> ptri_slot, pvtx_slot, pedge_slot;
+  ctx->h_npatch.assign(nt_topo, 0);
+  ctx->max_patches = 0;
+  for (int t = 0; t < nt_topo; ++t) {
+    nv[t] = tp->nv[t];
+    ntv[t] = tri_off[t + 1] - tri_off[t];
+    nev[t] = edge_off[t + 1] - edge_off[t];
+    const int NT = ntv[t], NE = nev[t], NV = nv[t];
+    if (NV <= 0 || NT <= 0 || NE <= 0) return fail(ctx, STIV_E_ARG, "set_topology: empty mesh");
+    const int *T3 = tri.data() + 3 * (size_t)tri_off[t];
+    const int *E2 = edge.data() + 2 * (size_t)edge_off[t];
+    std::map<std::pair<int, int>, int> eid;
+    for (int e = 0; e < NE; ++e) {
+      int a = E2[2 * e], b = E2[2 * e + 1];
+      if (a < 0 || b < 0 || a >= NV || b >= NV || a >= b)
+        return fail(ctx, STIV_E_ARG, "set_topology: edges must be (lo, hi) local ids");
+      eid[{a, b}] = e;
+    }
+    std::vector<int> tri_edges(3 * (size_t)NT);
+    std::vector<std::vector<int>> edge_tris(NE);
+    for (int k = 0; k < NT; ++k)
+      for (int r = 0; r < 3; ++r) {
+        int a = T3[3 * k + r], b = T3[3 * k + (r + 1) % 3];
+        if (a < 0 || b < 0 || a >= NV || b >= NV) return fail(ctx, STIV_E_ARG, "set_topology: bad triangle");
+        auto it = eid.find({std::min(a, b), std::max(a, b)});
+        if (it == eid.end()) return fail(ctx, STIV_E_ARG, "set_topology: triangle edge missing from edge list");
+        tri_edges[3 * k + r] = it->second;
+        edge_tris[it->second].push_back(k);
+      }
+    for (int e = 0; e < NE; ++e)
+      if (edge_tris[e].empty()) return fail(ctx, STIV_E_ARG, "set_topology: edge not on any triangle");
+    std::vector<char> vref(NV, 0);
+    for (int k = 0; k < 3 * NT; ++k) vref[T3[k]] = 1;
+    for (int v = 0; v < NV; ++v)
+      if (!vref[v]) return fail(ctx, STIV_E_ARG, "set_topology: vertex not on any triangle");
+    // greedy breadth-first patches of up to kMaxPatchTri neighbouring triangles
+    std::vector<int> tpatch(NT, -1);
+    std::vector<std::vector<int>> patches;
+    for (int seed = 0; seed < NT; ++seed) {
+      if (tpatch[seed] >= 0) continue;
+      std::vector<int> members, queue{seed};
+      std::vector<int> verts;
+      size_t qh = 0;
+      tpatch[seed] = (int)patches.size();
+      while (qh < queue.size() && (int)members.size() < kMaxPatchTri) {
+        int k = queue[qh++];
+        std::vector<int> nv2 = verts;
+        for (int r = 0; r < 3; ++r)
+          if (std::find(nv2.begin(), nv2.end(), T3[3 * k + r]) == nv2.end()) nv2.push_back(T3[3 * k + r]);
+        if ((int)nv2.size() > kMaxPatchRef) {
+          tpatch[k] = -1;
+          continue;
+        }
+        verts.swap(nv2);
+        members.push_back(k);
+        for (int r = 0; r < 3; ++r)
+          for (int k2 : edge_tris[tri_edges[3 * k + r]])
+            if (tpatch[k2] < 0) {
+              tpatch[k2] = (int)patches.size();
+              queue.push_back(k2);
+            }
+      }
+      for (size_t q = qh; q < queue.size(); ++q) tpatch[queue[q]] = -1;  // release unvisited
+      for (int k : members) tpatch[k] = (int)patches.size();
+      patches.push_back(members);
+    }
+    const int np = (int)patches.size();
+    if (np > kMaxPatchesPerVes) return fail(ctx, STIV_E_ARG, "set_topology: mesh too large for the patch table");
+    ctx->h_npatch[t] = np;
+    ctx->max_patches = std::max(ctx->max_patches, np);
+    std::vector<char> vown(NV, 0), eown(NE, 0);
+    for (int pi = 0; pi < np; ++pi) {
+      const auto &mem = patches[pi];
+      std::vector<int> refs;
+      for (int k : mem)
+        for (int r = 0; r < 3; ++r) refs.push_back(T3[3 * k + r]);
+      std::sort(refs.begin(), refs.end());
+      refs.erase(std::unique(refs.begin(), refs.end()), refs.end());
+      auto slot_of = [&](int v) { return (uint8_t)(std::lower_bound(refs.begin(), refs.end(), v) - refs.begin()); };
+      for (int v : refs) pref.push_back(v);
+      pref_off.push_back((int)pref.size());
+      for (int k : mem) {
+        ptri.push_back(k);
+        for (int r = 0; r < 3; ++r) ptri_slot.push_back(slot_of(T3[3 * k + r]));
+      }
+      ptri_off.push_back((int)ptri.size());
+      int nown_v = 0, nown_e = 0;
+      for (int k : mem)
+        for (int r = 0; r < 3; ++r) {
+          int v = T3[3 * k + r];
+          if (!vown[v]) {
+            vown[v] = 1;
+            pvtx.push_back(v);
+            pvtx_slot.push_back(slot_of(v));
+            ++nown_v;
+          }
+          int e = tri_edges[3 * k + r];
+          if (!eown[e]) {
+            eown[e] = 1;
+            pedge.push_back(e);
+            pedge_slot.push_back(slot_of(E2[2 * e]));
+            pedge_slot.push_back(slot_of(E2[2 * e + 1]));
+            ++nown_e;
+          }
+        }
+      if (nown_v > kMaxPatchOwnV || nown_e > kMaxPatchOwnE || (int)refs.size() > kMaxPatchRef)
+        return fail(ctx, STIV_E_ARG, "set_topology: patch exceeds tile limits");
+      pvtx_off.push_back((int)pvtx.size());
+      pedge_off.push_back((int)pedge.size());
+    }
+    patch_off.push_back(patch_off.back() + np);
+  }
+  HIPCHK(upload(ctx->t_nv, nv));
+  HIPCHK(upload(ctx->t_nt, ntv));
+  HIPCHK(upload(ctx->t_ne, nev));
+  HIPCHK(upload(ctx->t_tri_off, tri_off));
+  HIPCHK(upload(ctx->t_edge_off, edge_off));
+  HIPCHK(upload(ctx->t_tri, tri));
+  HIPCHK(upload(ctx->t_edge, edge));
+  HIPCHK(upload(ctx->t_patch_off, patch_off));
+  HIPCHK(upload(ctx->t_ptri_off, ptri_off));
+  HIPCHK(upload(ctx->t_ptri, ptri));
+  HIPCHK(upload(ctx->t_ptri_slot, ptri_slot));
+  HIPCHK(upload(ctx->t_pvtx_off, pvtx_off));
+  HIPCHK(upload(ctx->t_pvtx, pvtx));
+  HIPCHK(upload(ctx->t_pvtx_slot, pvtx_slot));
+  HIPCHK(upload(ctx->t_pedge_off, pedge_off));
+  HIPCHK(upload(ctx->t_pedge, pedge));
+  HIPCHK(upload(ctx->t_pedge_slot, pedge_slot));
+  HIPCHK(upload(ctx->t_pref_off, pref_off));
+  HIPCHK(upload(ctx->t_pref, pref));
+  DevTopo &D = ctx->topo;
+  D.n_topo = nt_topo;
+  D.nv = P<int>(ctx->t_nv); D.nt = P<int>(ctx->t_nt); D.ne = P<int>(ctx->t_ne);
+  D.tri_off = P<int>(ctx->t_tri_off); D.edge_off = P<int>(ctx->t_edge_off);
+  D.tri = P<int>(ctx->t_tri); D.edge = P<int>(ctx->t_edge);
+  D.patch_off = P<int>(ctx->t_patch_off);
+  D.ptri_off = P<int>(ctx->t_ptri_off); D.ptri = P<int>(ctx->t_ptri); D.ptri_slot = P<uint8_t>(ctx->t_ptri_slot);
+  D.pvtx_off = P<int>(ctx->t_pvtx_off); D.pvtx = P<int>(ctx->t_pvtx); D.pvtx_slot = P<uint8_t>(ctx->t_pvtx_slot);
+  D.pedge_off = P<int>(ctx->t_pedge_off); D.pedge = P<int>(ctx->t_pedge);
+  D.pedge_slot = P<uint8_t>(ctx->t_pedge_slot);
+  D.pref_off = P<int>(ctx->t_pref_off); D.pref = P<int>(ctx->t_pref);
+  ctx->have_topo = true;
+  return STIV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Arena
+// ---------------------------------------------------------------------------
+static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
+  const int64_t N = s->n_ves;
+  const int64_t S = s->n_scenes;
+  if (ctx->cap_cp == 0) ctx->cap_cp = std::max<int64_t>(64 * N, 4096);
+  if (ctx->cap_pairs == 0) ctx->cap_pairs = std::max<int64_t>(16 * N, 4096);
+  if (ctx->cap_work == 0) ctx->cap_work = std::max<int64_t>(64 * ctx->cap_pairs, 1 << 16);
+  if (ctx->cap_cand == 0) ctx->cap_cand = std::max<int64_t>(16 * ctx->cap_work, 1 << 20);
+  if (ctx->cap_ct == 0) ctx->cap_ct = std::max<int64_t>(ctx->cap_cand / 8, 1 << 18);
+  ctx->cap_patch = N * std::max(ctx->max_patches, 1);
+  const int64_t hash_cap = pow2_at_least(4 * ctx->cap_pairs);
+  HIPCHK(ensure(ctx->counters, sizeof(Counters)));
+  HIPCHK(ensure(ctx->ves_box, 6 * 8 * (N + 1)));
+  HIPCHK(ensure(ctx->ves_scene, 4 * (N + 1)));
+  HIPCHK(ensure(ctx->grid, sizeof(SceneGrid) * (S + 1)));
+  HIPCHK(ensure(ctx->cp_cnt, 8 * (N + 1)));
+  HIPCHK(ensure(ctx->cp_off, 8 * (N + 2)));
+  HIPCHK(ensure(ctx->cp_keys, 8 * ctx->cap_cp));
+  HIPCHK(ensure(ctx->cp_vals, 4 * ctx->cap_cp));
+  HIPCHK(ensure(ctx->cp_tk, 8 * ctx->cap_cp));
+  HIPCHK(ensure(ctx->cp_tv, 4 * ctx->cap_cp));
+  HIPCHK(ensure(ctx->hash, 8 * hash_cap));
+  HIPCHK(ensure(ctx->uniq, 8 * ctx->cap_pairs));
+  HIPCHK(ensure(ctx->sorted, 8 * ctx->cap_pairs));
+  HIPCHK(ensure(ctx->cnt_a, 4 * (N + 1)));
+  HIPCHK(ensure(ctx->cursor_a, 4 * (N + 1)));
+  HIPCHK(ensure(ctx->off_a, 8 * (N + 2)));
+  HIPCHK(ensure(ctx->pairs, sizeof(PairRec) * ctx->cap_pairs));
+  HIPCHK(ensure(ctx->ves_patch_cnt, 8 * (N + 1)));
+  HIPCHK(ensure(ctx->ves_patch_off, 8 * (N + 2)));
+  HIPCHK(ensure(ctx->patch_box, 6 * 8 * (ctx->cap_patch + 1)));
+  HIPCHK(ensure(ctx->work, 8 * ctx->cap_work));
+  HIPCHK(ensure(ctx->cand, sizeof(Cand) * ctx->cap_cand));
+  HIPCHK(ensure(ctx->ct, sizeof(Cand) * ctx->cap_ct));
+  HIPCHK(ensure(ctx->ct_s, 8 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->ct_vol, 8 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->ct_grad, 12 * 8 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->pair_cnt, 4 * (ctx->cap_pairs + 1)));
+  HIPCHK(ensure(ctx->pair_cursor, 4 * (ctx->cap_pairs + 1)));
+  HIPCHK(ensure(ctx->pair_off, 8 * (ctx->cap_pairs + 2)));
+  HIPCHK(ensure(ctx->perm, 4 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->gkeys, 8 * 8 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->gidx, 4 * 8 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->pair_V, 8 * (ctx->cap_pairs + 1)));
+  HIPCHK(ensure(ctx->pair_hasvt, 4 * (ctx->cap_pairs + 1)));
+  HIPCHK(ensure(ctx->pair_rows, 4 * (ctx->cap_pairs + 1)));
+  HIPCHK(ensure(ctx->vol_off, 8 * (ctx->cap_pairs + 2)));
+  HIPCHK(ensure(ctx->row_off, 8 * (ctx->cap_pairs + 2)));
+  HIPCHK(ensure(ctx->row_vtx, 4 * 4 * ctx->cap_ct));
+  HIPCHK(ensure(ctx->row_g, 3 * 8 * 4 * ctx->cap_ct));
+  return STIV_OK;
+}
+
+static stiv_status check_args(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p) {
+  if (!s || !p) return fail(ctx, STIV_E_ARG, "null scene or params");
+  if (!ctx->have_topo) return fail(ctx, STIV_E_STATE, "stiv_set_topology has not been called");
+  if (!(p->d >= 0.0) || !std::isfinite(p->d)) return fail(ctx, STIV_E_ARG, "d must be finite and >= 0");
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(ctx, STIV_E_ARG, "eps must be finite and > 0");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(ctx, STIV_E_ARG, "dt must be finite and > 0");
+  if (s->n_ves < 0 || s->n_vtx < 0 || s->n_scenes < 1) return fail(ctx, STIV_E_ARG, "bad scene sizes");
+  if (s->n_ves >= (1 << 24)) return fail(ctx, STIV_E_ARG, "at most 2^24 - 1 vesicles");
+  if (s->n_ves > 0 && (!s->vtx_off || !s->topo_id || !s->scene_off || !s->box_len || !s->x0 || !s->x1))
+    return fail(ctx, STIV_E_ARG, "null scene array");
+  return STIV_OK;
+}
+
+// Validate the small structural arrays (device) on the host before any
+// kernel indexes with them.  The result is cached per (pointers, sizes);
+// stiv_reserve clears the cache, so callers that rewrite these arrays in
+// place call stiv_reserve first.
+static stiv_status check_structure(stiv_ctx *ctx, const stiv_scene *s) {
+  const void *ptrs[4] = {s->vtx_off, s->topo_id, s->scene_off, s->box_len};
+  const int64_t sizes[3] = {s->n_ves, s->n_vtx, s->n_scenes};
+  if (std::memcmp(ptrs, ctx->val_ptr, sizeof ptrs) == 0 && std::memcmp(sizes, ctx->val_size, sizeof sizes) == 0)
+    return STIV_OK;
+  std::vector<int32_t> vo(s->n_ves + 1), tid(s->n_ves), so(s->n_scenes + 1);
+  std::vector<double> bl(3 * (size_t)s->n_scenes);
+  HIPCHK(hipMemcpy(vo.data(), s->vtx_off, vo.size() * 4, hipMemcpyDeviceToHost));
+  if (s->n_ves) HIPCHK(hipMemcpy(tid.data(), s->topo_id, tid.size() * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(so.data(), s->scene_off, so.size() * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bl.data(), s->box_len, bl.size() * 8, hipMemcpyDeviceToHost));
+  if (vo[0] != 0 || vo[s->n_ves] != s->n_vtx) return fail(ctx, STIV_E_ARG, "vtx_off must run from 0 to n_vtx");
+  std::vector<int> nv_topo(ctx->topo.n_topo);
+  {
+    std::vector<int> tmp(ctx->topo.n_topo);
+    HIPCHK(hipMemcpy(tmp.data(), ctx->topo.nv, tmp.size() * 4, hipMemcpyDeviceToHost));
+    nv_topo = tmp;
+  }
+  for (int v = 0; v < s->n_ves; ++v) {
+    if (tid[v] < 0 || tid[v] >= ctx->topo.n_topo) return fail(ctx, STIV_E_ARG, "topo_id out of range");
+    if (vo[v + 1] - vo[v] != nv_topo[tid[v]])
+      return fail(ctx, STIV_E_ARG, "vtx_off does not match the vertex count of the vesicle's topology");
+  }
+  if (so[0] != 0 || so[s->n_scenes] != s->n_ves) return fail(ctx, STIV_E_ARG, "scene_off must run from 0 to n_ves");
+  for (int k = 0; k < s->n_scenes; ++k)
+    if (so[k + 1] < so[k]) return fail(ctx, STIV_E_ARG, "scene_off must be non-decreasing");
+  for (double L : bl)
+    if (!(L >= 0.0) || !std::isfinite(L)) return fail(ctx, STIV_E_ARG, "box_len must be finite and >= 0");
+  std::memcpy(ctx->val_ptr, ptrs, sizeof ptrs);
+  std::memcpy(ctx->val_size, sizes, sizeof sizes);
+  return STIV_OK;
+}
+
+stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p) {
+  if (!ctx) return STIV_E_ARG;
+  stiv_status st = check_args(ctx, s, p);
+  if (st != STIV_OK) return st;
+  HIPCHK(hipSetDevice(ctx->device));
+  for (auto &q : ctx->val_ptr) q = nullptr;
+  st = check_structure(ctx, s);
+  if (st != STIV_OK) return st;
+  return arena(ctx, s);
+}
+
+static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p, stiv_result *out, hipStream_t st) {
+  const double h = 0.5 * p->d;
+  const int64_t N = S.n_ves;
+  Counters *cnt = P<Counters>(ctx->counters);
+  const DevTopo &T = ctx->topo;
+  const int64_t hash_cap = pow2_at_least(4 * ctx->cap_pairs);
+  hipEventRecord(ctx->ev[8], st);
+  launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 0ull, sizeof(Counters) / 8, st);
+  launch_ves_patch_count(S, T, P<int64_t>(ctx->ves_patch_cnt), st);
+  launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, st);
+  // ---- K0 boxes
+  hipEventRecord(ctx->ev[0], st);
+  launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box), cnt, st);
+  hipEventRecord(ctx->ev[1], st);
+  // ---- K1 vesicle broad phase
+  launch_ves_scene(S, P<int>(ctx->ves_scene), st);
+  launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), st);
+  launch_cp_count(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
+                  P<int64_t>(ctx->cp_cnt), st);
+  launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, st);
+  launch_cp_emit(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
+                 P<int64_t>(ctx->cp_off), P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), ctx->cap_cp, st);
+  const unsigned long long *n_cp = reinterpret_cast<const unsigned long long *>(P<int64_t>(ctx->cp_off) + N);
+  int scene_bits = 0;
+  while ((1ll << scene_bits) < S.n_scenes) ++scene_bits;
+  launch_radix_sort_u64(P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), P<uint64_t>(ctx->cp_tk),
+                        P<uint32_t>(ctx->cp_tv), n_cp, ctx->cap_cp, 30 + scene_bits, st);
+  launch_fill_u64(P<uint64_t>(ctx->hash), ~0ull, hash_cap, st);
+  launch_cell_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->cp_keys),
+                    P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap,
+                    P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
+  launch_self_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->hash), hash_cap,
+                    P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
+  launch_fill_i32(P<int32_t>(ctx->cnt_a), 0, N + 1, st);
+  launch_fill_i32(P<int32_t>(ctx->cursor_a), 0, N + 1, st);
+  launch_pair_bucket_count(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a), cnt, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->cnt_a), P<int64_t>(ctx->off_a), nullptr, N, st);
+  launch_pair_bucket_scatter(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int64_t>(ctx->off_a),
+                             P<int32_t>(ctx->cursor_a), P<uint64_t>(ctx->sorted), cnt, st);
+  launch_pair_bucket_sort_emit(S, P<int>(ctx->ves_scene), P<int64_t>(ctx->off_a), P<uint64_t>(ctx->sorted), (int)N,
+                               P<PairRec>(ctx->pairs), out->pair_ab, out->pair_shift, out->cap_pairs, st);
+  hipEventRecord(ctx->ev[2], st);
+  // ---- K2 primitive broad phase
+  launch_patch_pairs(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, P<double>(ctx->ves_box),
+                     P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<uint64_t>(ctx->work),
+                     ctx->cap_work, cnt, st);
+  hipEventRecord(ctx->ev[3], st);
+  launch_prim_cand(S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box),
+                   P<uint64_t>(ctx->work), ctx->cap_work, h, P<Cand>(ctx->cand), ctx->cap_cand, cnt, st);
+  hipEventRecord(ctx->ev[4], st);
+  // ---- K3 + K4 narrow phase, volumes and gradients
+  launch_narrow(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps, p->dt,
+                P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
+                cnt, st);
+  hipEventRecord(ctx->ev[5], st);
+  // ---- K5 aggregation
+  launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
+  launch_fill_i32(P<int32_t>(ctx->pair_cursor), 0, ctx->cap_pairs + 1, st);
+  launch_ct_pair_count(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int32_t>(ctx->pair_cnt), st);
+  const unsigned long long *n_pairs_dev = &cnt->n_pairs;
+  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_cnt), P<int64_t>(ctx->pair_off), n_pairs_dev, ctx->cap_pairs, st);
+  launch_ct_scatter(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int64_t>(ctx->pair_off), P<int32_t>(ctx->pair_cursor),
+                    P<int32_t>(ctx->perm), st);
+  launch_ct_sort_aggregate(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, cnt, P<int64_t>(ctx->pair_off),
+                           P<int32_t>(ctx->perm), P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol),
+                           P<double>(ctx->ct_grad), p->dt, P<uint64_t>(ctx->gkeys), P<int32_t>(ctx->gidx),
+                           out->ct_key, out->ct_tau, out->ct_vol, out->ct_grad, out->cap_ct, P<double>(ctx->pair_V),
+                           P<int32_t>(ctx->pair_hasvt), P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx),
+                           P<double>(ctx->row_g), st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_hasvt), P<int64_t>(ctx->vol_off), n_pairs_dev, ctx->cap_pairs, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_rows), P<int64_t>(ctx->row_off), n_pairs_dev, ctx->cap_pairs, st);
+  launch_write_volumes(cnt, ctx->cap_pairs, P<int64_t>(ctx->pair_off), P<int64_t>(ctx->vol_off),
+                       P<int64_t>(ctx->row_off), P<int32_t>(ctx->pair_hasvt), P<double>(ctx->pair_V),
+                       P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx), P<double>(ctx->row_g), out->vol_pair,
+                       out->vol_V, out->cap_vol, out->j_vol, out->j_vtx, out->j_g, out->cap_jrow, st);
+  launch_finalize(cnt, P<int64_t>(ctx->vol_off), P<int64_t>(ctx->row_off), ctx->cap_pairs, P<int64_t>(ctx->cp_off) + N,
+                  st);
+  hipEventRecord(ctx->ev[6], st);
+}
+
+stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out, void *stream) {
+  if (!ctx) return STIV_E_ARG;
+  if (!out) return fail(ctx, STIV_E_ARG, "null result");
+  stiv_status st0 = check_args(ctx, s, p);
+  if (st0 != STIV_OK) return st0;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (s->n_ves == 0) {
+    out->n_pairs = out->n_cand_vt = out->n_cand_ee = out->n_ct_vt = out->n_ct_ee = out->n_vol = out->n_jrow = 0;
+    out->n_initially_within_d = out->n_degenerate_skipped = 0;
+    return STIV_OK;
+  }
+  stiv_status sv = check_structure(ctx, s);
+  if (sv != STIV_OK) return sv;
+  DevScene S;
+  S.n_ves = s->n_ves; S.n_vtx = s->n_vtx; S.n_scenes = s->n_scenes;
+  S.vtx_off = s->vtx_off; S.topo_id = s->topo_id; S.scene_off = s->scene_off;
+  S.box_len = s->box_len; S.x0 = s->x0; S.x1 = s->x1;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    stiv_status sa = arena(ctx, s);
+    if (sa != STIV_OK) return sa;
+    run_pipeline(ctx, S, p, out, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const Counters &c = *ctx->h_cnt;
+    if (c.nonfinite) return fail(ctx, STIV_E_NUMERIC, "a position is NaN or infinite");
+    if (c.shift_overflow)
+      return fail(ctx, STIV_E_ARG, "periodic box too small: image shifts beyond +-7 box lengths");
+    bool grow = false;
+    const int64_t need_cp = (int64_t)c.n_cp;
+    if (need_cp > ctx->cap_cp) { ctx->cap_cp = need_cp + need_cp / 4; grow = true; }
+    if ((int64_t)c.n_pairs > ctx->cap_pairs || c.hash_overflow) {
+      ctx->cap_pairs = (int64_t)c.n_pairs * 2 + 1024;
+      grow = true;
+    }
+    if ((int64_t)c.n_work > ctx->cap_work) { ctx->cap_work = (int64_t)c.n_work + c.n_work / 4 + 1024; grow = true; }
+    if ((int64_t)c.n_cand > ctx->cap_cand) { ctx->cap_cand = (int64_t)c.n_cand + c.n_cand / 4 + 1024; grow = true; }
+    if ((int64_t)c.n_ct > ctx->cap_ct) { ctx->cap_ct = (int64_t)c.n_ct + c.n_ct / 4 + 1024; grow = true; }
+    if (grow) continue;
+    out->n_pairs = (int64_t)c.n_pairs;
+    out->n_cand_vt = (int64_t)c.n_cand_vt;
+    out->n_cand_ee = (int64_t)c.n_cand_ee;
+    out->n_ct_vt = (int64_t)c.n_ct_vt;
+    out->n_ct_ee = (int64_t)c.n_ct_ee;
+    out->n_vol = (int64_t)c.n_vol;
+    out->n_jrow = (int64_t)c.n_jrow;
+    out->n_initially_within_d = (int64_t)c.within_d;
+    out->n_degenerate_skipped = (int64_t)c.degenerate;
+    float ms[8] = {};
+    for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&ms[k], ctx->ev[k], ctx->ev[k + 1]);
+    (void)hipEventElapsedTime(&ms[6], ctx->ev[8], ctx->ev[6]);
+    std::memcpy(ctx->stage_ms, ms, sizeof ms);
+    const int64_t n_cand = out->n_cand_vt + out->n_cand_ee;
+    if ((p->flags & STIV_EMIT_CANDIDATES) && out->cand) {
+      const int64_t n = std::min(n_cand, out->cap_cand);
+      if (n > 0) {
+        HIPCHK(hipMemcpyAsync(out->cand, ctx->cand.p, (size_t)n * sizeof(Cand), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+      }
+    }
+    const bool over = out->n_pairs > out->cap_pairs || out->n_ct_vt + out->n_ct_ee > out->cap_ct ||
+                      out->n_vol > out->cap_vol || out->n_jrow > out->cap_jrow ||
+                      ((p->flags & STIV_EMIT_CANDIDATES) && n_cand > out->cap_cand);
+    if (over) return fail(ctx, STIV_E_CAPACITY, "an output array is too small; n_* hold the required sizes");
+    return STIV_OK;
+  }
+  return fail(ctx, STIV_E_CAPACITY, "internal buffers did not converge after growing");
+}
+
+stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n) {
+  if (!ctx || !ms) return STIV_E_ARG;
+  for (int k = 0; k < n && k < 7; ++k) ms[k] = ctx->stage_ms[k];
+  return STIV_OK;
+}
+
+stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, void *stream) {
+  if (!ctx || n < 0 || (n > 0 && (!keys || !vals))) return fail(ctx, STIV_E_ARG, "bad sort arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(ensure(ctx->sort_tk, 8 * (size_t)(n + 1)));
+  HIPCHK(ensure(ctx->sort_tv, 4 * (size_t)(n + 1)));
+  launch_radix_sort_u64(keys, vals, P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), nullptr, n, 64, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return STIV_OK;
+}
+
+}  // extern "C"
