@@ -82,6 +82,8 @@ def main():
              "aggregation", "device_total"]
     stage_ms = {n: round(float(v), 4) for n, v in zip(names, stages)}
     log("stages (ms): %s" % stage_ms)
+    work = ctx.stats()
+    log("work: %s" % work)
 
     # roofline of the dominant kernel
     n_patches = int(sum(ctx_patch for ctx_patch in [0]))  # patch boxes: counted below
@@ -122,6 +124,7 @@ def main():
                    "contacts_ee": int(res["n_ct_ee"]), "contact_volumes": int(res["n_vol"]),
                    "jacobian_rows": int(res["n_jrow"])},
         "stages_ms": stage_ms,
+        "work": work,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

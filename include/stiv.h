@@ -154,6 +154,13 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
  * 5 aggregation, 6 whole call on the device.  Fills min(n, 7) values. */
 stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n);
 
+/* Work counts of the last detect (diagnostics, tuning): 0 check points,
+ * 1 candidate vesicle pairs, 2 patch-pair work items, 3 FP32 pre-candidates
+ * (a superset of the candidates), 4 vertex-triangle candidates, 5 edge-edge
+ * candidates, 6 candidates whose polynomial needed a root search, 7 contacts.
+ * Fills min(n, 8) values. */
+stiv_status stiv_get_stats(stiv_ctx *ctx, int64_t *vals, int n);
+
 /* Device pointers to the library's internal Morton sort (tests only need
  * it for the worked example of Alg. 1 / Table 3): stable sort of n 64-bit
  * keys with 32-bit values, ascending, equal keys keep input order. */

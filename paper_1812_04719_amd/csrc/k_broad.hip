@@ -80,11 +80,13 @@ __device__ inline bool box_overlap_shifted(const double *A, const double *B, con
 __device__ void test_pair_all_shifts(int a, int b, const double *A, const double *B, const double *L,
                                      uint64_t *hash, int64_t cap, uint64_t *uniq, int64_t uniq_cap,
                                      Counters *cnt) {
+  // candidate shifts per axis: (A.lo - B.hi)/L <= sigma <= (A.hi - B.lo)/L, widened
+  // by 1e-6 against rounding; each one is then tested exactly
   int lo[3], hi[3];
   for (int c = 0; c < 3; ++c) {
     if (L[c] > 0.0) {
-      lo[c] = (int)floor((A[c] - B[3 + c]) / L[c]) - 1;
-      hi[c] = (int)ceil((A[3 + c] - B[c]) / L[c]) + 1;
+      lo[c] = (int)ceil((A[c] - B[3 + c]) / L[c] - 1e-6);
+      hi[c] = (int)floor((A[3 + c] - B[c]) / L[c] + 1e-6);
       if (lo[c] < -kMaxShift || hi[c] > kMaxShift) {
         atomicAdd(&cnt->shift_overflow, 1ull);
         lo[c] = lo[c] < -kMaxShift ? -kMaxShift : lo[c];
@@ -109,9 +111,16 @@ __device__ void test_pair_all_shifts(int a, int b, const double *A, const double
       }
 }
 
+// Scene of each vesicle: binary search of scene_off (one thread per vesicle).
 __global__ void k_ves_scene(DevScene S, int *ves_scene) {
-  for (int sc = blockIdx.x * blockDim.x + threadIdx.x; sc < S.n_scenes; sc += gridDim.x * blockDim.x)
-    for (int v = S.scene_off[sc]; v < S.scene_off[sc + 1]; ++v) ves_scene[v] = sc;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
+    int lo = 0, hi = S.n_scenes;  // invariant: scene_off[lo] <= v < scene_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (S.scene_off[mid] <= v) lo = mid; else hi = mid;
+    }
+    ves_scene[v] = lo;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *box, SceneGrid *grid) {
@@ -249,9 +258,11 @@ __global__ void k_cell_pairs(DevScene S, const double *box, const int *ves_scene
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t k = keys[i];
     const int vi = (int)vals[i];
+    // a box's check points are consecutive in the stable order: test each box once per cell
+    if (i > 0 && keys[i - 1] == k && (int)vals[i - 1] == vi) continue;
     for (int64_t j = i + 1; j < n && keys[j] == k; ++j) {
       const int vj = (int)vals[j];
-      if (vi == vj) continue;
+      if (vi == vj || (int)vals[j - 1] == vj) continue;
       const int a = vi < vj ? vi : vj, b = vi < vj ? vj : vi;
       const double *L = S.box_len + 3 * ves_scene[a];
       test_pair_all_shifts(a, b, box + 6 * (int64_t)a, box + 6 * (int64_t)b, L, hash, cap, uniq, uniq_cap, cnt);
@@ -333,7 +344,7 @@ int grid1d(int64_t n, int threads, int maxg = 2048) {
 }  // namespace
 
 void launch_ves_scene(const DevScene &S, int *ves_scene, hipStream_t st) {
-  k_ves_scene<<<grid1d(S.n_scenes, 256), 256, 0, st>>>(S, ves_scene);
+  k_ves_scene<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_scene);
 }
 void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, hipStream_t st) {
   int g = S.n_scenes < 1024 ? S.n_scenes : 1024;

@@ -130,16 +130,35 @@ __host__ __device__ void bernstein_on(const double f[7], int n, double u, double
     for (int j = n; j >= r; --j) b[j] += b[j - 1];
 }
 
-// Bisection on [lo, hi] with f(lo) = flo != 0 and a sign change; width 2^-50.
+// Root of f in [lo, hi] where f(lo) = flo != 0 and f changes sign: Newton
+// steps kept inside the shrinking bracket, bisection when a step would leave
+// it or converge too slowly; stops at a step below 2^-52 or a bracket of
+// width 2^-50.
 __host__ __device__ double refine(const double f[7], int n, double lo, double hi, double flo) {
   const double tol = 8.881784197001252e-16;
-  for (int it = 0; it < 120 && hi - lo > tol; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    const double fm = horner(f, n, mid);
-    if (fm == 0.0) return mid;
-    if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else hi = mid;
+  double x = 0.5 * (lo + hi), dx = hi - lo, dxold = dx;
+  for (int it = 0; it < 100; ++it) {
+    double fx = f[n], dfx = 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+      dfx = dfx * x + fx;
+      fx = fx * x + f[k];
+    }
+    if (fx == 0.0) return x;
+    if ((fx < 0.0) == (flo < 0.0)) { lo = x; flo = fx; } else { hi = x; }
+    if (hi - lo <= tol) break;
+    const double xn = (dfx != 0.0) ? x - fx / dfx : x;
+    if (!(xn > lo && xn < hi) || fabs(2.0 * fx) > fabs(dxold * dfx)) {
+      dxold = dx;
+      dx = 0.5 * (hi - lo);
+      x = lo + dx;
+    } else {
+      dxold = dx;
+      dx = xn - x;
+      x = xn;
+      if (fabs(dx) <= 2.220446049250313e-16 * fmax(fabs(x), 1e-300)) break;
+    }
   }
-  return 0.5 * (lo + hi);
+  return x;
 }
 
 // Earliest valid root.  Returns 1 with *s on contact, 0 otherwise.
@@ -278,15 +297,138 @@ __device__ inline d3 load_pos(const double *x, int64_t nv, int64_t gid) {
   return mk(x[gid], x[nv + gid], x[2 * nv + gid]);
 }
 
-__global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const PairRec *pairs, const Cand *cand,
-                                                int64_t cand_cap, double d, double eps, double dt, Cand *ct,
-                                                double *ct_s, double *ct_vol, double *ct_grad, int64_t ct_cap,
-                                                Counters *cnt) {
-  int64_t nc = (int64_t)cnt->n_cand;
-  nc = nc < cand_cap ? nc : cand_cap;
+// Global vertex ids and per-vertex image shifts of a candidate; order
+// (p, a, b, c) for vertex-triangle, (a, b, c, e) for edge-edge.  side[k] is 1
+// for vertices of the pair's second vesicle (shifted by sigma L).
+__device__ inline void cand_vertices(const DevScene &S, const DevTopo &T, const PairRec &pr, const Cand &c,
+                                     int64_t gid[4], int side[4]) {
+  if (c.kind == 2) {
+    const int ta = S.topo_id[pr.a], tb = S.topo_id[pr.b];
+    const int *ea = T.edge + 2 * ((int64_t)T.edge_off[ta] + c.i);
+    const int *eb = T.edge + 2 * ((int64_t)T.edge_off[tb] + c.j);
+    gid[0] = S.vtx_off[pr.a] + ea[0]; gid[1] = S.vtx_off[pr.a] + ea[1];
+    gid[2] = S.vtx_off[pr.b] + eb[0]; gid[3] = S.vtx_off[pr.b] + eb[1];
+    side[0] = side[1] = 0; side[2] = side[3] = 1;
+  } else {
+    const int vv = c.kind ? pr.b : pr.a, vt = c.kind ? pr.a : pr.b;
+    const int *tri = T.tri + 3 * ((int64_t)T.tri_off[S.topo_id[vt]] + c.j);
+    gid[0] = S.vtx_off[vv] + c.i;
+    for (int q = 0; q < 3; ++q) gid[1 + q] = S.vtx_off[vt] + tri[q];
+    side[0] = c.kind ? 1 : 0;
+    side[1] = side[2] = side[3] = c.kind ? 0 : 1;
+  }
+}
+
+// Load the candidate's vertices; Q gets X0 + shift and D = X1 - X0, raw the
+// unshifted positions.  Returns whether the FP64 primitive boxes overlap:
+// box = ((min over vertices of min(X0, X1)) - h) + shift, likewise for max.
+__device__ inline bool load_quad(const DevScene &S, const PairRec &pr, const int64_t gid[4], const int side[4],
+                                 bool ee, double h, Quad &Q) {
   const int64_t NV = S.n_vtx;
+  double lo[2][3], hi[2][3];
+  for (int g = 0; g < 2; ++g)
+    for (int c = 0; c < 3; ++c) { lo[g][c] = INFINITY; hi[g][c] = -INFINITY; }
+  Q.ee = ee;
+  for (int k = 0; k < 4; ++k) {
+    const d3 a = load_pos(S.x0, NV, gid[k]), b = load_pos(S.x1, NV, gid[k]);
+    const double sx = side[k] ? pr.sh[0] : 0.0, sy = side[k] ? pr.sh[1] : 0.0, sz = side[k] ? pr.sh[2] : 0.0;
+    Q.X0[k] = mk(a.x + sx, a.y + sy, a.z + sz);
+    Q.D[k] = b - a;
+    // group 0: first primitive (vertex, or edge a-b); group 1: triangle or edge c-e
+    const int grp = ee ? (k >= 2) : (k >= 1);
+    lo[grp][0] = fmin(lo[grp][0], fmin(a.x, b.x)); hi[grp][0] = fmax(hi[grp][0], fmax(a.x, b.x));
+    lo[grp][1] = fmin(lo[grp][1], fmin(a.y, b.y)); hi[grp][1] = fmax(hi[grp][1], fmax(a.y, b.y));
+    lo[grp][2] = fmin(lo[grp][2], fmin(a.z, b.z)); hi[grp][2] = fmax(hi[grp][2], fmax(a.z, b.z));
+  }
+  // shift of each group (all vertices of a group are on the same side)
+  const int sg0 = side[0], sg1 = side[3];
+  bool ov = true;
+  for (int c = 0; c < 3; ++c) {
+    const double s0 = sg0 ? pr.sh[c] : 0.0, s1 = sg1 ? pr.sh[c] : 0.0;
+    const double l0 = (lo[0][c] - h) + s0, u0 = (hi[0][c] + h) + s0;
+    const double l1 = (lo[1][c] - h) + s1, u1 = (hi[1][c] + h) + s1;
+    ov = ov && (l0 <= u1) && (l1 <= u0);
+  }
+  return ov;
+}
+
+// Screen: exact box test (counts the candidate), polynomial coefficients and
+// one Bernstein test on [0,1].  A polynomial with all Bernstein coefficients
+// positive (d > 0), or of one strict sign (d = 0), has no root and no
+// within-d start; everything else goes to the root search queue.
+__global__ __launch_bounds__(256) void k_narrow_screen(DevScene S, DevTopo T, const PairRec *pairs,
+                                                       const Cand *pre, int64_t pre_cap, double d, int32_t *hard,
+                                                       int64_t hard_cap, Cand *list, int64_t list_cap,
+                                                       Counters *cnt) {
+  int64_t n = (int64_t)cnt->n_pre;
+  n = n < pre_cap ? n : pre_cap;
+  const double h = 0.5 * d;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long nvt = 0, nee = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    bool is_cand = false, need = false;
+    Cand c;
+    c.pair = c.kind = c.i = c.j = 0;
+    if (i < n) {
+      c = pre[i];
+      const PairRec pr = pairs[c.pair];
+      int64_t gid[4];
+      int side[4];
+      cand_vertices(S, T, pr, c, gid, side);
+      Quad Q;
+      is_cand = load_quad(S, pr, gid, side, c.kind == 2, h, Q);
+      if (is_cand) {
+        if (c.kind == 2) ++nee; else ++nvt;
+        double f[7], b[7];
+        const int deg = poly_coeffs(Q, d, f);
+        bernstein_on(f, deg, 0.0, 1.0, b);
+        bool pos = true, neg = true;
+        for (int k = 0; k <= deg; ++k) { pos &= b[k] > 0.0; neg &= b[k] < 0.0; }
+        need = !(pos || (d == 0.0 && neg));
+      }
+    }
+    const unsigned long long mh = __ballot(need);
+    const int leader_h = mh ? __ffsll((long long)mh) - 1 : 0;
+    unsigned long long bh = 0;
+    if ((int)(threadIdx.x & 63) == leader_h && mh) bh = atomicAdd(&cnt->n_hard, (unsigned long long)__popcll(mh));
+    bh = __shfl(bh, leader_h, 64);
+    if (need) {
+      const unsigned long long slot = bh + __popcll(mh & lanemask_lt());
+      if ((int64_t)slot < hard_cap) hard[slot] = (int32_t)i;
+    }
+    if (list) {
+      const unsigned long long mc = __ballot(is_cand);
+      const int leader_c = mc ? __ffsll((long long)mc) - 1 : 0;
+      unsigned long long bc = 0;
+      if ((int)(threadIdx.x & 63) == leader_c && mc)
+        bc = atomicAdd(&cnt->n_cand_list, (unsigned long long)__popcll(mc));
+      bc = __shfl(bc, leader_c, 64);
+      if (is_cand) {
+        const unsigned long long slot = bc + __popcll(mc & lanemask_lt());
+        if ((int64_t)slot < list_cap) list[slot] = c;
+      }
+    }
+  }
+  // one atomic per wavefront for the candidate counts
+  for (int off = 32; off > 0; off >>= 1) {
+    nvt += __shfl_xor(nvt, off, 64);
+    nee += __shfl_xor(nee, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (nvt) atomicAdd(&cnt->n_cand_vt, nvt);
+    if (nee) atomicAdd(&cnt->n_cand_ee, nee);
+  }
+}
+
+// Root search on the queued candidates, then volume and gradient on contact.
+__global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const PairRec *pairs, const Cand *pre,
+                                                const int32_t *hard, int64_t hard_cap, double d, double eps,
+                                                double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
+                                                int64_t ct_cap, Counters *cnt) {
+  int64_t nc = (int64_t)cnt->n_hard;
+  nc = nc < hard_cap ? nc : hard_cap;
   int within = 0, deg = 0;
-  // uniform trip count per wavefront so the ballot below sees every lane
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {
     const int64_t i = base + threadIdx.x;
@@ -296,47 +438,21 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
     c.pair = c.kind = c.i = c.j = 0;
     for (int k = 0; k < 12; ++k) g[k] = 0.0;
     if (i < nc) {
-      c = cand[i];
+      c = pre[hard[i]];
       const PairRec pr = pairs[c.pair];
       int64_t gid[4];
-      double shk[4][3];
+      int side[4];
+      cand_vertices(S, T, pr, c, gid, side);
       Quad Q;
-      Q.ee = (c.kind == 2);
-      if (c.kind == 2) {
-        const int ta = S.topo_id[pr.a], tb = S.topo_id[pr.b];
-        const int *ea = T.edge + 2 * ((int64_t)T.edge_off[ta] + c.i);
-        const int *eb = T.edge + 2 * ((int64_t)T.edge_off[tb] + c.j);
-        gid[0] = S.vtx_off[pr.a] + ea[0]; gid[1] = S.vtx_off[pr.a] + ea[1];
-        gid[2] = S.vtx_off[pr.b] + eb[0]; gid[3] = S.vtx_off[pr.b] + eb[1];
-        for (int q = 0; q < 3; ++q) {
-          shk[0][q] = shk[1][q] = 0.0;
-          shk[2][q] = shk[3][q] = pr.sh[q];
-        }
-      } else {
-        const int vv = c.kind ? pr.b : pr.a, vt = c.kind ? pr.a : pr.b;
-        const int tt = S.topo_id[vt];
-        const int *tri = T.tri + 3 * ((int64_t)T.tri_off[tt] + c.j);
-        gid[0] = S.vtx_off[vv] + c.i;
-        for (int q = 0; q < 3; ++q) gid[1 + q] = S.vtx_off[vt] + tri[q];
-        for (int q = 0; q < 3; ++q) {
-          const double sv = c.kind ? pr.sh[q] : 0.0, st = c.kind ? 0.0 : pr.sh[q];
-          shk[0][q] = sv;
-          shk[1][q] = shk[2][q] = shk[3][q] = st;
-        }
-      }
-      for (int k = 0; k < 4; ++k) {
-        const d3 a = load_pos(S.x0, NV, gid[k]), b = load_pos(S.x1, NV, gid[k]);
-        Q.X0[k] = mk(a.x + shk[k][0], a.y + shk[k][1], a.z + shk[k][2]);
-        Q.D[k] = b - a;
-      }
+      load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Q);
       hit = earliest(Q, d, &s, &within, &deg);
       if (hit && !Q.ee) volume_grad(Q, s, d, eps, dt, s == 0.0, &V, g);
     }
     const unsigned long long m = __ballot(hit != 0);
     const int nh = __popcll(m);
-    unsigned long long slot0 = 0;
     const int leader = m ? __ffsll((long long)m) - 1 : 0;
     const int nee_w = __popcll(__ballot(hit != 0 && c.kind == 2));
+    unsigned long long slot0 = 0;
     if ((int)(threadIdx.x & 63) == leader && nh) {
       slot0 = atomicAdd(&cnt->n_ct, (unsigned long long)nh);
       if (nee_w) atomicAdd(&cnt->n_ct_ee, (unsigned long long)nee_w);
@@ -359,13 +475,25 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
 
 }  // namespace
 
-void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *cand, int64_t cand_cap,
-                   double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, Counters *cnt, hipStream_t st) {
-  int64_t g = (cand_cap + 255) / 256;
-  if (g > 4096) g = 4096;
+static int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  k_narrow<<<(int)g, 256, 0, st>>>(S, T, pairs, cand, cand_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap, cnt);
+  return (int)g;
+}
+
+void launch_narrow_screen(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *pre,
+                          int64_t pre_cap, double d, int32_t *hard, int64_t hard_cap, Cand *list, int64_t list_cap,
+                          Counters *cnt, hipStream_t st) {
+  k_narrow_screen<<<grid_for(pre_cap), 256, 0, st>>>(S, T, pairs, pre, pre_cap, d, hard, hard_cap, list, list_cap,
+                                                     cnt);
+}
+
+void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *pre, const int32_t *hard,
+                   int64_t hard_cap, double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol,
+                   double *ct_grad, int64_t ct_cap, Counters *cnt, hipStream_t st) {
+  k_narrow<<<grid_for(hard_cap), 256, 0, st>>>(S, T, pairs, pre, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
+                                               ct_grad, ct_cap, cnt);
 }
 
 }  // namespace stiv

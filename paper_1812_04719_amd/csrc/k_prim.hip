@@ -12,10 +12,11 @@
 //                  against the other vesicle's box, then test the surviving
 //                  patch pairs; emit (pair, patch a, patch b) work items.
 //   k_prim_cand    one wavefront per work item: stage the two patches'
-//                  vertex boxes in LDS, cull each primitive against the other
-//                  patch's box, test the survivors pairwise and compact the
-//                  hits with a wavefront ballot + prefix count, one atomic per
-//                  wavefront per batch.
+//                  per-vertex boxes in LDS (FP32, rounded outward), cull each
+//                  primitive against the other patch's box, then each lane
+//                  holds one left-hand primitive box in registers and sweeps
+//                  the right-hand list from LDS; hits are buffered in LDS and
+//                  flushed with one atomic per batch.
 #include "stiv_common.h"
 
 namespace stiv {
@@ -100,32 +101,57 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 
 // --------------------------------------------------------------------------
 // Per work item: one wavefront.
+//
+// The primitive boxes here are FP32, rounded outward from the FP64 boxes, so
+// every pair whose FP64 boxes intersect passes (a superset).  The exact FP64
+// test is made by the narrow-phase kernel, which loads the same four vertices
+// anyway; only pairs passing it count as candidates.
 // --------------------------------------------------------------------------
-struct PrimList {
-  double box[kMaxPatchOwnE][6];
-  int id[kMaxPatchOwnE];
-};
+constexpr int kHitBuf = 256;
 
 struct WaveLds {
-  double vb[2][kMaxPatchRef][6];  // raw vertex boxes: min/max of X0, X1 (no inflation, no shift)
-  PrimList L[2];
-  int n[2];
+  float vb[2][kMaxPatchRef][6];  // per-vertex boxes: ((min - h) + sh, (max + h) + sh), outward to FP32
+  float rbox[kMaxPatchOwnE][6];  // right-hand list (current kind): boxes
+  int rid[kMaxPatchOwnE];        //   and primitive ids
+  int lk[kMaxPatchOwnE];         // left-hand list: patch-table index of the primitive
+  int nl, nr, nh;
+  Cand hits[kHitBuf];
 };
 
-// Box of a primitive from its vertex slots: (min - h) + sh, (max + h) + sh.
-__device__ inline void prim_box(const double (*vb)[6], const uint8_t *slot, int nvert, double h,
-                                const double *sh, double *out) {
-  double lo[3], hi[3];
-  for (int c = 0; c < 3; ++c) { lo[c] = vb[slot[0]][c]; hi[c] = vb[slot[0]][3 + c]; }
+__device__ inline bool ov6f(const float *A, const float *B) {
+  return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
+}
+
+__device__ inline void box_from_slots(const float (*vb)[6], const uint8_t *slot, int nvert, float *out) {
+  for (int c = 0; c < 6; ++c) out[c] = vb[slot[0]][c];
   for (int k = 1; k < nvert; ++k)
     for (int c = 0; c < 3; ++c) {
-      lo[c] = fmin(lo[c], vb[slot[k]][c]);
-      hi[c] = fmax(hi[c], vb[slot[k]][3 + c]);
+      out[c] = fminf(out[c], vb[slot[k]][c]);
+      out[3 + c] = fmaxf(out[3 + c], vb[slot[k]][3 + c]);
     }
-  for (int c = 0; c < 3; ++c) {
-    out[c] = (lo[c] - h) + sh[c];
-    out[3 + c] = (hi[c] + h) + sh[c];
-  }
+}
+
+__device__ inline float wave_minf(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline float wave_maxf(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Move the wave's buffered hits to the global pre-candidate list.
+__device__ inline void flush_hits(WaveLds &W, Cand *out, int64_t cap, unsigned long long *counter) {
+  const int lane = threadIdx.x;
+  const int n = W.nh;
+  unsigned long long base = 0;
+  if (lane == 0 && n) base = atomicAdd(counter, (unsigned long long)n);
+  base = __shfl(base, 0, 64);
+  for (int k = lane; k < n; k += 64)
+    if ((int64_t)(base + k) < cap) out[base + k] = W.hits[k];
+  __syncthreads();
+  if (lane == 0) W.nh = 0;
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const PairRec *pairs,
@@ -136,99 +162,95 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   const int lane = threadIdx.x;
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
-  const double zero[3] = {0.0, 0.0, 0.0};
+  if (lane == 0) W.nh = 0;
+  __syncthreads();
   for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
     const uint64_t wr = work[w];
     const int p = (int)(wr >> 32);
-    const int ia = (int)((wr >> 16) & 0xffffu), ib = (int)(wr & 0xffffu);
+    const int pk[2] = {(int)((wr >> 16) & 0xffffu), (int)(wr & 0xffffu)};
     const PairRec pr = pairs[p];
     const int ves[2] = {pr.a, pr.b};
-    const int pk[2] = {ia, ib};
     int P[2];
-    double pbox[2][6];
+    float pb[2][6];
     for (int side = 0; side < 2; ++side) {
-      const int t = S.topo_id[ves[side]];
-      P[side] = T.patch_off[t] + pk[side];
-      const double *src = patch_box + 6 * (ves_patch_off[ves[side]] + pk[side]);
-      const double *sh = side ? pr.sh : zero;
-      for (int c = 0; c < 3; ++c) { pbox[side][c] = src[c] + sh[c]; pbox[side][3 + c] = src[3 + c] + sh[c]; }
+      P[side] = T.patch_off[S.topo_id[ves[side]]] + pk[side];
       const int base = S.vtx_off[ves[side]];
-      const int r0 = T.pref_off[P[side]], r1 = T.pref_off[P[side] + 1];
-      for (int r = r0 + lane; r < r1; r += 64) {
-        const int64_t g = base + T.pref[r];
+      const int r0 = T.pref_off[P[side]], nref = T.pref_off[P[side] + 1] - r0;
+      const double sh[3] = {side ? pr.sh[0] : 0.0, side ? pr.sh[1] : 0.0, side ? pr.sh[2] : 0.0};
+      float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (int r = lane; r < nref; r += 64) {
+        const int64_t g = base + T.pref[r0 + r];
         for (int c = 0; c < 3; ++c) {
           const double a = S.x0[c * (int64_t)S.n_vtx + g], b = S.x1[c * (int64_t)S.n_vtx + g];
-          W.vb[side][r - r0][c] = fmin(a, b);
-          W.vb[side][r - r0][3 + c] = fmax(a, b);
+          const float l = __double2float_rd((fmin(a, b) - h) + sh[c]);
+          const float u = __double2float_ru((fmax(a, b) + h) + sh[c]);
+          W.vb[side][r][c] = l;
+          W.vb[side][r][3 + c] = u;
+          lo[c] = fminf(lo[c], l);
+          hi[c] = fmaxf(hi[c], u);
         }
+      }
+      for (int c = 0; c < 3; ++c) {
+        pb[side][c] = wave_minf(lo[c]);
+        pb[side][3 + c] = wave_maxf(hi[c]);
       }
     }
     __syncthreads();
-    // three phases: kind 0 (vertices of a x triangles of b), kind 1 (vertices
-    // of b x triangles of a), kind 2 (edges of a x edges of b)
     for (int kind = 0; kind < 3; ++kind) {
-      // list 0: the "left" primitive (vertex or edge of side sl), list 1: triangle or edge of side sr
-      const int sl = (kind == 1) ? 1 : 0;
-      const int sr = 1 - sl;
-      for (int li = 0; li < 2; ++li) {
-        const int side = li == 0 ? sl : sr;
-        const double *sh = side ? pr.sh : zero;
-        const double *other = pbox[1 - side];
-        int beg, end, nvert;
-        const int *ids;
-        const uint8_t *slots;
-        if (kind == 2) {
-          beg = T.pedge_off[P[side]]; end = T.pedge_off[P[side] + 1]; ids = T.pedge; slots = T.pedge_slot; nvert = 2;
-        } else if (li == 0) {
-          beg = T.pvtx_off[P[side]]; end = T.pvtx_off[P[side] + 1]; ids = T.pvtx; slots = T.pvtx_slot; nvert = 1;
-        } else {
-          beg = T.ptri_off[P[side]]; end = T.ptri_off[P[side] + 1]; ids = T.ptri; slots = T.ptri_slot; nvert = 3;
-        }
-        if (lane == 0) W.n[li] = 0;
-        __syncthreads();
-        for (int k0 = beg; k0 < end; k0 += 64) {
-          const int k = k0 + lane;
-          double bx[6];
-          bool keep = false;
-          if (k < end) {
-            prim_box(W.vb[side], slots + (int64_t)nvert * k, nvert, h, sh, bx);
-            keep = ov6(bx, other);
-          }
-          const unsigned long long m = __ballot(keep);
-          const int pos = W.n[li] + __popcll(m & lanemask_lt());
-          if (keep) {
-            for (int c = 0; c < 6; ++c) W.L[li].box[pos][c] = bx[c];
-            W.L[li].id[pos] = ids[k];
-          }
-          __syncthreads();
-          if (lane == 0) W.n[li] += __popcll(m);
-          __syncthreads();
+      const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
+      // left list: owned vertices (kinds 0, 1) or owned edges (kind 2) of side sl
+      const int lbeg = kind == 2 ? T.pedge_off[P[sl]] : T.pvtx_off[P[sl]];
+      const int lend = kind == 2 ? T.pedge_off[P[sl] + 1] : T.pvtx_off[P[sl] + 1];
+      const uint8_t *lslot = kind == 2 ? T.pedge_slot : T.pvtx_slot;
+      const int lnv = kind == 2 ? 2 : 1;
+      // right list: triangles (kinds 0, 1) or owned edges (kind 2) of side sr
+      const int rbeg = kind == 2 ? T.pedge_off[P[sr]] : T.ptri_off[P[sr]];
+      const int rend = kind == 2 ? T.pedge_off[P[sr] + 1] : T.ptri_off[P[sr] + 1];
+      const uint8_t *rslot = kind == 2 ? T.pedge_slot : T.ptri_slot;
+      const int *rids = kind == 2 ? T.pedge : T.ptri;
+      const int rnv = kind == 2 ? 2 : 3;
+      if (lane == 0) { W.nl = 0; W.nr = 0; }
+      __syncthreads();
+      for (int k = lbeg + lane; k < lend; k += 64) {
+        float bx[6];
+        box_from_slots(W.vb[sl], lslot + (int64_t)lnv * k, lnv, bx);
+        if (ov6f(bx, pb[sr])) W.lk[atomicAdd(&W.nl, 1)] = k;
+      }
+      for (int k = rbeg + lane; k < rend; k += 64) {
+        float bx[6];
+        box_from_slots(W.vb[sr], rslot + (int64_t)rnv * k, rnv, bx);
+        if (ov6f(bx, pb[sl])) {
+          const int q = atomicAdd(&W.nr, 1);
+          for (int c = 0; c < 6; ++c) W.rbox[q][c] = bx[c];
+          W.rid[q] = rids[k];
         }
       }
-      const int n0 = W.n[0], n1 = W.n[1];
-      const int tot = n0 * n1;
-      for (int base = 0; base < tot; base += 64) {
-        const int t = base + lane;
-        bool hit = false;
-        int i = 0, j = 0;
-        if (t < tot) {
-          const int x = t / n1, y = t % n1;
-          hit = ov6(W.L[0].box[x], W.L[1].box[y]);
-          i = W.L[0].id[x];
-          j = W.L[1].id[y];
+      __syncthreads();
+      const int nl = W.nl, nr = W.nr;
+      const int *lids = kind == 2 ? T.pedge : T.pvtx;
+      for (int l0 = 0; l0 < nl; l0 += 64) {
+        const bool act = l0 + lane < nl;
+        float lb[6];
+        int lidv = 0;
+        if (act) {
+          const int k = W.lk[l0 + lane];
+          box_from_slots(W.vb[sl], lslot + (int64_t)lnv * k, lnv, lb);
+          lidv = lids[k];
         }
-        const unsigned long long slot = wave_append(hit, &cnt->n_cand);
-        const int nh = __popcll(__ballot(hit));
-        if (lane == 0 && nh) atomicAdd(kind == 2 ? &cnt->n_cand_ee : &cnt->n_cand_vt, (unsigned long long)nh);
-        if (hit && (int64_t)slot < cand_cap) {
-          Cand cd;
-          cd.pair = p; cd.kind = kind; cd.i = i; cd.j = j;
-          cand[slot] = cd;
+        for (int j = 0; j < nr; ++j) {
+          if (*(volatile int *)&W.nh > kHitBuf - 64) flush_hits(W, cand, cand_cap, &cnt->n_pre);
+          if (act && ov6f(lb, W.rbox[j])) {
+            const int q = atomicAdd(&W.nh, 1);
+            Cand cd;
+            cd.pair = p; cd.kind = kind; cd.i = lidv; cd.j = W.rid[j];
+            W.hits[q] = cd;
+          }
         }
       }
       __syncthreads();
     }
   }
+  flush_hits(W, cand, cand_cap, &cnt->n_pre);
 }
 
 }  // namespace

@@ -64,6 +64,19 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_1wg(uint64_t *keys, uint
   const int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
   const int64_t lo = (int64_t)t * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  // only the bits below the largest key need passes
+  {
+    __shared__ unsigned long long kmax;
+    if (t == 0) kmax = 0;
+    __syncthreads();
+    uint64_t m = 0;
+    for (int64_t i = lo; i < hi; ++i) m = keys[i] > m ? keys[i] : m;
+    if (m) atomicMax(&kmax, (unsigned long long)m);
+    __syncthreads();
+    const int used = kmax ? 64 - __clzll((long long)kmax) : 0;
+    key_bits = used < key_bits ? used : key_bits;
+    __syncthreads();
+  }
   uint64_t *sk = keys, *dk = tk;
   uint32_t *sv = vals, *dv = tv;
   int passes = 0;

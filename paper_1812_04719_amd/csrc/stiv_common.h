@@ -64,12 +64,15 @@ struct Counters {
   unsigned long long n_raw_pairs;  // pair insertions (with duplicates)
   unsigned long long n_pairs;
   unsigned long long n_work;       // patch-pair work items
-  unsigned long long n_cand_vt, n_cand_ee, n_cand;
+  unsigned long long n_pre;        // FP32 pre-candidates (superset of the exact candidates)
+  unsigned long long n_cand_vt, n_cand_ee;  // exact FP64 candidates
+  unsigned long long n_hard;       // candidates whose F changes sign on [0,1] (root search)
+  unsigned long long n_cand_list;  // candidates written to the optional list
   unsigned long long n_ct, n_ct_vt, n_ct_ee;
   unsigned long long n_vol, n_jrow;
   unsigned long long within_d, degenerate;
   unsigned long long hash_overflow, shift_overflow, nonfinite, lds_fallback;
-  unsigned long long pad[4];
+  unsigned long long pad[1];
 };
 
 // Narrow-phase candidate record.
@@ -125,10 +128,13 @@ void launch_prim_cand(const DevScene &S, const DevTopo &T, const PairRec *pairs,
                       const double *patch_box, const uint64_t *work, int64_t work_cap, double h, Cand *cand,
                       int64_t cand_cap, Counters *cnt, hipStream_t st);
 
-// K3 + K4
-void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *cand, int64_t cand_cap,
-                   double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, Counters *cnt, hipStream_t st);
+// K3 + K4: screen (exact box test + one Bernstein test), then root search
+void launch_narrow_screen(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *pre,
+                          int64_t pre_cap, double d, int32_t *hard, int64_t hard_cap, Cand *list, int64_t list_cap,
+                          Counters *cnt, hipStream_t st);
+void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *pre, const int32_t *hard,
+                   int64_t hard_cap, double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol,
+                   double *ct_grad, int64_t ct_cap, Counters *cnt, hipStream_t st);
 
 // K5
 void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st);

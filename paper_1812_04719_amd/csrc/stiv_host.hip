@@ -61,7 +61,8 @@ struct stiv_ctx {
   int max_patches = 0;
   // arena
   Buf counters, ves_box, ves_scene, grid, cp_cnt, cp_off, cp_keys, cp_vals, cp_tk, cp_tv, hash, uniq, sorted,
-      cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, ct, ct_s, ct_vol,
+      cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
+      ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
       row_off, row_vtx, row_g, sort_tk, sort_tv;
   int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0;
@@ -129,7 +130,8 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->t_pref_off, &ctx->t_pref, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
-                &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->ct,
+                &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
+                &ctx->cand_list, &ctx->ct,
                 &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
                 &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
                 &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv};
@@ -340,6 +342,7 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->patch_box, 6 * 8 * (ctx->cap_patch + 1)));
   HIPCHK(ensure(ctx->work, 8 * ctx->cap_work));
   HIPCHK(ensure(ctx->cand, sizeof(Cand) * ctx->cap_cand));
+  HIPCHK(ensure(ctx->hard, sizeof(int32_t) * ctx->cap_cand));
   HIPCHK(ensure(ctx->ct, sizeof(Cand) * ctx->cap_ct));
   HIPCHK(ensure(ctx->ct_s, 8 * ctx->cap_ct));
   HIPCHK(ensure(ctx->ct_vol, 8 * ctx->cap_ct));
@@ -471,10 +474,13 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_prim_cand(S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box),
                    P<uint64_t>(ctx->work), ctx->cap_work, h, P<Cand>(ctx->cand), ctx->cap_cand, cnt, st);
   hipEventRecord(ctx->ev[4], st);
-  // ---- K3 + K4 narrow phase, volumes and gradients
-  launch_narrow(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps, p->dt,
-                P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
-                cnt, st);
+  // ---- K3 + K4 narrow phase (exact box test, screen, root search), volumes and gradients
+  const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
+  launch_narrow_screen(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, P<int32_t>(ctx->hard),
+                       ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr, emit ? ctx->cap_cand : 0, cnt, st);
+  launch_narrow(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), P<int32_t>(ctx->hard), ctx->cap_cand, p->d,
+                p->eps, p->dt, P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol),
+                P<double>(ctx->ct_grad), ctx->cap_ct, cnt, st);
   hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
   launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
@@ -522,6 +528,7 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
   for (int attempt = 0; attempt < 4; ++attempt) {
     stiv_status sa = arena(ctx, s);
     if (sa != STIV_OK) return sa;
+    if (p->flags & STIV_EMIT_CANDIDATES) HIPCHK(ensure(ctx->cand_list, sizeof(Cand) * ctx->cap_cand));
     run_pipeline(ctx, S, p, out, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -538,7 +545,7 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
       grow = true;
     }
     if ((int64_t)c.n_work > ctx->cap_work) { ctx->cap_work = (int64_t)c.n_work + c.n_work / 4 + 1024; grow = true; }
-    if ((int64_t)c.n_cand > ctx->cap_cand) { ctx->cap_cand = (int64_t)c.n_cand + c.n_cand / 4 + 1024; grow = true; }
+    if ((int64_t)c.n_pre > ctx->cap_cand) { ctx->cap_cand = (int64_t)c.n_pre + c.n_pre / 4 + 1024; grow = true; }
     if ((int64_t)c.n_ct > ctx->cap_ct) { ctx->cap_ct = (int64_t)c.n_ct + c.n_ct / 4 + 1024; grow = true; }
     if (grow) continue;
     out->n_pairs = (int64_t)c.n_pairs;
@@ -558,7 +565,7 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
     if ((p->flags & STIV_EMIT_CANDIDATES) && out->cand) {
       const int64_t n = std::min(n_cand, out->cap_cand);
       if (n > 0) {
-        HIPCHK(hipMemcpyAsync(out->cand, ctx->cand.p, (size_t)n * sizeof(Cand), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(out->cand, ctx->cand_list.p, (size_t)n * sizeof(Cand), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
       }
     }
@@ -574,6 +581,15 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
 stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n) {
   if (!ctx || !ms) return STIV_E_ARG;
   for (int k = 0; k < n && k < 7; ++k) ms[k] = ctx->stage_ms[k];
+  return STIV_OK;
+}
+
+stiv_status stiv_get_stats(stiv_ctx *ctx, int64_t *vals, int n) {
+  if (!ctx || !vals) return STIV_E_ARG;
+  const Counters &c = *ctx->h_cnt;
+  const int64_t v[8] = {(int64_t)c.n_cp, (int64_t)c.n_pairs, (int64_t)c.n_work, (int64_t)c.n_pre,
+                        (int64_t)c.n_cand_vt, (int64_t)c.n_cand_ee, (int64_t)c.n_hard, (int64_t)c.n_ct};
+  for (int k = 0; k < n && k < 8; ++k) vals[k] = v[k];
   return STIV_OK;
 }
 

@@ -22,7 +22,9 @@ _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HI
            -5: "STIV_E_STATE"}
 
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
-           "stiv_get_stage_times", "stiv_sort_pairs_u64", "stiv_last_error")
+           "stiv_get_stage_times", "stiv_get_stats", "stiv_sort_pairs_u64", "stiv_last_error")
+STAT_NAMES = ("check_points", "vesicle_pairs", "work_items", "pre_candidates", "candidates_vt", "candidates_ee",
+              "root_searches", "contacts")
 
 
 class StivError(RuntimeError):
@@ -78,6 +80,7 @@ def lib():
             L.stiv_detect.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_params),
                                       C.POINTER(stiv_result), C.c_void_p]
             L.stiv_get_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int]
+            L.stiv_get_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int]
             L.stiv_sort_pairs_u64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
             L.stiv_last_error.argtypes = [C.c_void_p]
             L.stiv_last_error.restype = C.c_char_p
@@ -141,6 +144,11 @@ class Context:
         ms = (C.c_float * 7)()
         self._check(lib().stiv_get_stage_times(self._h, ms, 7))
         return list(ms)
+
+    def stats(self):
+        v = (C.c_int64 * 8)()
+        self._check(lib().stiv_get_stats(self._h, v, 8))
+        return dict(zip(STAT_NAMES, list(v)))
 
     def sort_pairs_u64(self, keys, vals):
         """Stable sort of device uint64 keys (as int64 tensor bits) with uint32 values (as int32)."""
