@@ -11,13 +11,10 @@
 //   k_patch_pairs  one workgroup per vesicle pair: cull each side's patches
 //                  against the other vesicle's box, then test the surviving
 //                  patch pairs; emit (pair, patch a, patch b) work items.
-//   k_prim_cand    one wavefront per work item: stage the two patches'
-//                  per-vertex boxes in LDS (FP32, rounded outward), cull each
-//                  primitive against the other patch's box, then each lane
-//                  holds one left-hand primitive box in registers and sweeps
-//                  the right-hand list from LDS; hits are buffered in LDS and
-//                  flushed with one atomic per batch.
-#include "stiv_common.h"
+//   k_prim_cand    one wavefront per work item: FP32 register-tiled filter
+//                  over LDS-staged patches, then the exact FP64 box test and
+//                  the polynomial screen of the narrow phase on the hits.
+#include "narrow_math.h"
 
 namespace stiv {
 
@@ -100,35 +97,55 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 }
 
 // --------------------------------------------------------------------------
-// Per work item: one wavefront.
+// Per work item: one wavefront, FP64 positions of both patches in LDS.
 //
-// The primitive boxes here are FP32, rounded outward from the FP64 boxes, so
-// every pair whose FP64 boxes intersect passes (a superset).  The exact FP64
-// test is made by the narrow-phase kernel, which loads the same four vertices
-// anyway; only pairs passing it count as candidates.
+// 1. Stage X0 and X1 of every vertex referenced by the two patches.
+// 2. Per kind, build the left list (owned vertices, or owned edges) and the
+//    right list (triangles, or owned edges) of primitives whose boxes meet
+//    the other patch's box; boxes are FP32 rounded outward from the FP64
+//    boxes, so the filter keeps a superset.
+// 3. Each lane holds one left box in registers and sweeps the right list in
+//    LDS; FP32 hits are buffered in LDS.
+// 4. Buffered hits are processed 64 at a time with all lanes busy: the exact
+//    FP64 box test (the candidate definition), then the polynomial screen.
+//    Candidates whose polynomial can have a root on [0,1] are queued for the
+//    root-search kernel; the rest are finished here.
 // --------------------------------------------------------------------------
 constexpr int kHitBuf = 256;
 
 struct WaveLds {
-  float vb[2][kMaxPatchRef][6];  // per-vertex boxes: ((min - h) + sh, (max + h) + sh), outward to FP32
-  float rbox[kMaxPatchOwnE][6];  // right-hand list (current kind): boxes
-  int rid[kMaxPatchOwnE];        //   and primitive ids
-  int lk[kMaxPatchOwnE];         // left-hand list: patch-table index of the primitive
+  double pos[2][kMaxPatchRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
+  float rbox[kMaxPatchOwnE][6];    // right-hand list of the current kind: FP32 boxes
+  int rk[kMaxPatchOwnE];           //   and patch-table indices
+  int lk[kMaxPatchOwnE];           // left-hand list: patch-table indices
   int nl, nr, nh;
-  Cand hits[kHitBuf];
+  int4 hits[kHitBuf];              // (kind, left index, right index, -)
 };
 
 __device__ inline bool ov6f(const float *A, const float *B) {
   return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
 }
 
-__device__ inline void box_from_slots(const float (*vb)[6], const uint8_t *slot, int nvert, float *out) {
-  for (int c = 0; c < 6; ++c) out[c] = vb[slot[0]][c];
+// FP64 box of a primitive (min - h + sh, max + h + sh), rounded outward to FP32.
+__device__ inline void prim_box32(const double (*pos)[6], const uint8_t *slot, int nvert, double h, const double *sh,
+                                  float *out) {
+  double lo[3], hi[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = fmin(pos[slot[0]][c], pos[slot[0]][3 + c]);
+    hi[c] = fmax(pos[slot[0]][c], pos[slot[0]][3 + c]);
+  }
   for (int k = 1; k < nvert; ++k)
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      out[c] = fminf(out[c], vb[slot[k]][c]);
-      out[3 + c] = fmaxf(out[3 + c], vb[slot[k]][3 + c]);
+      lo[c] = fmin(lo[c], fmin(pos[slot[k]][c], pos[slot[k]][3 + c]));
+      hi[c] = fmax(hi[c], fmax(pos[slot[k]][c], pos[slot[k]][3 + c]));
     }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    out[c] = __double2float_rd((lo[c] - h) + sh[c]);
+    out[3 + c] = __double2float_ru((hi[c] + h) + sh[c]);
+  }
 }
 
 __device__ inline float wave_minf(float v) {
@@ -140,28 +157,118 @@ __device__ inline float wave_maxf(float v) {
   return v;
 }
 
-// Move the wave's buffered hits to the global pre-candidate list.
-__device__ inline void flush_hits(WaveLds &W, Cand *out, int64_t cap, unsigned long long *counter) {
+// Exact FP64 box test of a buffered hit and the polynomial screen; queue the
+// candidates that need a root search.  All 64 lanes take part.
+template <int N>
+__device__ void process_hits(WaveLds &W, const DevTopo &T, const PairRec &pr, int p, const int P[2], double d,
+                             Cand *hard, int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt,
+                             unsigned long long &nvt, unsigned long long &nee) {
   const int lane = threadIdx.x;
-  const int n = W.nh;
-  unsigned long long base = 0;
-  if (lane == 0 && n) base = atomicAdd(counter, (unsigned long long)n);
-  base = __shfl(base, 0, 64);
-  for (int k = lane; k < n; k += 64)
-    if ((int64_t)(base + k) < cap) out[base + k] = W.hits[k];
+  const double h = 0.5 * d;
+  const int nh = *(volatile int *)&W.nh;
+  for (int r0 = 0; r0 < nh; r0 += 64) {
+    const int k = r0 + lane;
+    bool is_cand = false, need = false;
+    Cand c;
+    c.pair = p; c.kind = 0; c.i = 0; c.j = 0;
+    if (k < nh) {
+      const int4 hv = W.hits[k];
+      const int kind = hv.x, kl = hv.y, kr = hv.z;
+      const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
+      int slots[4];
+      if (kind == 2) {
+        slots[0] = T.pedge_slot[2 * kl]; slots[1] = T.pedge_slot[2 * kl + 1];
+        slots[2] = T.pedge_slot[2 * kr]; slots[3] = T.pedge_slot[2 * kr + 1];
+      } else {
+        slots[0] = T.pvtx_slot[kl];
+        slots[1] = T.ptri_slot[3 * kr]; slots[2] = T.ptri_slot[3 * kr + 1]; slots[3] = T.ptri_slot[3 * kr + 2];
+      }
+      const bool ee = kind == 2;
+      // vertex k belongs to side sl for the first primitive, sr for the second
+      const int nfirst = ee ? 2 : 1;
+      nm::Quad Q;
+      Q.ee = ee;
+      double lo[2][3], hi[2][3];
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) { lo[g][q] = INFINITY; hi[g][q] = -INFINITY; }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool second = v >= nfirst;
+        const int side = second ? sr : sl;
+        const double *pp = W.pos[side][slots[v]];
+        const double shx = side ? pr.sh[0] : 0.0, shy = side ? pr.sh[1] : 0.0, shz = side ? pr.sh[2] : 0.0;
+        Q.X0[v] = nm::mk(pp[0] + shx, pp[1] + shy, pp[2] + shz);
+        Q.D[v] = nm::mk(pp[3] - pp[0], pp[4] - pp[1], pp[5] - pp[2]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double mn = fmin(pp[q], pp[3 + q]), mx = fmax(pp[q], pp[3 + q]);
+          if (second) { lo[1][q] = fmin(lo[1][q], mn); hi[1][q] = fmax(hi[1][q], mx); }
+          else { lo[0][q] = fmin(lo[0][q], mn); hi[0][q] = fmax(hi[0][q], mx); }
+        }
+      }
+      bool ov = true;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double s0 = sl ? pr.sh[q] : 0.0, s1 = sr ? pr.sh[q] : 0.0;
+        const double l0 = (lo[0][q] - h) + s0, u0 = (hi[0][q] + h) + s0;
+        const double l1 = (lo[1][q] - h) + s1, u1 = (hi[1][q] + h) + s1;
+        ov = ov && l0 <= u1 && l1 <= u0;
+      }
+      if (ov) {
+        is_cand = true;
+        if (ee) ++nee; else ++nvt;
+        c.kind = kind;
+        c.i = ee ? T.pedge[kl] : T.pvtx[kl];
+        c.j = ee ? T.pedge[kr] : T.ptri[kr];
+        need = nm::needs_root_search<N>(Q, d);
+      }
+    }
+    const unsigned long long mh = __ballot(need);
+    if (mh) {
+      const int leader = __ffsll((long long)mh) - 1;
+      unsigned long long b = 0;
+      if (lane == leader) b = atomicAdd(&cnt->n_hard, (unsigned long long)__popcll(mh));
+      b = __shfl(b, leader, 64);
+      if (need) {
+        const unsigned long long slot = b + __popcll(mh & lanemask_lt());
+        if ((int64_t)slot < hard_cap) hard[slot] = c;
+      }
+    }
+    if (list) {
+      const unsigned long long mc = __ballot(is_cand);
+      if (mc) {
+        const int leader = __ffsll((long long)mc) - 1;
+        unsigned long long b = 0;
+        if (lane == leader) b = atomicAdd(&cnt->n_cand_list, (unsigned long long)__popcll(mc));
+        b = __shfl(b, leader, 64);
+        if (is_cand) {
+          const unsigned long long slot = b + __popcll(mc & lanemask_lt());
+          if ((int64_t)slot < list_cap) list[slot] = c;
+        }
+      }
+    }
+  }
   __syncthreads();
-  if (lane == 0) W.nh = 0;
+  if (lane == 0) {
+    W.nh = 0;
+    if (nh) atomicAdd(&cnt->n_pre, (unsigned long long)nh);
+  }
   __syncthreads();
 }
 
+template <int N>
 __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const PairRec *pairs,
-                                                  const int64_t *ves_patch_off, const double *patch_box,
-                                                  const uint64_t *work, int64_t work_cap, double h, Cand *cand,
-                                                  int64_t cand_cap, Counters *cnt) {
+                                                  const int64_t *ves_patch_off, const uint64_t *work,
+                                                  int64_t work_cap, double d, Cand *hard, int64_t hard_cap,
+                                                  Cand *list, int64_t list_cap, Counters *cnt) {
   __shared__ WaveLds W;
   const int lane = threadIdx.x;
+  const double h = 0.5 * d;
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
+  unsigned long long nvt = 0, nee = 0;
   if (lane == 0) W.nh = 0;
   __syncthreads();
   for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
@@ -170,26 +277,28 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     const int pk[2] = {(int)((wr >> 16) & 0xffffu), (int)(wr & 0xffffu)};
     const PairRec pr = pairs[p];
     const int ves[2] = {pr.a, pr.b};
+    const double zero[3] = {0.0, 0.0, 0.0};
     int P[2];
     float pb[2][6];
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
       P[side] = T.patch_off[S.topo_id[ves[side]]] + pk[side];
       const int base = S.vtx_off[ves[side]];
       const int r0 = T.pref_off[P[side]], nref = T.pref_off[P[side] + 1] - r0;
-      const double sh[3] = {side ? pr.sh[0] : 0.0, side ? pr.sh[1] : 0.0, side ? pr.sh[2] : 0.0};
+      const double *sh = side ? pr.sh : zero;
       float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
       for (int r = lane; r < nref; r += 64) {
         const int64_t g = base + T.pref[r0 + r];
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
           const double a = S.x0[c * (int64_t)S.n_vtx + g], b = S.x1[c * (int64_t)S.n_vtx + g];
-          const float l = __double2float_rd((fmin(a, b) - h) + sh[c]);
-          const float u = __double2float_ru((fmax(a, b) + h) + sh[c]);
-          W.vb[side][r][c] = l;
-          W.vb[side][r][3 + c] = u;
-          lo[c] = fminf(lo[c], l);
-          hi[c] = fmaxf(hi[c], u);
+          W.pos[side][r][c] = a;
+          W.pos[side][r][3 + c] = b;
+          lo[c] = fminf(lo[c], __double2float_rd((fmin(a, b) - h) + sh[c]));
+          hi[c] = fmaxf(hi[c], __double2float_ru((fmax(a, b) + h) + sh[c]));
         }
       }
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         pb[side][c] = wave_minf(lo[c]);
         pb[side][3 + c] = wave_maxf(hi[c]);
@@ -198,59 +307,61 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     __syncthreads();
     for (int kind = 0; kind < 3; ++kind) {
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
-      // left list: owned vertices (kinds 0, 1) or owned edges (kind 2) of side sl
       const int lbeg = kind == 2 ? T.pedge_off[P[sl]] : T.pvtx_off[P[sl]];
       const int lend = kind == 2 ? T.pedge_off[P[sl] + 1] : T.pvtx_off[P[sl] + 1];
       const uint8_t *lslot = kind == 2 ? T.pedge_slot : T.pvtx_slot;
       const int lnv = kind == 2 ? 2 : 1;
-      // right list: triangles (kinds 0, 1) or owned edges (kind 2) of side sr
       const int rbeg = kind == 2 ? T.pedge_off[P[sr]] : T.ptri_off[P[sr]];
       const int rend = kind == 2 ? T.pedge_off[P[sr] + 1] : T.ptri_off[P[sr] + 1];
       const uint8_t *rslot = kind == 2 ? T.pedge_slot : T.ptri_slot;
-      const int *rids = kind == 2 ? T.pedge : T.ptri;
       const int rnv = kind == 2 ? 2 : 3;
+      const double *shl = sl ? pr.sh : zero, *shr = sr ? pr.sh : zero;
       if (lane == 0) { W.nl = 0; W.nr = 0; }
       __syncthreads();
       for (int k = lbeg + lane; k < lend; k += 64) {
         float bx[6];
-        box_from_slots(W.vb[sl], lslot + (int64_t)lnv * k, lnv, bx);
+        prim_box32(W.pos[sl], lslot + (int64_t)lnv * k, lnv, h, shl, bx);
         if (ov6f(bx, pb[sr])) W.lk[atomicAdd(&W.nl, 1)] = k;
       }
       for (int k = rbeg + lane; k < rend; k += 64) {
         float bx[6];
-        box_from_slots(W.vb[sr], rslot + (int64_t)rnv * k, rnv, bx);
+        prim_box32(W.pos[sr], rslot + (int64_t)rnv * k, rnv, h, shr, bx);
         if (ov6f(bx, pb[sl])) {
           const int q = atomicAdd(&W.nr, 1);
+#pragma unroll
           for (int c = 0; c < 6; ++c) W.rbox[q][c] = bx[c];
-          W.rid[q] = rids[k];
+          W.rk[q] = k;
         }
       }
       __syncthreads();
       const int nl = W.nl, nr = W.nr;
-      const int *lids = kind == 2 ? T.pedge : T.pvtx;
       for (int l0 = 0; l0 < nl; l0 += 64) {
         const bool act = l0 + lane < nl;
         float lb[6];
-        int lidv = 0;
+        int kl = 0;
         if (act) {
-          const int k = W.lk[l0 + lane];
-          box_from_slots(W.vb[sl], lslot + (int64_t)lnv * k, lnv, lb);
-          lidv = lids[k];
+          kl = W.lk[l0 + lane];
+          prim_box32(W.pos[sl], lslot + (int64_t)lnv * kl, lnv, h, shl, lb);
         }
         for (int j = 0; j < nr; ++j) {
-          if (*(volatile int *)&W.nh > kHitBuf - 64) flush_hits(W, cand, cand_cap, &cnt->n_pre);
-          if (act && ov6f(lb, W.rbox[j])) {
-            const int q = atomicAdd(&W.nh, 1);
-            Cand cd;
-            cd.pair = p; cd.kind = kind; cd.i = lidv; cd.j = W.rid[j];
-            W.hits[q] = cd;
-          }
+          if (*(volatile int *)&W.nh > kHitBuf - 64)
+            process_hits<N>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee);
+          if (act && ov6f(lb, W.rbox[j])) W.hits[atomicAdd(&W.nh, 1)] = make_int4(kind, kl, W.rk[j], 0);
         }
       }
       __syncthreads();
     }
+    // the buffered hits refer to this work item's LDS positions: finish them now
+    process_hits<N>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee);
   }
-  flush_hits(W, cand, cand_cap, &cnt->n_pre);
+  for (int off = 32; off > 0; off >>= 1) {
+    nvt += __shfl_xor(nvt, off, 64);
+    nee += __shfl_xor(nee, off, 64);
+  }
+  if (lane == 0) {
+    if (nvt) atomicAdd(&cnt->n_cand_vt, nvt);
+    if (nee) atomicAdd(&cnt->n_cand_ee, nee);
+  }
 }
 
 }  // namespace
@@ -263,9 +374,14 @@ void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pair
 }
 
 void launch_prim_cand(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
-                      const double *patch_box, const uint64_t *work, int64_t work_cap, double h, Cand *cand,
-                      int64_t cand_cap, Counters *cnt, hipStream_t st) {
-  k_prim_cand<<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, patch_box, work, work_cap, h, cand, cand_cap, cnt);
+                      const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
+                      int64_t list_cap, Counters *cnt, hipStream_t st) {
+  if (d == 0.0)
+    k_prim_cand<3><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
+                                        list_cap, cnt);
+  else
+    k_prim_cand<6><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
+                                        list_cap, cnt);
 }
 
 }  // namespace stiv

@@ -1,0 +1,310 @@
+// FP64 narrow-phase mathematics shared by the primitive-candidate kernel
+// (screen) and the root-search kernel.  See k_narrow.hip for the method.
+#pragma once
+#include "stiv_common.h"
+
+namespace stiv {
+namespace nm {
+
+struct d3 {
+  double x, y, z;
+};
+__host__ __device__ inline d3 mk(double x, double y, double z) { return d3{x, y, z}; }
+__host__ __device__ inline d3 operator+(d3 a, d3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__host__ __device__ inline d3 operator-(d3 a, d3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__host__ __device__ inline d3 operator*(double s, d3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__host__ __device__ inline double dotp(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline d3 crossp(d3 a, d3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+struct Quad {
+  d3 X0[4], D[4];  // vertex-triangle: p, a, b, c; edge-edge: a, b, c, e
+  bool ee;
+};
+
+__host__ __device__ inline d3 at(const Quad &Q, int k, double s) { return Q.X0[k] + s * Q.D[k]; }
+__host__ __device__ inline d3 vmin(d3 a, d3 b) { return mk(fmin(a.x, b.x), fmin(a.y, b.y), fmin(a.z, b.z)); }
+__host__ __device__ inline d3 vmax(d3 a, d3 b) { return mk(fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)); }
+
+// F coefficients, lowest degree first.  N = 6: F = g^2 - d^2 q; N = 3: F = g
+// (used when d == 0).  All loops have compile-time bounds so the coefficient
+// arrays stay in registers.
+template <int N>
+__host__ __device__ void poly_coeffs(const Quad &Q, double d, double f[N + 1]) {
+  d3 u0, u1, v0, v1, w0, w1;
+  if (!Q.ee) {
+    u0 = Q.X0[2] - Q.X0[1]; u1 = Q.D[2] - Q.D[1];
+    v0 = Q.X0[3] - Q.X0[1]; v1 = Q.D[3] - Q.D[1];
+    w0 = Q.X0[0] - Q.X0[1]; w1 = Q.D[0] - Q.D[1];
+  } else {
+    u0 = Q.X0[1] - Q.X0[0]; u1 = Q.D[1] - Q.D[0];
+    v0 = Q.X0[3] - Q.X0[2]; v1 = Q.D[3] - Q.D[2];
+    w0 = Q.X0[2] - Q.X0[0]; w1 = Q.D[2] - Q.D[0];
+  }
+  const d3 n0 = crossp(u0, v0);
+  const d3 n1 = crossp(u0, v1) + crossp(u1, v0);
+  const d3 n2 = crossp(u1, v1);
+  const double g0 = dotp(w0, n0), g1 = dotp(w1, n0) + dotp(w0, n1), g2 = dotp(w1, n1) + dotp(w0, n2),
+               g3 = dotp(w1, n2);
+  if constexpr (N == 3) {
+    (void)d;
+    f[0] = g0; f[1] = g1; f[2] = g2; f[3] = g3;
+  } else {
+    const double q0 = dotp(n0, n0), q1 = 2.0 * dotp(n0, n1), q2 = dotp(n1, n1) + 2.0 * dotp(n0, n2),
+                 q3 = 2.0 * dotp(n1, n2), q4 = dotp(n2, n2);
+    const double dd = d * d;
+    f[0] = g0 * g0 - dd * q0;
+    f[1] = 2.0 * (g0 * g1) - dd * q1;
+    f[2] = (g1 * g1 + 2.0 * (g0 * g2)) - dd * q2;
+    f[3] = 2.0 * (g0 * g3 + g1 * g2) - dd * q3;
+    f[4] = (g2 * g2 + 2.0 * (g1 * g3)) - dd * q4;
+    f[5] = 2.0 * (g2 * g3);
+    f[6] = g3 * g3;
+  }
+}
+
+template <int N>
+__host__ __device__ inline double horner(const double f[N + 1], double s) {
+  double r = f[N];
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k) r = r * s + f[k];
+  return r;
+}
+
+// 1 inside, 0 outside, -1 degenerate (normal vanishes).
+__host__ __device__ inline int inside_at(const Quad &Q, double s) {
+  const d3 A = at(Q, 0, s), B = at(Q, 1, s), C = at(Q, 2, s), E = at(Q, 3, s);
+  if (!Q.ee) {
+    const d3 e1 = C - B, e2 = E - B, w = A - B;
+    const d3 n = crossp(e1, e2);
+    const double q = dotp(n, n);
+    if (q == 0.0) return -1;
+    const double bb = dotp(crossp(w, e2), n), cc = dotp(crossp(e1, w), n);
+    return (bb >= 0.0 && cc >= 0.0 && bb + cc <= q) ? 1 : 0;
+  }
+  const d3 ea = B - A, eb = E - C, w = C - A;
+  const d3 m = crossp(ea, eb);
+  const double q = dotp(m, m);
+  if (q == 0.0) return -1;
+  const double uu = dotp(crossp(w, eb), m), vv = dotp(crossp(w, ea), m);
+  return (uu >= 0.0 && uu <= q && vv >= 0.0 && vv <= q) ? 1 : 0;
+}
+
+// Bernstein coefficients of f restricted to [u, u + wd]: Taylor shift to u,
+// scale by wd, then b_j = sum_{k<=j} C(j,k)/C(N,k) c_k (j-fold prefix sums of
+// c_k / C(N,k)).
+template <int N>
+__host__ __device__ void bernstein_on(const double f[N + 1], double u, double wd, double b[N + 1]) {
+  double c[N + 1];
+#pragma unroll
+  for (int k = 0; k <= N; ++k) c[k] = f[k];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = N - 1; k >= i; --k) c[k] += u * c[k + 1];
+  double p = wd;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) { c[k] *= p; p *= wd; }
+  double binom = 1.0;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    binom = binom * (double)(N - k + 1) / (double)k;
+    c[k] /= binom;
+  }
+#pragma unroll
+  for (int j = 0; j <= N; ++j) b[j] = c[j];
+#pragma unroll
+  for (int r = 1; r <= N; ++r)
+#pragma unroll
+    for (int j = N; j >= r; --j) b[j] += b[j - 1];
+}
+
+// Root of f in [lo, hi] where f(lo) = flo != 0 and f changes sign: Newton
+// steps kept inside the shrinking bracket, bisection when a step would leave
+// it or converge too slowly; stops at a step below 2^-52 or a bracket of
+// width 2^-50.
+template <int N>
+__host__ __device__ double refine(const double f[N + 1], double lo, double hi, double flo) {
+  const double tol = 8.881784197001252e-16;
+  double x = 0.5 * (lo + hi), dx = hi - lo, dxold = dx;
+  for (int it = 0; it < 100; ++it) {
+    double fx = f[N], dfx = 0.0;
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+      dfx = dfx * x + fx;
+      fx = fx * x + f[k];
+    }
+    if (fx == 0.0) return x;
+    if ((fx < 0.0) == (flo < 0.0)) { lo = x; flo = fx; } else { hi = x; }
+    if (hi - lo <= tol) break;
+    const double xn = (dfx != 0.0) ? x - fx / dfx : x;
+    if (!(xn > lo && xn < hi) || fabs(2.0 * fx) > fabs(dxold * dfx)) {
+      dxold = dx;
+      dx = 0.5 * (hi - lo);
+      x = lo + dx;
+    } else {
+      dxold = dx;
+      dx = xn - x;
+      x = xn;
+      if (fabs(dx) <= 2.220446049250313e-16 * fmax(fabs(x), 1e-300)) break;
+    }
+  }
+  return x;
+}
+
+// Earliest valid root of F (degree N).  Returns 1 with *s on contact.
+// *deg counts degenerate skips (vanishing normal at a root, F == 0, or a
+// polynomial that stays zero up to rounding over a whole interval).
+template <int N>
+__host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *within, int *deg) {
+  double f[N + 1];
+  poly_coeffs<N>(Q, d, f);
+  bool allzero = true;
+#pragma unroll
+  for (int k = 0; k <= N; ++k) allzero &= (f[k] == 0.0);
+  if (allzero) { (*deg)++; return 0; }
+  if (N == 6 && f[0] < 0.0 && inside_at(Q, 0.0) == 1) {
+    (*within)++;
+    *s_out = 0.0;
+    return 1;
+  }
+  const int kMaxLevel = 44;
+  const int kMaxVisits = 4096;
+  int level = 0, visits = 0;
+  long long idx = 0;
+  while (true) {
+    if (++visits > kMaxVisits) {
+      (*deg)++;
+      return 0;
+    }
+    const double wd = ldexp(1.0, -level);
+    const double u = (double)idx * wd;
+    double b[N + 1];
+    bernstein_on<N>(f, u, wd, b);
+    bool pos = true, neg = true;
+    int changes = 0, last = 0;
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      pos &= b[k] > 0.0;
+      neg &= b[k] < 0.0;
+      const int sg = (b[k] > 0.0) - (b[k] < 0.0);
+      if (sg != 0) {
+        if (last != 0 && sg != last) ++changes;
+        last = sg;
+      }
+    }
+    bool descend = false;
+    if (!(pos || neg)) {
+      const double v = u + wd;
+      const double fu = horner<N>(f, u), fv = horner<N>(f, v);
+      double root = -1.0;
+      if (changes == 1 && b[0] != 0.0 && b[N] != 0.0 && fu != 0.0 && fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
+        root = refine<N>(f, u, v, fu);
+      } else if (level < kMaxLevel) {
+        descend = true;
+      } else if (fu == 0.0) {
+        root = u;
+      } else if (fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
+        root = refine<N>(f, u, v, fu);
+      }
+      if (root >= 0.0) {
+        const int in = inside_at(Q, root);
+        if (in < 0) (*deg)++;
+        if (in == 1) {
+          *s_out = root;
+          return 1;
+        }
+      }
+    }
+    if (descend) {
+      ++level;
+      idx <<= 1;
+      continue;
+    }
+    // next interval in left-to-right order
+    while (level > 0 && (idx & 1)) { idx >>= 1; --level; }
+    if (level == 0) break;
+    ++idx;
+  }
+  return 0;
+}
+
+// V and dV/dX1 (order p, a, b, c) of a vertex-triangle contact at s.
+__host__ __device__ inline void volume_grad(const Quad &Q, double s, double d, double eps, double dt, bool clamped, double *V,
+                            double g[12]) {
+  const d3 Pp = at(Q, 0, s), Pa = at(Q, 1, s), Pb = at(Q, 2, s), Pc = at(Q, 3, s);
+  const d3 e1 = Pb - Pa, e2 = Pc - Pa, w = Pp - Pa;
+  const d3 e1s = Q.D[2] - Q.D[1], e2s = Q.D[3] - Q.D[1], ws = Q.D[0] - Q.D[1];
+  const d3 n = crossp(e1, e2);
+  const double q = dotp(n, n);
+  const d3 U = (1.0 / dt) * Q.D[0];
+  const double un = dotp(U, n);
+  const double R = sqrt(eps * eps * q + un * un);
+  *V = 0.5 * dt * (1.0 - s) * R;
+  const d3 m = (1.0 / R) * ((eps * eps) * n + un * U);
+  const double k = 0.5 * dt * (1.0 - s);
+  d3 gp = (0.5 * (1.0 - s) * un / R) * n;
+  d3 ga = (k * s) * crossp(e1 - e2, m);
+  d3 gb = (k * s) * crossp(e2, m);
+  d3 gc = (k * s) * crossp(m, e1);
+  if (!clamped) {
+    const d3 ns = crossp(e1s, e2) + crossp(e1, e2s);
+    const double gv = dotp(w, n);
+    const double gs = dotp(ws, n) + dotp(w, ns);
+    const d3 dgp = n, dga = crossp(e1 - e2, w) - n, dgb = crossp(e2, w), dgc = crossp(w, e1);
+    double Fs;
+    d3 Fp, Fa, Fb, Fc;
+    if (d == 0.0) {
+      Fs = gs; Fp = dgp; Fa = dga; Fb = dgb; Fc = dgc;
+    } else {
+      const double dd = d * d;
+      Fs = 2.0 * gv * gs - 2.0 * dd * dotp(n, ns);
+      Fp = (2.0 * gv) * dgp;
+      Fa = (2.0 * gv) * dga - dd * (2.0 * crossp(e1 - e2, n));
+      Fb = (2.0 * gv) * dgb - dd * (2.0 * crossp(e2, n));
+      Fc = (2.0 * gv) * dgc - dd * (2.0 * crossp(n, e1));
+    }
+    if (Fs != 0.0) {
+      const double dVds = 0.5 * dt * (-R + (1.0 - s) * dotp(m, ns));
+      const double cf = -dVds * s / Fs;
+      gp = gp + cf * Fp;
+      ga = ga + cf * Fa;
+      gb = gb + cf * Fb;
+      gc = gc + cf * Fc;
+    }
+  }
+  g[0] = gp.x; g[1] = gp.y; g[2] = gp.z;
+  g[3] = ga.x; g[4] = ga.y; g[5] = ga.z;
+  g[6] = gb.x; g[7] = gb.y; g[8] = gb.z;
+  g[9] = gc.x; g[10] = gc.y; g[11] = gc.z;
+}
+
+// Screen of one candidate: true if F may have a root in [0,1] or the vertex
+// may start within d (the candidate then needs the root search).  Uses the
+// Bernstein coefficients on [0,1]: all positive (d > 0) or all of one strict
+// sign (d = 0) proves there is neither.
+template <int N>
+__host__ __device__ inline bool needs_root_search(const Quad &Q, double d) {
+  double f[N + 1], b[N + 1];
+  poly_coeffs<N>(Q, d, f);
+  double binom = 1.0;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    binom = binom * (double)(N - k + 1) / (double)k;
+    f[k] /= binom;
+  }
+#pragma unroll
+  for (int j = 0; j <= N; ++j) b[j] = f[j];
+#pragma unroll
+  for (int r = 1; r <= N; ++r)
+#pragma unroll
+    for (int j = N; j >= r; --j) b[j] += b[j - 1];
+  bool pos = true, neg = true;
+#pragma unroll
+  for (int k = 0; k <= N; ++k) { pos &= b[k] > 0.0; neg &= b[k] < 0.0; }
+  return !(pos || (N == 3 && neg));
+}
+
+}  // namespace nm
+}  // namespace stiv

@@ -125,16 +125,13 @@ void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pair
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
                         uint64_t *work, int64_t work_cap, Counters *cnt, hipStream_t st);
 void launch_prim_cand(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
-                      const double *patch_box, const uint64_t *work, int64_t work_cap, double h, Cand *cand,
-                      int64_t cand_cap, Counters *cnt, hipStream_t st);
+                      const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
+                      int64_t list_cap, Counters *cnt, hipStream_t st);
 
-// K3 + K4: screen (exact box test + one Bernstein test), then root search
-void launch_narrow_screen(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *pre,
-                          int64_t pre_cap, double d, int32_t *hard, int64_t hard_cap, Cand *list, int64_t list_cap,
-                          Counters *cnt, hipStream_t st);
-void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *pre, const int32_t *hard,
-                   int64_t hard_cap, double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol,
-                   double *ct_grad, int64_t ct_cap, Counters *cnt, hipStream_t st);
+// K3 + K4: root search on the queued candidates, volumes and gradients
+void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
+                   double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
+                   int64_t ct_cap, Counters *cnt, hipStream_t st);
 
 // K5
 void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st);

@@ -65,7 +65,7 @@ struct stiv_ctx {
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
       row_off, row_vtx, row_g, sort_tk, sort_tv;
-  int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0;
+  int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0, cap_list = 0;
   Counters *h_cnt = nullptr;  // pinned
   // last structurally validated scene (pointers + sizes); see check_structure
   const void *val_ptr[4] = {};
@@ -316,7 +316,7 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   if (ctx->cap_cp == 0) ctx->cap_cp = std::max<int64_t>(64 * N, 4096);
   if (ctx->cap_pairs == 0) ctx->cap_pairs = std::max<int64_t>(16 * N, 4096);
   if (ctx->cap_work == 0) ctx->cap_work = std::max<int64_t>(64 * ctx->cap_pairs, 1 << 16);
-  if (ctx->cap_cand == 0) ctx->cap_cand = std::max<int64_t>(16 * ctx->cap_work, 1 << 20);
+  if (ctx->cap_cand == 0) ctx->cap_cand = std::max<int64_t>(4 * ctx->cap_work, 1 << 20);
   if (ctx->cap_ct == 0) ctx->cap_ct = std::max<int64_t>(ctx->cap_cand / 8, 1 << 18);
   ctx->cap_patch = N * std::max(ctx->max_patches, 1);
   const int64_t hash_cap = pow2_at_least(4 * ctx->cap_pairs);
@@ -342,7 +342,6 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->patch_box, 6 * 8 * (ctx->cap_patch + 1)));
   HIPCHK(ensure(ctx->work, 8 * ctx->cap_work));
   HIPCHK(ensure(ctx->cand, sizeof(Cand) * ctx->cap_cand));
-  HIPCHK(ensure(ctx->hard, sizeof(int32_t) * ctx->cap_cand));
   HIPCHK(ensure(ctx->ct, sizeof(Cand) * ctx->cap_ct));
   HIPCHK(ensure(ctx->ct_s, 8 * ctx->cap_ct));
   HIPCHK(ensure(ctx->ct_vol, 8 * ctx->cap_ct));
@@ -471,16 +470,15 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                      P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<uint64_t>(ctx->work),
                      ctx->cap_work, cnt, st);
   hipEventRecord(ctx->ev[3], st);
-  launch_prim_cand(S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box),
-                   P<uint64_t>(ctx->work), ctx->cap_work, h, P<Cand>(ctx->cand), ctx->cap_cand, cnt, st);
-  hipEventRecord(ctx->ev[4], st);
-  // ---- K3 + K4 narrow phase (exact box test, screen, root search), volumes and gradients
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
-  launch_narrow_screen(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, P<int32_t>(ctx->hard),
-                       ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr, emit ? ctx->cap_cand : 0, cnt, st);
-  launch_narrow(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), P<int32_t>(ctx->hard), ctx->cap_cand, p->d,
-                p->eps, p->dt, P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol),
-                P<double>(ctx->ct_grad), ctx->cap_ct, cnt, st);
+  launch_prim_cand(S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<uint64_t>(ctx->work),
+                   ctx->cap_work, p->d, P<Cand>(ctx->cand), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
+                   emit ? ctx->cap_list : 0, cnt, st);
+  hipEventRecord(ctx->ev[4], st);
+  // ---- K3 + K4 root search, volumes and gradients
+  launch_narrow(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps, p->dt,
+                P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
+                cnt, st);
   hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
   launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
@@ -528,7 +526,10 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
   for (int attempt = 0; attempt < 4; ++attempt) {
     stiv_status sa = arena(ctx, s);
     if (sa != STIV_OK) return sa;
-    if (p->flags & STIV_EMIT_CANDIDATES) HIPCHK(ensure(ctx->cand_list, sizeof(Cand) * ctx->cap_cand));
+    if (p->flags & STIV_EMIT_CANDIDATES) {
+      if (ctx->cap_list == 0) ctx->cap_list = 4 * ctx->cap_cand;
+      HIPCHK(ensure(ctx->cand_list, sizeof(Cand) * ctx->cap_list));
+    }
     run_pipeline(ctx, S, p, out, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -545,7 +546,11 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
       grow = true;
     }
     if ((int64_t)c.n_work > ctx->cap_work) { ctx->cap_work = (int64_t)c.n_work + c.n_work / 4 + 1024; grow = true; }
-    if ((int64_t)c.n_pre > ctx->cap_cand) { ctx->cap_cand = (int64_t)c.n_pre + c.n_pre / 4 + 1024; grow = true; }
+    if ((int64_t)c.n_hard > ctx->cap_cand) { ctx->cap_cand = (int64_t)c.n_hard + c.n_hard / 4 + 1024; grow = true; }
+    if ((p->flags & STIV_EMIT_CANDIDATES) && (int64_t)c.n_cand_list > ctx->cap_list) {
+      ctx->cap_list = (int64_t)c.n_cand_list + c.n_cand_list / 4 + 1024;
+      grow = true;
+    }
     if ((int64_t)c.n_ct > ctx->cap_ct) { ctx->cap_ct = (int64_t)c.n_ct + c.n_ct / 4 + 1024; grow = true; }
     if (grow) continue;
     out->n_pairs = (int64_t)c.n_pairs;
