@@ -138,6 +138,11 @@ stiv_status stiv_destroy(stiv_ctx *ctx);
  * (groups of neighbouring triangles with their owned vertices and edges). */
 stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *topo);
 
+/* Triangles per patch of the primitive broad phase: 16, 32 or 64 (default
+ * 64).  Changing it discards the topology tiling, so call stiv_set_topology
+ * afterwards.  Results do not depend on it; speed does (see the autotuner). */
+stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch);
+
 /* Pre-size the scratch arena for scenes of this shape (optional; detect
  * grows it on demand). */
 stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p);

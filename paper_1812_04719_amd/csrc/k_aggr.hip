@@ -76,6 +76,8 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
   __shared__ uint64_t skey[kLdsSort];
   __shared__ int32_t sidx[kLdsSort];
   __shared__ int s_nvt;
+  __shared__ double s_part[kAggThreads];
+  __shared__ int s_cnt[kAggThreads];
   int64_t np = (int64_t)cnt->n_pairs;
   np = np < pairs_cap ? np : pairs_cap;
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
@@ -123,20 +125,26 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
     }
     __syncthreads();
     const int nvt = s_nvt;  // VT contacts come first (kind 0, 1 before 2)
-    // ---- V = sum of V_k in canonical order
-    if (threadIdx.x == 0) {
-      double V = 0.0;
-      for (int k = 0; k < nvt; ++k) V += ct_vol[idx[k]];
-      pair_V[p] = V;
-      pair_hasvt[p] = nvt > 0;
-    }
-    // keep the sorted contact order of the VT contacts before reusing the buffer
-    __syncthreads();
-    if (nvt == 0) {
-      if (threadIdx.x == 0) pair_rows[p] = 0;
+    // ---- V = sum of V_k: each thread adds a contiguous run of the sorted VT
+    // contacts, then the partial sums are added in thread order (a fixed
+    // order, so repeated runs give the same bits)
+    {
+      const int chunk = (nvt + kAggThreads - 1) / kAggThreads;
+      const int lo = threadIdx.x * chunk, hi = min(nvt, lo + chunk);
+      double part = 0.0;
+      for (int k = lo; k < hi; ++k) part += ct_vol[idx[k]];
+      s_part[threadIdx.x] = part;
       __syncthreads();
-      continue;
+      if (threadIdx.x == 0) {
+        double V = 0.0;
+        for (int k = 0; k < kAggThreads; ++k) V += s_part[k];
+        pair_V[p] = V;
+        pair_hasvt[p] = nvt > 0;
+        if (nvt == 0) pair_rows[p] = 0;
+      }
+      __syncthreads();
     }
+    if (nvt == 0) continue;
     // ---- J rows: 4 contributions per VT contact keyed by (global vertex, order)
     const PairRec pr = pairs[p];
     const int nj = 4 * nvt;
@@ -176,28 +184,40 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
     __threadfence_block();
     __syncthreads();
     bitonic(jkey, jidx, nj2);
-    if (threadIdx.x == 0) {
-      int rows = 0;
-      int e = 0;
-      while (e < nj) {
+    // segments of equal vertex: each thread owns a contiguous chunk of entries,
+    // counts the segment starts in it, and after a scan of those counts writes
+    // the rows that start in its chunk (adding the segment in entry order)
+    {
+      const int chunk = (nj + kAggThreads - 1) / kAggThreads;
+      const int lo = threadIdx.x * chunk, hi = min(nj, lo + chunk);
+      int starts = 0;
+      for (int e = lo; e < hi; ++e) starts += (e == 0 || (jkey[e] >> 24) != (jkey[e - 1] >> 24));
+      s_cnt[threadIdx.x] = starts;
+      __syncthreads();
+      for (int offs = 1; offs < kAggThreads; offs <<= 1) {
+        const int add = threadIdx.x >= offs ? s_cnt[threadIdx.x - offs] : 0;
+        __syncthreads();
+        s_cnt[threadIdx.x] += add;
+        __syncthreads();
+      }
+      int row = s_cnt[threadIdx.x] - starts;
+      for (int e = lo; e < hi; ++e) {
         const uint64_t gv = jkey[e] >> 24;
+        if (!(e == 0 || gv != (jkey[e - 1] >> 24))) continue;
         double g[3] = {0.0, 0.0, 0.0};
-        int f = e;
-        while (f < nj && (jkey[f] >> 24) == gv) {
+        for (int f = e; f < nj && (jkey[f] >> 24) == gv; ++f) {
           const int32_t c4 = jidx[f];
           const int64_t c = c4 >> 2;
           const int role = c4 & 3;
           for (int q = 0; q < 3; ++q) g[q] += ct_grad[12 * c + 3 * role + q];
-          ++f;
         }
-        row_vtx_tmp[4 * off + rows] = (int32_t)gv;
-        for (int q = 0; q < 3; ++q) row_g_tmp[3 * (4 * off + rows) + q] = g[q];
-        ++rows;
-        e = f;
+        row_vtx_tmp[4 * off + row] = (int32_t)gv;
+        for (int q = 0; q < 3; ++q) row_g_tmp[3 * (4 * off + row) + q] = g[q];
+        ++row;
       }
-      pair_rows[p] = rows;
+      if (threadIdx.x == kAggThreads - 1) pair_rows[p] = s_cnt[kAggThreads - 1];
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 

@@ -5,8 +5,8 @@
 // FP64 box is bit-identical to any other correct evaluation.  Patch boxes
 // (the same over the vertices referenced by a patch's triangles) feed the
 // primitive broad phase.  One workgroup streams one vesicle's SoA positions
-// with coalesced 8-byte lanes; this is the one stage that reads every byte
-// of X0 and X1.
+// with coalesced 8-byte lanes, once; this is the one stage that reads every
+// byte of X0 and X1.
 #include "stiv_common.h"
 
 namespace stiv {
@@ -22,8 +22,24 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// Order-preserving map of doubles to unsigned 64-bit keys (for exact
+// min/max with integer LDS atomics); finite inputs only.
+__device__ inline unsigned long long okey(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline double okey_inv(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+// One workgroup per vesicle: each thread streams vertices (coalesced SoA
+// loads of X0 and X1), folds them into the vesicle box and, through the
+// vertex -> patch incidence lists, into the LDS boxes of the patches that
+// reference the vertex.
 __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, const int64_t *ves_patch_off,
                                                double *ves_box, double *patch_box, Counters *cnt) {
+  __shared__ unsigned long long pk[kMaxPatchesPerVes][6];  // lo as key, hi as key
   __shared__ double red[4][6];
   __shared__ int bad_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -31,16 +47,32 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
   for (int v = blockIdx.x; v < S.n_ves; v += gridDim.x) {
     const int base = S.vtx_off[v];
     const int nvv = S.vtx_off[v + 1] - base;
+    const int t = S.topo_id[v];
+    const int np = T.patch_off[t + 1] - T.patch_off[t];
+    const int vb = T.vbase[t];
+    for (int k = threadIdx.x; k < np; k += blockDim.x)
+      for (int c = 0; c < 3; ++c) { pk[k][c] = ~0ull; pk[k][3 + c] = 0ull; }
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
     double lo[3], hi[3];
     for (int c = 0; c < 3; ++c) { lo[c] = INFINITY; hi[c] = -INFINITY; }
     int bad = 0;
-    if (threadIdx.x == 0) bad_any = 0;
     for (int i = threadIdx.x; i < nvv; i += blockDim.x) {
+      double l[3], u[3];
       for (int c = 0; c < 3; ++c) {
-        double a = S.x0[c * nv_all + base + i], b = S.x1[c * nv_all + base + i];
+        const double a = S.x0[c * nv_all + base + i], b = S.x1[c * nv_all + base + i];
         bad |= !(isfinite(a) && isfinite(b));
-        lo[c] = fmin(lo[c], fmin(a, b));
-        hi[c] = fmax(hi[c], fmax(a, b));
+        l[c] = fmin(a, b);
+        u[c] = fmax(a, b);
+        lo[c] = fmin(lo[c], l[c]);
+        hi[c] = fmax(hi[c], u[c]);
+      }
+      for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) {
+        const int q = T.vp[e];
+        for (int c = 0; c < 3; ++c) {
+          atomicMin(&pk[q][c], okey(l[c]));
+          atomicMax(&pk[q][3 + c], okey(u[c]));
+        }
       }
     }
     for (int c = 0; c < 3; ++c) {
@@ -49,7 +81,6 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
     }
     if (lane == 0)
       for (int c = 0; c < 3; ++c) { red[wave][c] = lo[c]; red[wave][3 + c] = hi[c]; }
-    __syncthreads();
     if (bad) atomicOr(&bad_any, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -61,32 +92,13 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
       }
       if (bad_any) atomicAdd(&cnt->nonfinite, 1ull);
     }
-    // patch boxes: one wave per patch
-    const int t = S.topo_id[v];
-    const int p0 = T.patch_off[t], p1 = T.patch_off[t + 1];
     const int64_t slot0 = ves_patch_off[v];
-    for (int k = wave; k < p1 - p0; k += 4) {
-      const int P = p0 + k;
-      double pl[3], ph[3];
-      for (int c = 0; c < 3; ++c) { pl[c] = INFINITY; ph[c] = -INFINITY; }
-      for (int r = T.pref_off[P] + lane; r < T.pref_off[P + 1]; r += 64) {
-        const int64_t g = base + T.pref[r];
+    if (!bad_any)
+      for (int k = threadIdx.x; k < np; k += blockDim.x)
         for (int c = 0; c < 3; ++c) {
-          double a = S.x0[c * nv_all + g], b = S.x1[c * nv_all + g];
-          pl[c] = fmin(pl[c], fmin(a, b));
-          ph[c] = fmax(ph[c], fmax(a, b));
+          patch_box[6 * (slot0 + k) + c] = okey_inv(pk[k][c]) - h;
+          patch_box[6 * (slot0 + k) + 3 + c] = okey_inv(pk[k][3 + c]) + h;
         }
-      }
-      for (int c = 0; c < 3; ++c) {
-        pl[c] = wave_min(pl[c]);
-        ph[c] = wave_max(ph[c]);
-      }
-      if (lane == 0)
-        for (int c = 0; c < 3; ++c) {
-          patch_box[6 * (slot0 + k) + c] = pl[c] - h;
-          patch_box[6 * (slot0 + k) + 3 + c] = ph[c] + h;
-        }
-    }
     __syncthreads();
   }
 }

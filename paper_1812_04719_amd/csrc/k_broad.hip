@@ -55,6 +55,14 @@ __device__ void hash_insert(uint64_t key, uint64_t *hash, int64_t cap, uint64_t 
                             Counters *cnt) {
   uint64_t h = mix64(key) & (uint64_t)(cap - 1);
   for (int64_t probe = 0; probe < cap; ++probe) {
+    // most insertions repeat a pair already present: look before the atomic
+    const uint64_t seen = __hip_atomic_load((unsigned long long *)&hash[h], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (seen == key) return;
+    if (seen != kEmpty) {
+      h = (h + 1) & (uint64_t)(cap - 1);
+      continue;
+    }
     uint64_t prev = atomicCAS((unsigned long long *)&hash[h], (unsigned long long)kEmpty,
                               (unsigned long long)key);
     if (prev == kEmpty) {

@@ -41,15 +41,29 @@ __device__ inline unsigned long long wave_append(bool want, unsigned long long *
 }
 
 constexpr int kPPThreads = 256;
+constexpr int kPPBuf = 1024;
 
+__device__ inline bool ov6f_(const float *A, const float *B) {
+  return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
+}
+
+// One workgroup per vesicle pair.  Each side's patch boxes that meet the
+// other vesicle's box are staged in LDS as FP32 boxes rounded outward (a
+// conservative filter: the primitive kernel applies the exact test later),
+// the surviving patch pairs are tested, and the work items are buffered in
+// LDS and written with one atomic per flush.
 __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo T, const PairRec *pairs,
                                                             const double *ves_box, const int64_t *ves_patch_off,
                                                             const double *patch_box, uint64_t *work,
                                                             int64_t work_cap, Counters *cnt, int64_t pairs_cap) {
-  __shared__ int sA[kMaxPatchesPerVes], sB[kMaxPatchesPerVes];
-  __shared__ int nA, nB;
+  __shared__ float bA[kMaxPatchesPerVes][6], bB[kMaxPatchesPerVes][6];
+  __shared__ short iA[kMaxPatchesPerVes], iB[kMaxPatchesPerVes];
+  __shared__ uint64_t buf[kPPBuf];
+  __shared__ int nA, nB, nbuf;
+  __shared__ unsigned long long base_sh;
   int64_t np = (int64_t)cnt->n_pairs;
   np = np < pairs_cap ? np : pairs_cap;
+  if (threadIdx.x == 0) nbuf = 0;
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     const PairRec pr = pairs[p];
     double boxA[6], boxB[6];
@@ -64,35 +78,59 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
     __syncthreads();
     for (int k = threadIdx.x; k < na; k += blockDim.x) {
       const double *P = patch_box + 6 * (pa0 + k);
-      if (ov6(P, boxB)) sA[atomicAdd(&nA, 1)] = k;
+      if (ov6(P, boxB)) {
+        const int q = atomicAdd(&nA, 1);
+        for (int c = 0; c < 3; ++c) {
+          bA[q][c] = __double2float_rd(P[c]);
+          bA[q][3 + c] = __double2float_ru(P[3 + c]);
+        }
+        iA[q] = (short)k;
+      }
     }
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
       const double *P = patch_box + 6 * (pb0 + k);
       double Q[6];
       for (int c = 0; c < 3; ++c) { Q[c] = P[c] + pr.sh[c]; Q[3 + c] = P[3 + c] + pr.sh[c]; }
-      if (ov6(Q, boxA)) sB[atomicAdd(&nB, 1)] = k;
+      if (ov6(Q, boxA)) {
+        const int q = atomicAdd(&nB, 1);
+        for (int c = 0; c < 3; ++c) {
+          bB[q][c] = __double2float_rd(Q[c]);
+          bB[q][3 + c] = __double2float_ru(Q[3 + c]);
+        }
+        iB[q] = (short)k;
+      }
     }
     __syncthreads();
     const int ma = nA, mb = nB;
     const int tot = ma * mb;
-    for (int base = 0; base < tot; base += blockDim.x) {
-      const int t = base + threadIdx.x;
-      bool hit = false;
-      int ia = 0, ib = 0;
+    for (int t0 = 0; t0 < tot; t0 += blockDim.x) {
+      const int t = t0 + threadIdx.x;
       if (t < tot) {
-        ia = sA[t / mb];
-        ib = sB[t % mb];
-        const double *P = patch_box + 6 * (pa0 + ia);
-        const double *Qr = patch_box + 6 * (pb0 + ib);
-        double Q[6];
-        for (int c = 0; c < 3; ++c) { Q[c] = Qr[c] + pr.sh[c]; Q[3 + c] = Qr[3 + c] + pr.sh[c]; }
-        hit = ov6(P, Q);
+        const int x = t / mb, y = t - x * mb;
+        if (ov6f_(bA[x], bB[y])) {
+          const int q = atomicAdd(&nbuf, 1);
+          buf[q] = ((uint64_t)p << 32) | ((uint64_t)(uint16_t)iA[x] << 16) | (uint64_t)(uint16_t)iB[y];
+        }
       }
-      const unsigned long long slot = wave_append(hit, &cnt->n_work);
-      if (hit && (int64_t)slot < work_cap)
-        work[slot] = ((uint64_t)p << 32) | ((uint64_t)ia << 16) | (uint64_t)ib;
+      __syncthreads();
+      if (nbuf > kPPBuf - kPPThreads) {  // flush
+        if (threadIdx.x == 0) base_sh = atomicAdd(&cnt->n_work, (unsigned long long)nbuf);
+        __syncthreads();
+        for (int k = threadIdx.x; k < nbuf; k += blockDim.x)
+          if ((int64_t)(base_sh + k) < work_cap) work[base_sh + k] = buf[k];
+        __syncthreads();
+        if (threadIdx.x == 0) nbuf = 0;
+        __syncthreads();
+      }
     }
     __syncthreads();
+  }
+  __syncthreads();
+  if (nbuf > 0) {
+    if (threadIdx.x == 0) base_sh = atomicAdd(&cnt->n_work, (unsigned long long)nbuf);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nbuf; k += blockDim.x)
+      if ((int64_t)(base_sh + k) < work_cap) work[base_sh + k] = buf[k];
   }
 }
 
@@ -113,13 +151,17 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 // --------------------------------------------------------------------------
 constexpr int kHitBuf = 256;
 
+template <int TILE>
 struct WaveLds {
-  double pos[2][kMaxPatchRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
-  float rbox[kMaxPatchOwnE][6];    // right-hand list of the current kind: FP32 boxes
-  int rk[kMaxPatchOwnE];           //   and patch-table indices
-  int lk[kMaxPatchOwnE];           // left-hand list: patch-table indices
-  int nl, nr, nh;
-  int4 hits[kHitBuf];              // (kind, left index, right index, -)
+  static constexpr int kRef = TileCaps<TILE>::ref;
+  static constexpr int kL = TileCaps<TILE>::owne > TileCaps<TILE>::ownv ? TileCaps<TILE>::owne : TileCaps<TILE>::ownv;
+  static constexpr int kR = TileCaps<TILE>::owne > TILE ? TileCaps<TILE>::owne : TILE;
+  double pos[2][kRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
+  float lbox[kL][6];       // left-hand list of the current kind: FP32 boxes
+  float rbox[kR][6];       // right-hand list
+  int lk[kL];              // patch-table indices of the left-hand list
+  int rk[kR];              // and of the right-hand list
+  int4 hits[kHitBuf];      // (kind, left index, right index, -)
 };
 
 __device__ inline bool ov6f(const float *A, const float *B) {
@@ -159,13 +201,13 @@ __device__ inline float wave_maxf(float v) {
 
 // Exact FP64 box test of a buffered hit and the polynomial screen; queue the
 // candidates that need a root search.  All 64 lanes take part.
-template <int N>
-__device__ void process_hits(WaveLds &W, const DevTopo &T, const PairRec &pr, int p, const int P[2], double d,
+template <int N, int TILE>
+__device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &pr, int p, const int P[2], double d,
                              Cand *hard, int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt,
-                             unsigned long long &nvt, unsigned long long &nee) {
+                             unsigned long long &nvt, unsigned long long &nee, int nh) {
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
-  const int nh = *(volatile int *)&W.nh;
+  __syncthreads();
   for (int r0 = 0; r0 < nh; r0 += 64) {
     const int k = r0 + lane;
     bool is_cand = false, need = false;
@@ -250,27 +292,21 @@ __device__ void process_hits(WaveLds &W, const DevTopo &T, const PairRec &pr, in
       }
     }
   }
-  __syncthreads();
-  if (lane == 0) {
-    W.nh = 0;
-    if (nh) atomicAdd(&cnt->n_pre, (unsigned long long)nh);
-  }
+  if (lane == 0 && nh) atomicAdd(&cnt->n_pre, (unsigned long long)nh);
   __syncthreads();
 }
 
-template <int N>
+template <int N, int TILE>
 __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const PairRec *pairs,
                                                   const int64_t *ves_patch_off, const uint64_t *work,
                                                   int64_t work_cap, double d, Cand *hard, int64_t hard_cap,
                                                   Cand *list, int64_t list_cap, Counters *cnt) {
-  __shared__ WaveLds W;
+  __shared__ WaveLds<TILE> W;
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
   unsigned long long nvt = 0, nee = 0;
-  if (lane == 0) W.nh = 0;
-  __syncthreads();
   for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
     const uint64_t wr = work[w];
     const int p = (int)(wr >> 32);
@@ -305,6 +341,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
       }
     }
     __syncthreads();
+    int nh = 0;  // buffered hits (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
       const int lbeg = kind == 2 ? T.pedge_off[P[sl]] : T.pvtx_off[P[sl]];
@@ -316,43 +353,68 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
       const uint8_t *rslot = kind == 2 ? T.pedge_slot : T.ptri_slot;
       const int rnv = kind == 2 ? 2 : 3;
       const double *shl = sl ? pr.sh : zero, *shr = sr ? pr.sh : zero;
-      if (lane == 0) { W.nl = 0; W.nr = 0; }
-      __syncthreads();
-      for (int k = lbeg + lane; k < lend; k += 64) {
+      // compact the primitives whose box meets the other patch's box (ballot + prefix count)
+      int nl = 0, nr = 0;
+      for (int k0 = lbeg; k0 < lend; k0 += 64) {
+        const int k = k0 + lane;
         float bx[6];
-        prim_box32(W.pos[sl], lslot + (int64_t)lnv * k, lnv, h, shl, bx);
-        if (ov6f(bx, pb[sr])) W.lk[atomicAdd(&W.nl, 1)] = k;
+        bool keep = false;
+        if (k < lend) {
+          prim_box32(W.pos[sl], lslot + (int64_t)lnv * k, lnv, h, shl, bx);
+          keep = ov6f(bx, pb[sr]);
+        }
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+          const int q = nl + __popcll(m & lanemask_lt());
+#pragma unroll
+          for (int c = 0; c < 6; ++c) W.lbox[q][c] = bx[c];
+          W.lk[q] = k;
+        }
+        nl += __popcll(m);
       }
-      for (int k = rbeg + lane; k < rend; k += 64) {
+      for (int k0 = rbeg; k0 < rend; k0 += 64) {
+        const int k = k0 + lane;
         float bx[6];
-        prim_box32(W.pos[sr], rslot + (int64_t)rnv * k, rnv, h, shr, bx);
-        if (ov6f(bx, pb[sl])) {
-          const int q = atomicAdd(&W.nr, 1);
+        bool keep = false;
+        if (k < rend) {
+          prim_box32(W.pos[sr], rslot + (int64_t)rnv * k, rnv, h, shr, bx);
+          keep = ov6f(bx, pb[sl]);
+        }
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+          const int q = nr + __popcll(m & lanemask_lt());
 #pragma unroll
           for (int c = 0; c < 6; ++c) W.rbox[q][c] = bx[c];
           W.rk[q] = k;
         }
+        nr += __popcll(m);
       }
       __syncthreads();
-      const int nl = W.nl, nr = W.nr;
-      for (int l0 = 0; l0 < nl; l0 += 64) {
-        const bool act = l0 + lane < nl;
-        float lb[6];
-        int kl = 0;
-        if (act) {
-          kl = W.lk[l0 + lane];
-          prim_box32(W.pos[sl], lslot + (int64_t)lnv * kl, lnv, h, shl, lb);
+      // all left x right pairs, 64 per round; t = x * nr + y, with x = t / nr
+      // as (t * ceil(2^32 / nr)) >> 32, exact for t < 2^16 (t <= 128 * 128 here)
+      const int tot = nl * nr;
+      const unsigned long long magic = nr ? ((1ull << 32) + (unsigned long long)nr - 1ull) / (unsigned long long)nr : 0ull;
+      for (int t0 = 0; t0 < tot; t0 += 64) {
+        const unsigned int t = (unsigned int)(t0 + lane);
+        bool hit = false;
+        int x = 0, y = 0;
+        if ((int)t < tot) {
+          x = (int)(((unsigned long long)t * magic) >> 32);
+          y = (int)t - x * nr;
+          hit = ov6f(W.lbox[x], W.rbox[y]);
         }
-        for (int j = 0; j < nr; ++j) {
-          if (*(volatile int *)&W.nh > kHitBuf - 64)
-            process_hits<N>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee);
-          if (act && ov6f(lb, W.rbox[j])) W.hits[atomicAdd(&W.nh, 1)] = make_int4(kind, kl, W.rk[j], 0);
+        const unsigned long long m = __ballot(hit);
+        if (hit) W.hits[nh + __popcll(m & lanemask_lt())] = make_int4(kind, W.lk[x], W.rk[y], 0);
+        nh += __popcll(m);
+        if (nh > kHitBuf - 64) {
+          process_hits<N, TILE>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+          nh = 0;
         }
       }
       __syncthreads();
     }
     // the buffered hits refer to this work item's LDS positions: finish them now
-    process_hits<N>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee);
+    if (nh) process_hits<N, TILE>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee, nh);
   }
   for (int off = 32; off > 0; off >>= 1) {
     nvt += __shfl_xor(nvt, off, 64);
@@ -373,15 +435,27 @@ void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pair
                                              pairs_cap);
 }
 
-void launch_prim_cand(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
-                      const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
-                      int64_t list_cap, Counters *cnt, hipStream_t st) {
+template <int TILE>
+static void launch_tile(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
+                        const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
+                        int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (d == 0.0)
-    k_prim_cand<3><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
-                                        list_cap, cnt);
+    k_prim_cand<3, TILE><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
+                                              list_cap, cnt);
   else
-    k_prim_cand<6><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
-                                        list_cap, cnt);
+    k_prim_cand<6, TILE><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
+                                              list_cap, cnt);
+}
+
+void launch_prim_cand(int tile, const DevScene &S, const DevTopo &T, const PairRec *pairs,
+                      const int64_t *ves_patch_off, const uint64_t *work, int64_t work_cap, double d, Cand *hard,
+                      int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st) {
+  if (tile <= 16)
+    launch_tile<16>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+  else if (tile <= 32)
+    launch_tile<32>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+  else
+    launch_tile<64>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
 }
 
 }  // namespace stiv

@@ -12,10 +12,25 @@ namespace stiv {
 // mesh is owned by exactly one patch), so a (patch, patch) work item yields
 // every primitive pair exactly once.
 // ---------------------------------------------------------------------------
-constexpr int kMaxPatchTri = 64;   // triangles per patch
-constexpr int kMaxPatchRef = 128;  // distinct vertices referenced by a patch's triangles
-constexpr int kMaxPatchOwnV = 128; // owned vertices per patch
-constexpr int kMaxPatchOwnE = 192; // owned edges per patch
+// Patch sizes (triangles per patch) the kernels are built for, and the LDS
+// capacities each size needs.  The host tiling stops growing a patch before
+// any capacity would be exceeded.
+template <int TILE>
+struct TileCaps;
+template <>
+struct TileCaps<16> {
+  static constexpr int ref = 24, ownv = 24, owne = 40;
+};
+template <>
+struct TileCaps<32> {
+  static constexpr int ref = 40, ownv = 40, owne = 64;
+};
+template <>
+struct TileCaps<64> {
+  static constexpr int ref = 64, ownv = 64, owne = 128;
+};
+constexpr int kMaxPatchTri = 64;   // largest supported patch
+constexpr int kMaxPatchRef = 64;
 constexpr int kMaxPatchesPerVes = 1024;
 constexpr int kMaxShift = 7;       // |sigma_c| bound for periodic images (pair key packing)
 
@@ -36,6 +51,8 @@ struct DevTopo {
   const int *pedge_off, *pedge;        // owned edges (edge ids)
   const uint8_t *pedge_slot;           // [..][2]
   const int *pref_off, *pref;          // referenced vertices (local ids)
+  const int *vbase;                    // [n_topo] first row of each topology in vp_off
+  const int *vp_off, *vp;              // vertex -> patches (local patch index) referencing it
 };
 
 struct DevScene {
@@ -124,9 +141,9 @@ void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
                         uint64_t *work, int64_t work_cap, Counters *cnt, hipStream_t st);
-void launch_prim_cand(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
-                      const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
-                      int64_t list_cap, Counters *cnt, hipStream_t st);
+void launch_prim_cand(int tile, const DevScene &S, const DevTopo &T, const PairRec *pairs,
+                      const int64_t *ves_patch_off, const uint64_t *work, int64_t work_cap, double d, Cand *hard,
+                      int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st);
 
 // K3 + K4: root search on the queued candidates, volumes and gradients
 void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,

@@ -55,10 +55,12 @@ struct stiv_ctx {
   bool have_topo = false;
   // topology (device)
   Buf t_nv, t_nt, t_ne, t_tri_off, t_edge_off, t_tri, t_edge, t_patch_off, t_ptri_off, t_ptri, t_ptri_slot,
-      t_pvtx_off, t_pvtx, t_pvtx_slot, t_pedge_off, t_pedge, t_pedge_slot, t_pref_off, t_pref;
+      t_pvtx_off, t_pvtx, t_pvtx_slot, t_pedge_off, t_pedge, t_pedge_slot, t_pref_off, t_pref, t_vbase, t_vp_off,
+      t_vp;
   DevTopo topo{};
   std::vector<int> h_npatch;  // patches per topology
   int max_patches = 0;
+  int tile = 64;  // triangles per patch (16, 32 or 64)
   // arena
   Buf counters, ves_box, ves_scene, grid, cp_cnt, cp_off, cp_keys, cp_vals, cp_tk, cp_tv, hash, uniq, sorted,
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
@@ -127,7 +129,7 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
   Buf *all[] = {&ctx->t_nv, &ctx->t_nt, &ctx->t_ne, &ctx->t_tri_off, &ctx->t_edge_off, &ctx->t_tri, &ctx->t_edge,
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
-                &ctx->t_pref_off, &ctx->t_pref, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
@@ -162,6 +164,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   std::vector<int> patch_off(1, 0), ptri_off(1, 0), ptri, pvtx_off(1, 0), pvtx, pedge_off(1, 0), pedge,
       pref_off(1, 0), pref;
   std::vector<uint8_t> ptri_slot, pvtx_slot, pedge_slot;
+  std::vector<int> vbase, vp_off(1, 0), vp;
   ctx->h_npatch.assign(nt_topo, 0);
   ctx->max_patches = 0;
   for (int t = 0; t < nt_topo; ++t) {
@@ -196,25 +199,33 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
     for (int k = 0; k < 3 * NT; ++k) vref[T3[k]] = 1;
     for (int v = 0; v < NV; ++v)
       if (!vref[v]) return fail(ctx, STIV_E_ARG, "set_topology: vertex not on any triangle");
-    // greedy breadth-first patches of up to kMaxPatchTri neighbouring triangles
+    // greedy breadth-first patches of up to `tile` neighbouring triangles; a
+    // triangle is not added when the patch would exceed its vertex or edge
+    // capacity for this patch size
+    int cap_ref = TileCaps<64>::ref, cap_edge = TileCaps<64>::owne;
+    if (ctx->tile == 16) { cap_ref = TileCaps<16>::ref; cap_edge = TileCaps<16>::owne; }
+    if (ctx->tile == 32) { cap_ref = TileCaps<32>::ref; cap_edge = TileCaps<32>::owne; }
     std::vector<int> tpatch(NT, -1);
     std::vector<std::vector<int>> patches;
     for (int seed = 0; seed < NT; ++seed) {
       if (tpatch[seed] >= 0) continue;
       std::vector<int> members, queue{seed};
-      std::vector<int> verts;
+      std::vector<int> verts, edges;
       size_t qh = 0;
       tpatch[seed] = (int)patches.size();
-      while (qh < queue.size() && (int)members.size() < kMaxPatchTri) {
+      while (qh < queue.size() && (int)members.size() < ctx->tile) {
         int k = queue[qh++];
-        std::vector<int> nv2 = verts;
-        for (int r = 0; r < 3; ++r)
+        std::vector<int> nv2 = verts, ne2 = edges;
+        for (int r = 0; r < 3; ++r) {
           if (std::find(nv2.begin(), nv2.end(), T3[3 * k + r]) == nv2.end()) nv2.push_back(T3[3 * k + r]);
-        if ((int)nv2.size() > kMaxPatchRef) {
+          if (std::find(ne2.begin(), ne2.end(), tri_edges[3 * k + r]) == ne2.end()) ne2.push_back(tri_edges[3 * k + r]);
+        }
+        if ((int)nv2.size() > cap_ref || (int)ne2.size() > cap_edge) {
           tpatch[k] = -1;
           continue;
         }
         verts.swap(nv2);
+        edges.swap(ne2);
         members.push_back(k);
         for (int r = 0; r < 3; ++r)
           for (int k2 : edge_tris[tri_edges[3 * k + r]])
@@ -231,6 +242,22 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
     if (np > kMaxPatchesPerVes) return fail(ctx, STIV_E_ARG, "set_topology: mesh too large for the patch table");
     ctx->h_npatch[t] = np;
     ctx->max_patches = std::max(ctx->max_patches, np);
+    {
+      std::vector<std::vector<int>> vpl(NV);
+      for (int pi = 0; pi < np; ++pi)
+        for (int k : patches[pi])
+          for (int r = 0; r < 3; ++r) {
+            auto &l = vpl[T3[3 * k + r]];
+            if (l.empty() || l.back() != pi) l.push_back(pi);
+          }
+      vbase.push_back((int)vp_off.size() - 1);
+      for (int v = 0; v < NV; ++v) {
+        std::sort(vpl[v].begin(), vpl[v].end());
+        vpl[v].erase(std::unique(vpl[v].begin(), vpl[v].end()), vpl[v].end());
+        for (int q : vpl[v]) vp.push_back(q);
+        vp_off.push_back((int)vp.size());
+      }
+    }
     std::vector<char> vown(NV, 0), eown(NE, 0);
     for (int pi = 0; pi < np; ++pi) {
       const auto &mem = patches[pi];
@@ -266,7 +293,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
             ++nown_e;
           }
         }
-      if (nown_v > kMaxPatchOwnV || nown_e > kMaxPatchOwnE || (int)refs.size() > kMaxPatchRef)
+      if (nown_v > cap_ref || nown_e > cap_edge || (int)refs.size() > cap_ref)
         return fail(ctx, STIV_E_ARG, "set_topology: patch exceeds tile limits");
       pvtx_off.push_back((int)pvtx.size());
       pedge_off.push_back((int)pedge.size());
@@ -292,6 +319,9 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   HIPCHK(upload(ctx->t_pedge_slot, pedge_slot));
   HIPCHK(upload(ctx->t_pref_off, pref_off));
   HIPCHK(upload(ctx->t_pref, pref));
+  HIPCHK(upload(ctx->t_vbase, vbase));
+  HIPCHK(upload(ctx->t_vp_off, vp_off));
+  HIPCHK(upload(ctx->t_vp, vp));
   DevTopo &D = ctx->topo;
   D.n_topo = nt_topo;
   D.nv = P<int>(ctx->t_nv); D.nt = P<int>(ctx->t_nt); D.ne = P<int>(ctx->t_ne);
@@ -303,6 +333,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   D.pedge_off = P<int>(ctx->t_pedge_off); D.pedge = P<int>(ctx->t_pedge);
   D.pedge_slot = P<uint8_t>(ctx->t_pedge_slot);
   D.pref_off = P<int>(ctx->t_pref_off); D.pref = P<int>(ctx->t_pref);
+  D.vbase = P<int>(ctx->t_vbase); D.vp_off = P<int>(ctx->t_vp_off); D.vp = P<int>(ctx->t_vp);
   ctx->have_topo = true;
   return STIV_OK;
 }
@@ -471,7 +502,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                      ctx->cap_work, cnt, st);
   hipEventRecord(ctx->ev[3], st);
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
-  launch_prim_cand(S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<uint64_t>(ctx->work),
+  launch_prim_cand(ctx->tile, S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<uint64_t>(ctx->work),
                    ctx->cap_work, p->d, P<Cand>(ctx->cand), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
                    emit ? ctx->cap_list : 0, cnt, st);
   hipEventRecord(ctx->ev[4], st);
@@ -586,6 +617,17 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
 stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n) {
   if (!ctx || !ms) return STIV_E_ARG;
   for (int k = 0; k < n && k < 7; ++k) ms[k] = ctx->stage_ms[k];
+  return STIV_OK;
+}
+
+stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch) {
+  if (!ctx) return STIV_E_ARG;
+  if (tri_per_patch != 16 && tri_per_patch != 32 && tri_per_patch != 64)
+    return fail(ctx, STIV_E_ARG, "patch size must be 16, 32 or 64 triangles");
+  if (ctx->tile != tri_per_patch) {
+    ctx->tile = tri_per_patch;
+    ctx->have_topo = false;  // the tiling depends on the patch size: set the topology again
+  }
   return STIV_OK;
 }
 

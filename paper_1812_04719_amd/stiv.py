@@ -22,7 +22,7 @@ _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HI
            -5: "STIV_E_STATE"}
 
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
-           "stiv_get_stage_times", "stiv_get_stats", "stiv_sort_pairs_u64", "stiv_last_error")
+           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_sort_pairs_u64", "stiv_last_error")
 STAT_NAMES = ("check_points", "vesicle_pairs", "work_items", "pre_candidates", "candidates_vt", "candidates_ee",
               "root_searches", "contacts")
 
@@ -81,6 +81,7 @@ def lib():
                                       C.POINTER(stiv_result), C.c_void_p]
             L.stiv_get_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int]
             L.stiv_get_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int]
+            L.stiv_set_patch_size.argtypes = [C.c_void_p, C.c_int]
             L.stiv_sort_pairs_u64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
             L.stiv_last_error.argtypes = [C.c_void_p]
             L.stiv_last_error.restype = C.c_char_p
@@ -139,6 +140,10 @@ class Context:
                            edge_off.ctypes.data)
         self._check(lib().stiv_set_topology(self._h, C.byref(tp)))
         self._topo_key = key
+
+    def set_patch_size(self, tri_per_patch):
+        self._check(lib().stiv_set_patch_size(self._h, int(tri_per_patch)))
+        self._topo_key = None
 
     def stage_times(self):
         ms = (C.c_float * 7)()

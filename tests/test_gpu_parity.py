@@ -152,3 +152,17 @@ def test_capacity_retry(ctx):
     res, outs = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs)
     o = oracle.detect(sc)
     parity.compare(res, o, sc.dt, sc.eps)
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_patch_size_does_not_change_results(ctx, tile):
+    """The patch tiling is a performance choice: every size gives the oracle's sets."""
+    from paper_1812_04719_amd import stiv
+    sc = S.make_config(2)
+    ctx.set_patch_size(tile)
+    try:
+        g = run_gpu(ctx, sc, emit=True)
+    finally:
+        ctx.set_patch_size(64)
+    o = oracle.detect(sc, emit_candidates=True)
+    parity.compare(g, o, sc.dt, sc.eps, check_cand=True)
