@@ -153,6 +153,20 @@ stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *
 stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out,
                         void *stream);
 
+/* Backward pass (adjoint) of a detect.  `res` is the complete result of a
+ * stiv_detect on the same scene and parameters (its device arrays must be
+ * unchanged).  With cotangents dL_dV [n_vol] of the contact volumes and
+ * dL_dG [n_jrow][3] of the Jacobian rows (either may be NULL = zero), writes
+ * dL_dX0 and dL_dX1 [3][n_vtx] (overwritten; either may be NULL):
+ *   dL/dX = sum over VT contacts k of  gV grad V_k + H_k w,
+ * grad over X0 and X1 including the contact time's dependence on them
+ * (Eq. 3.1-3.2), H_k the Hessian of V_k, w the dL_dG rows of its vertices.
+ * Edge-edge contacts contribute nothing (they add nothing to V).  Enqueued
+ * on `stream`, no synchronisation.  Per-vertex sums are in a fixed order;
+ * a vertex in three or more contact volumes is summed with atomics. */
+stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
+                          const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, void *stream);
+
 /* Milliseconds of the last detect, measured with HIP events on the call's
  * stream: 0 box kernel, 1 vesicle broad phase (Morton grid), 2 patch-pair
  * cull, 3 primitive candidates, 4 narrow phase with volumes and gradients,

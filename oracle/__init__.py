@@ -72,6 +72,10 @@ def lib():
             L.oracle_roots01.restype = C.c_int
             L.oracle_roots01.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
             L.oracle_sort_scatter.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+            L.oracle_vt_grad_full.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
+                                              C.c_void_p, C.c_void_p, C.c_void_p]
+            L.oracle_vt_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
+                                             C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
             _lib = L
     return _lib
 
@@ -206,3 +210,28 @@ def sort_scatter(keys, idx):
     po = np.zeros_like(idx)
     lib().oracle_sort_scatter(keys.size, _ptr(keys), _ptr(idx), _ptr(ko), _ptr(po))
     return ko, po
+
+
+def vt_grad_full(x0, x1, s, d, eps, dt):
+    """(V, dV/dX0 [4,3], dV/dX1 [4,3]) of a vertex-triangle contact at parameter s."""
+    a = np.ascontiguousarray(x0, dtype=np.float64).reshape(12)
+    b = np.ascontiguousarray(x1, dtype=np.float64).reshape(12)
+    V = C.c_double(0.0)
+    g0 = np.zeros(12)
+    g1 = np.zeros(12)
+    lib().oracle_vt_grad_full(_ptr(a), _ptr(b), float(s), float(d), float(eps), float(dt), C.byref(V), _ptr(g0),
+                              _ptr(g1))
+    return V.value, g0.reshape(4, 3), g1.reshape(4, 3)
+
+
+def vt_backward(x0, x1, s, d, eps, dt, gV, w):
+    """Vector-Jacobian product of (V_k, dV_k/dX1) with cotangents (gV, w[4,3]):
+    returns (dL/dX0 [4,3], dL/dX1 [4,3]) by the complex-step method."""
+    a = np.ascontiguousarray(x0, dtype=np.float64).reshape(12)
+    b = np.ascontiguousarray(x1, dtype=np.float64).reshape(12)
+    ww = np.ascontiguousarray(w, dtype=np.float64).reshape(12)
+    g0 = np.zeros(12)
+    g1 = np.zeros(12)
+    lib().oracle_vt_backward(_ptr(a), _ptr(b), float(s), float(d), float(eps), float(dt), float(gV), _ptr(ww),
+                             _ptr(g0), _ptr(g1))
+    return g0.reshape(4, 3), g1.reshape(4, 3)

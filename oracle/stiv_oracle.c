@@ -37,6 +37,7 @@
  * into intervals where F is monotone; a sign change on such an interval holds
  * exactly one root, found by bisection to a width of 2^-50.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -873,5 +874,126 @@ void oracle_sort_scatter(int64_t n, const uint64_t *keys, const int64_t *idx, ui
     }
     keys_out[j + 1] = kk;
     perm_out[j + 1] = pk;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backward pass of one vertex-triangle contact by the complex-step method.  */
+/*                                                                            */
+/* V_k and its gradient with respect to X0 and X1 of (p, a, b, c) are        */
+/* written once in complex arithmetic.  Evaluating them at X1 + i h w (h =   */
+/* 1e-30), with the contact time s moved to the complex root of F by Newton  */
+/* steps, gives in the imaginary parts h times the directional derivative    */
+/* of the gradient along w, i.e. the Hessian of V_k applied to w, to machine  */
+/* precision (no subtractive cancellation).  The vector-Jacobian product of   */
+/* the pair (V_k, dV_k/dX1) with cotangents (gV, w) is then                   */
+/*   dL/dX = gV grad V_k + Im(grad V_k(X1 + i h w)) / h.                      */
+/* ------------------------------------------------------------------------ */
+typedef struct { double complex x, y, z; } c3;
+static c3 cmk(double complex x, double complex y, double complex z) { c3 r = {x, y, z}; return r; }
+static c3 cadd(c3 a, c3 b) { return cmk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static c3 csub(c3 a, c3 b) { return cmk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static c3 cscl(double complex s, c3 a) { return cmk(s * a.x, s * a.y, s * a.z); }
+static double complex cdot(c3 a, c3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static c3 ccross(c3 a, c3 b) {
+  return cmk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+/* F(s) and dF/ds for complex positions (vertex p, triangle a, b, c) */
+static void cF(const c3 X0[4], const c3 D[4], double complex s, double d, double complex *F, double complex *Fs) {
+  c3 P[4];
+  for (int k = 0; k < 4; ++k) P[k] = cadd(X0[k], cscl(s, D[k]));
+  c3 e1 = csub(P[2], P[1]), e2 = csub(P[3], P[1]), w = csub(P[0], P[1]);
+  c3 e1s = csub(D[2], D[1]), e2s = csub(D[3], D[1]), ws = csub(D[0], D[1]);
+  c3 n = ccross(e1, e2), ns = cadd(ccross(e1s, e2), ccross(e1, e2s));
+  double complex g = cdot(w, n), gs = cdot(ws, n) + cdot(w, ns);
+  if (d == 0.0) { *F = g; *Fs = gs; return; }
+  *F = g * g - d * d * cdot(n, n);
+  *Fs = 2.0 * g * gs - 2.0 * d * d * cdot(n, ns);
+}
+
+/* V, dV/dX0 (g0) and dV/dX1 (g1) in complex arithmetic at contact time s */
+static void cgrad(const c3 X0[4], const c3 X1[4], double complex s, double d, double eps, double dt, int clamped,
+                  double complex *V, double complex g0[12], double complex g1[12]) {
+  c3 D[4], P[4];
+  for (int k = 0; k < 4; ++k) { D[k] = csub(X1[k], X0[k]); P[k] = cadd(X0[k], cscl(s, D[k])); }
+  c3 e1 = csub(P[2], P[1]), e2 = csub(P[3], P[1]), w = csub(P[0], P[1]);
+  c3 e1s = csub(D[2], D[1]), e2s = csub(D[3], D[1]), ws = csub(D[0], D[1]);
+  c3 n = ccross(e1, e2);
+  double complex q = cdot(n, n);
+  c3 U = cscl(1.0 / dt, D[0]);
+  double complex un = cdot(U, n);
+  double complex R = csqrt(eps * eps * q + un * un);
+  *V = 0.5 * dt * (1.0 - s) * R;
+  c3 m = cscl(1.0 / R, cadd(cscl(eps * eps, n), cscl(un, U)));
+  double complex k = 0.5 * dt * (1.0 - s);
+  /* through U for p (dU/dX1 = 1/dt, dU/dX0 = -1/dt), through n for the triangle */
+  c3 tp = cscl(0.5 * (1.0 - s) * un / R, n);
+  c3 ta = cscl(k, ccross(csub(e1, e2), m)), tb = cscl(k, ccross(e2, m)), tc = cscl(k, ccross(m, e1));
+  c3 G1[4] = {tp, cscl(s, ta), cscl(s, tb), cscl(s, tc)};
+  c3 G0[4] = {cscl(-1.0, tp), cscl(1.0 - s, ta), cscl(1.0 - s, tb), cscl(1.0 - s, tc)};
+  if (!clamped) {
+    c3 ns = cadd(ccross(e1s, e2), ccross(e1, e2s));
+    double complex gv = cdot(w, n), gs = cdot(ws, n) + cdot(w, ns);
+    c3 dg[4] = {n, csub(ccross(csub(e1, e2), w), n), ccross(e2, w), ccross(w, e1)};
+    c3 FP[4];
+    double complex Fs;
+    if (d == 0.0) {
+      Fs = gs;
+      for (int j = 0; j < 4; ++j) FP[j] = dg[j];
+    } else {
+      Fs = 2.0 * gv * gs - 2.0 * d * d * cdot(n, ns);
+      c3 dq[4] = {cmk(0, 0, 0), cscl(2.0, ccross(csub(e1, e2), n)), cscl(2.0, ccross(e2, n)), cscl(2.0, ccross(n, e1))};
+      for (int j = 0; j < 4; ++j) FP[j] = csub(cscl(2.0 * gv, dg[j]), cscl(d * d, dq[j]));
+    }
+    double complex dVds = 0.5 * dt * (-R + (1.0 - s) * cdot(m, ns));
+    for (int j = 0; j < 4; ++j) {
+      G1[j] = cadd(G1[j], cscl(-dVds * s / Fs, FP[j]));
+      G0[j] = cadd(G0[j], cscl(-dVds * (1.0 - s) / Fs, FP[j]));
+    }
+  }
+  for (int j = 0; j < 4; ++j) {
+    g1[3 * j] = G1[j].x; g1[3 * j + 1] = G1[j].y; g1[3 * j + 2] = G1[j].z;
+    g0[3 * j] = G0[j].x; g0[3 * j + 1] = G0[j].y; g0[3 * j + 2] = G0[j].z;
+  }
+}
+
+/* Real V and gradients with respect to X0 and X1 (12 each, order p, a, b, c). */
+void oracle_vt_grad_full(const double *x0, const double *x1, double s, double d, double eps, double dt, double *V,
+                         double *g0, double *g1) {
+  c3 X0[4], X1[4];
+  for (int k = 0; k < 4; ++k) {
+    X0[k] = cmk(x0[3 * k], x0[3 * k + 1], x0[3 * k + 2]);
+    X1[k] = cmk(x1[3 * k], x1[3 * k + 1], x1[3 * k + 2]);
+  }
+  double complex Vc, a[12], b[12];
+  cgrad(X0, X1, s, d, eps, dt, s == 0.0, &Vc, a, b);
+  *V = creal(Vc);
+  for (int k = 0; k < 12; ++k) { g0[k] = creal(a[k]); g1[k] = creal(b[k]); }
+}
+
+/* dL/dX0, dL/dX1 of one contact for cotangents gV (of V_k) and w (of dV_k/dX1). */
+void oracle_vt_backward(const double *x0, const double *x1, double s, double d, double eps, double dt, double gV,
+                        const double *w, double *gx0, double *gx1) {
+  const double h = 1e-30;
+  c3 X0[4], X1[4], D[4];
+  for (int k = 0; k < 4; ++k) {
+    X0[k] = cmk(x0[3 * k], x0[3 * k + 1], x0[3 * k + 2]);
+    X1[k] = cmk(x1[3 * k] + I * h * w[3 * k], x1[3 * k + 1] + I * h * w[3 * k + 1], x1[3 * k + 2] + I * h * w[3 * k + 2]);
+    D[k] = csub(X1[k], X0[k]);
+  }
+  double complex sc = s;
+  if (s != 0.0) {
+    for (int it = 0; it < 8; ++it) { /* Newton to the complex root near the real one */
+      double complex F, Fs;
+      cF(X0, D, sc, d, &F, &Fs);
+      sc -= F / Fs;
+    }
+  }
+  double complex Vc, a[12], b[12];
+  cgrad(X0, X1, sc, d, eps, dt, s == 0.0, &Vc, a, b);
+  for (int k = 0; k < 12; ++k) {
+    gx0[k] = gV * creal(a[k]) + cimag(a[k]) / h;
+    gx1[k] = gV * creal(b[k]) + cimag(b[k]) / h;
   }
 }

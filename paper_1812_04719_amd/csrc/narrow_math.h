@@ -306,5 +306,139 @@ __host__ __device__ inline bool needs_root_search(const Quad &Q, double d) {
   return !(pos || (N == 3 && neg));
 }
 
+
+// ---------------------------------------------------------------------------
+// Full gradient of V_k with respect to X0 and X1 of the four vertices, for a
+// generic scalar type (double, or Dual for forward-mode derivatives of the
+// gradient itself: the Hessian-vector products of the backward pass).
+// P(s) = X0 + s D, D = X1 - X0, U_p = D_p / dt, V = 0.5 dt (1 - s) R,
+// R = sqrt(eps^2 q + (U_p.n)^2).  dP_j/dX1_j = s, dP_j/dX0_j = 1 - s,
+// dU_p/dX1_p = 1/dt = -dU_p/dX0_p; s moves with the positions through
+// F(s, X0, X1) = 0: ds/dX1_j = -s F_Pj / F_s, ds/dX0_j = -(1 - s) F_Pj / F_s.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+};
+__host__ __device__ inline Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
+__host__ __device__ inline Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
+__host__ __device__ inline Dual operator-(Dual a) { return Dual{-a.v, -a.d}; }
+__host__ __device__ inline Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, a.d * b.v + a.v * b.d}; }
+__host__ __device__ inline Dual operator/(Dual a, Dual b) {
+  return Dual{a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)};
+}
+__host__ __device__ inline Dual dsqrt(Dual a) {
+  const double r = sqrt(a.v);
+  return Dual{r, a.d / (2.0 * r)};
+}
+__host__ __device__ inline double dsqrt(double a) { return sqrt(a); }
+__host__ __device__ inline Dual cst(double x, Dual) { return Dual{x, 0.0}; }
+__host__ __device__ inline double cst(double x, double) { return x; }
+
+template <class T>
+struct V3 {
+  T x, y, z;
+};
+template <class T>
+__host__ __device__ inline V3<T> operator+(V3<T> a, V3<T> b) { return V3<T>{a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T>
+__host__ __device__ inline V3<T> operator-(V3<T> a, V3<T> b) { return V3<T>{a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T>
+__host__ __device__ inline V3<T> scale(T s, V3<T> a) { return V3<T>{s * a.x, s * a.y, s * a.z}; }
+template <class T>
+__host__ __device__ inline T dot3(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T>
+__host__ __device__ inline V3<T> cross3(V3<T> a, V3<T> b) {
+  return V3<T>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// X0, X1: (p, a, b, c) with the image shift already applied to X0 and X1.
+// Writes V, g0 = dV/dX0 (12), g1 = dV/dX1 (12); dsdx1 (optional, 12) gets
+// ds/dX1 of the contact time (zero when clamped at s = 0).
+template <class T>
+__host__ __device__ void full_grad(const V3<T> X0[4], const V3<T> X1[4], T s, double d, double eps, double dt,
+                                   bool clamped, T *V, T g0[12], T g1[12], T *dsdx1) {
+  const T one = cst(1.0, s), half = cst(0.5, s), two = cst(2.0, s);
+  const T tdt = cst(dt, s), te2 = cst(eps * eps, s), td2 = cst(d * d, s);
+  V3<T> D[4], P[4];
+  for (int k = 0; k < 4; ++k) {
+    D[k] = X1[k] - X0[k];
+    P[k] = X0[k] + scale(s, D[k]);
+  }
+  const V3<T> e1 = P[2] - P[1], e2 = P[3] - P[1], w = P[0] - P[1];
+  const V3<T> e1s = D[2] - D[1], e2s = D[3] - D[1], ws = D[0] - D[1];
+  const V3<T> n = cross3(e1, e2);
+  const T q = dot3(n, n);
+  const V3<T> U = scale(one / tdt, D[0]);
+  const T un = dot3(U, n);
+  const T R = dsqrt(te2 * q + un * un);
+  const T k = half * tdt * (one - s);
+  *V = k * R;
+  const V3<T> m = scale(one / R, scale(te2, n) + scale(un, U));  // dR/dn
+  // explicit parts at fixed s (through n for the triangle, through U for p)
+  const V3<T> tp = scale(half * (one - s) * un / R, n);
+  const V3<T> ta = scale(k, cross3(e1 - e2, m)), tb = scale(k, cross3(e2, m)), tc = scale(k, cross3(m, e1));
+  V3<T> G1[4] = {tp, scale(s, ta), scale(s, tb), scale(s, tc)};
+  V3<T> G0[4] = {scale(cst(-1.0, s), tp), scale(one - s, ta), scale(one - s, tb), scale(one - s, tc)};
+  V3<T> ds1[4];
+  const T zero = cst(0.0, s);
+  for (int j = 0; j < 4; ++j) ds1[j] = V3<T>{zero, zero, zero};
+  if (!clamped) {
+    const V3<T> ns = cross3(e1s, e2) + cross3(e1, e2s);
+    const T gv = dot3(w, n);
+    const T gs = dot3(ws, n) + dot3(w, ns);
+    const V3<T> dgp = n, dga = cross3(e1 - e2, w) - n, dgb = cross3(e2, w), dgc = cross3(w, e1);
+    T Fs;
+    V3<T> FP[4];
+    if (d == 0.0) {
+      Fs = gs;
+      FP[0] = dgp; FP[1] = dga; FP[2] = dgb; FP[3] = dgc;
+    } else {
+      Fs = two * gv * gs - two * td2 * dot3(n, ns);
+      FP[0] = scale(two * gv, dgp);
+      FP[1] = scale(two * gv, dga) - scale(td2 * two, cross3(e1 - e2, n));
+      FP[2] = scale(two * gv, dgb) - scale(td2 * two, cross3(e2, n));
+      FP[3] = scale(two * gv, dgc) - scale(td2 * two, cross3(n, e1));
+    }
+    const T dVds = half * tdt * (dot3(m, ns) * (one - s) - R);
+    for (int j = 0; j < 4; ++j) {
+      ds1[j] = scale(cst(-1.0, s) * s / Fs, FP[j]);
+      const V3<T> ds0 = scale(cst(-1.0, s) * (one - s) / Fs, FP[j]);
+      G1[j] = G1[j] + scale(dVds, ds1[j]);
+      G0[j] = G0[j] + scale(dVds, ds0);
+    }
+  }
+  for (int j = 0; j < 4; ++j) {
+    g1[3 * j] = G1[j].x; g1[3 * j + 1] = G1[j].y; g1[3 * j + 2] = G1[j].z;
+    g0[3 * j] = G0[j].x; g0[3 * j + 1] = G0[j].y; g0[3 * j + 2] = G0[j].z;
+    if (dsdx1) { dsdx1[3 * j] = ds1[j].x; dsdx1[3 * j + 1] = ds1[j].y; dsdx1[3 * j + 2] = ds1[j].z; }
+  }
+}
+
+// Vector-Jacobian product of one vertex-triangle contact for the backward
+// pass: with gV = dL/dV_k and w = dL/d(dV_k/dX1) (12), returns
+// c0 = dL/dX0 and c1 = dL/dX1 of the four vertices:
+//   c = gV grad V_k + d/de [grad V_k](X1 + e w),
+// the second term being the Hessian of V_k applied to w (symmetric), by
+// forward-mode differentiation of the full gradient.
+__host__ __device__ inline void vt_vjp(const V3<double> X0[4], const V3<double> X1[4], double s, double d,
+                                       double eps, double dt, bool clamped, double gV, const double w[12],
+                                       double c0[12], double c1[12]) {
+  double V, g0[12], g1[12], ds1[12];
+  full_grad<double>(X0, X1, s, d, eps, dt, clamped, &V, g0, g1, ds1);
+  double sdot = 0.0;
+  for (int k = 0; k < 12; ++k) sdot += ds1[k] * w[k];
+  V3<Dual> X0d[4], X1d[4];
+  for (int j = 0; j < 4; ++j) {
+    X0d[j] = V3<Dual>{Dual{X0[j].x, 0.0}, Dual{X0[j].y, 0.0}, Dual{X0[j].z, 0.0}};
+    X1d[j] = V3<Dual>{Dual{X1[j].x, w[3 * j]}, Dual{X1[j].y, w[3 * j + 1]}, Dual{X1[j].z, w[3 * j + 2]}};
+  }
+  Dual Vd, g0d[12], g1d[12];
+  full_grad<Dual>(X0d, X1d, Dual{s, clamped ? 0.0 : sdot}, d, eps, dt, clamped, &Vd, g0d, g1d, nullptr);
+  for (int k = 0; k < 12; ++k) {
+    c0[k] = gV * g0[k] + g0d[k].d;
+    c1[k] = gV * g1[k] + g1d[k].d;
+  }
+}
+
 }  // namespace nm
 }  // namespace stiv

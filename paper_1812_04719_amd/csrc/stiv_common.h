@@ -168,4 +168,11 @@ void launch_write_volumes(const Counters *cnt, int64_t pairs_cap, const int64_t 
 void launch_finalize(Counters *cnt, const int64_t *vol_off, const int64_t *row_off, int64_t pairs_cap,
                      const int64_t *cp_total, hipStream_t st);
 
+// Backward pass
+void launch_backward(const DevScene &S, const DevTopo &T, double d, double eps, double dt, int64_t n_ct,
+                     const int32_t *ct_key, const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift,
+                     int64_t n_vol, const int32_t *vol_pair, int64_t n_jrow, const int32_t *j_vol,
+                     const int32_t *j_vtx, const double *dV, const double *dG, double *contrib, uint64_t *gkeys,
+                     int32_t *gidx, double *dX0, double *dX1, hipStream_t st);
+
 }  // namespace stiv

@@ -66,7 +66,7 @@ struct stiv_ctx {
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
-      row_off, row_vtx, row_g, sort_tk, sort_tv;
+      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx;
   int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0, cap_list = 0;
   Counters *h_cnt = nullptr;  // pinned
   // last structurally validated scene (pointers + sizes); see check_structure
@@ -136,7 +136,8 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->cand_list, &ctx->ct,
                 &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
                 &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
-                &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv};
+                &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv,
+                &ctx->bwd_contrib, &ctx->bwd_keys, &ctx->bwd_idx};
   for (Buf *b : all)
     if (b->p) hipFree(b->p);
   for (auto &e : ctx->ev)
@@ -617,6 +618,38 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
 stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n) {
   if (!ctx || !ms) return STIV_E_ARG;
   for (int k = 0; k < n && k < 7; ++k) ms[k] = ctx->stage_ms[k];
+  return STIV_OK;
+}
+
+stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
+                          const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, void *stream) {
+  if (!ctx) return STIV_E_ARG;
+  if (!res) return fail(ctx, STIV_E_ARG, "null result");
+  stiv_status st0 = check_args(ctx, s, p);
+  if (st0 != STIV_OK) return st0;
+  HIPCHK(hipSetDevice(ctx->device));
+  stiv_status sv = check_structure(ctx, s);
+  if (sv != STIV_OK) return sv;
+  const int64_t n_ct = res->n_ct_vt + res->n_ct_ee;
+  if (res->n_pairs > res->cap_pairs || n_ct > res->cap_ct || res->n_vol > res->cap_vol || res->n_jrow > res->cap_jrow)
+    return fail(ctx, STIV_E_ARG, "backward needs a complete detect result (no capacity overflow)");
+  if (n_ct > 0 && (!res->ct_key || !res->ct_tau || !res->pair_ab || !res->pair_shift))
+    return fail(ctx, STIV_E_ARG, "backward needs the contact and pair arrays of the detect result");
+  if (res->n_vol > 0 && (!res->vol_pair || !res->j_vol || !res->j_vtx))
+    return fail(ctx, STIV_E_ARG, "backward needs the volume and Jacobian arrays of the detect result");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(ensure(ctx->bwd_contrib, 6 * 8 * 4 * (size_t)(n_ct + 1)));
+  HIPCHK(ensure(ctx->bwd_keys, 8 * 8 * (size_t)(n_ct + 1)));
+  HIPCHK(ensure(ctx->bwd_idx, 4 * 8 * (size_t)(n_ct + 1)));
+  DevScene S;
+  S.n_ves = s->n_ves; S.n_vtx = s->n_vtx; S.n_scenes = s->n_scenes;
+  S.vtx_off = s->vtx_off; S.topo_id = s->topo_id; S.scene_off = s->scene_off;
+  S.box_len = s->box_len; S.x0 = s->x0; S.x1 = s->x1;
+  launch_backward(S, ctx->topo, p->d, p->eps, p->dt, n_ct, res->ct_key, res->ct_tau, res->pair_ab, res->pair_shift,
+                  res->n_vol, res->vol_pair, res->n_jrow, res->j_vol, res->j_vtx, dL_dV, dL_dG,
+                  P<double>(ctx->bwd_contrib), P<uint64_t>(ctx->bwd_keys), P<int32_t>(ctx->bwd_idx), dL_dX0, dL_dX1,
+                  st);
+  HIPCHK(hipGetLastError());
   return STIV_OK;
 }
 

@@ -22,7 +22,7 @@ _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HI
            -5: "STIV_E_STATE"}
 
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
-           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_sort_pairs_u64", "stiv_last_error")
+           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_sort_pairs_u64", "stiv_last_error")
 STAT_NAMES = ("check_points", "vesicle_pairs", "work_items", "pre_candidates", "candidates_vt", "candidates_ee",
               "root_searches", "contacts")
 
@@ -82,6 +82,9 @@ def lib():
             L.stiv_get_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int]
             L.stiv_get_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int]
             L.stiv_set_patch_size.argtypes = [C.c_void_p, C.c_int]
+            L.stiv_backward.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_params),
+                                        C.POINTER(stiv_result), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]
             L.stiv_sort_pairs_u64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
             L.stiv_last_error.argtypes = [C.c_void_p]
             L.stiv_last_error.restype = C.c_char_p
@@ -249,7 +252,28 @@ def detect(ctx: Context, dscene: DeviceScene, d, eps, dt, outputs: Outputs = Non
         break
     else:
         raise StivError(STIV_E_CAPACITY, "outputs did not fit after growing")
-    return _collect(r, outputs, emit_candidates, to_numpy), outputs
+    res = _collect(r, outputs, emit_candidates, to_numpy)
+    res["_struct"] = r
+    return res, outputs
+
+
+def backward(ctx: Context, dscene: DeviceScene, d, eps, dt, result_struct, dL_dV=None, dL_dG=None, stream=None):
+    """dL/dX0, dL/dX1 ([3, n_vtx] float64 tensors) for cotangents of V and G."""
+    torch = _torch()
+    dev = dscene.x0.device
+    dX0 = torch.empty_like(dscene.x0)
+    dX1 = torch.empty_like(dscene.x1)
+    p = stiv_params(float(d), float(eps), float(dt), 0)
+    s = dscene.struct()
+    st_ptr = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    gv = dL_dV.contiguous() if dL_dV is not None else None
+    gg = dL_dG.contiguous() if dL_dG is not None else None
+    st = lib().stiv_backward(ctx._h, C.byref(s), C.byref(p), C.byref(result_struct),
+                             C.c_void_p(gv.data_ptr() if gv is not None else 0),
+                             C.c_void_p(gg.data_ptr() if gg is not None else 0), C.c_void_p(dX0.data_ptr()),
+                             C.c_void_p(dX1.data_ptr()), C.c_void_p(st_ptr))
+    ctx._check(st)
+    return dX0, dX1
 
 
 def _collect(r, o, emit, to_numpy):

@@ -87,3 +87,43 @@ def compare(gpu, ora, dt, eps, check_cand=False, pair_subset=None):
         scale = np.abs(ora["j_g"]).max() if len(ora["j_g"]) else 1.0
         assert np.all(np.abs(gpu["j_g"][rows] - ora["j_g"]) <= TOL * scale + 1e-14 * scale)
     return True
+
+
+def contact_positions(scene, pair_ab, pair_shift, key):
+    """Global vertex ids (p, a, b, c) and shifted X0, X1 [4,3] of a VT contact key."""
+    p, kind, i, j = [int(v) for v in key]
+    a, b = pair_ab[p]
+    sc = int(np.searchsorted(scene.scene_off, a, side="right") - 1)
+    sh = pair_shift[p] * scene.box_len[sc]
+    off = scene.vtx_off
+    vv, vt = (b, a) if kind == 1 else (a, b)
+    tri = scene.topos[scene.topo_id[vt]].tri[j]
+    gid = np.array([off[vv] + i, off[vt] + tri[0], off[vt] + tri[1], off[vt] + tri[2]])
+    shift = np.zeros((4, 3))
+    if kind == 1:
+        shift[0] = sh
+    else:
+        shift[1:] = sh
+    x0 = scene.x0[:, gid].T + shift
+    x1 = scene.x1[:, gid].T + shift
+    return gid, x0, x1
+
+
+def oracle_backward(scene, ora, gV, gG):
+    """dL/dX0, dL/dX1 [3, n_vtx] from the oracle's per-contact complex-step backward."""
+    import oracle
+    dX0 = np.zeros((3, scene.n_vtx))
+    dX1 = np.zeros((3, scene.n_vtx))
+    vol_of_pair = {int(p): v for v, p in enumerate(ora["vol_pair"])}
+    rows = {(int(v), int(g)): r for r, (v, g) in enumerate(zip(ora["j_vol"], ora["j_vtx"]))}
+    for k, key in enumerate(ora["ct_key"]):
+        if key[1] == 2:
+            continue
+        v = vol_of_pair[int(key[0])]
+        gid, x0, x1 = contact_positions(scene, ora["pair_ab"], ora["pair_shift"], key)
+        w = np.array([gG[rows[(v, int(g))]] for g in gid])
+        b0, b1 = oracle.vt_backward(x0, x1, ora["ct_s"][k], scene.d, scene.eps, scene.dt, gV[v], w)
+        for r in range(4):
+            dX0[:, gid[r]] += b0[r]
+            dX1[:, gid[r]] += b1[r]
+    return dX0, dX1

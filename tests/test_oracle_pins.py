@@ -372,3 +372,44 @@ def test_configs_general_position(k):
     if k == 3:
         # about two contact volumes per vesicle (Sec. 1 and Sec. 4.3 report ~2)
         assert 1.5 <= 2.0 * r.n_vol / sc.n_ves <= 2.5
+
+
+@pytest.mark.parametrize("d", [0.0, 0.02])
+def test_full_gradient_and_backward_vs_finite_differences(d):
+    """dV/dX0 and the complex-step backward (Hessian-vector product) vs central FD."""
+    rng = np.random.default_rng(77 + int(d * 100))
+    eps, dt = 1.0, 0.1
+    checked = 0
+    while checked < 10:
+        x0, x1 = _random_vt(rng)
+        hit, s_ref, amb = referee.earliest(x0, x1, d=d)
+        if not hit or amb or s_ref < 1e-3:
+            continue
+        s = oracle.narrow(x0, x1, d=d)
+        V, g0, g1 = oracle.vt_grad_full(x0, x1, s, d, eps, dt)
+        V2, G = oracle.vt_volume(x0, x1, s, d, eps, dt)
+        assert abs(V - V2) <= 1e-14 * abs(V) and np.allclose(g1, G, rtol=1e-13, atol=1e-15 * np.abs(G).max())
+
+        def at(a, b):
+            ss = oracle.narrow(a, b, d=d)
+            return oracle.vt_grad_full(a, b, ss, d, eps, dt)
+
+        h = 1e-6
+        fd0 = np.zeros((4, 3))
+        for k in range(4):
+            for c in range(3):
+                ap, am = x0.copy(), x0.copy()
+                ap[k, c] += h
+                am[k, c] -= h
+                fd0[k, c] = (at(ap, x1)[0] - at(am, x1)[0]) / (2 * h)
+        assert np.abs(g0 - fd0).max() <= 1e-6 * np.abs(fd0).max()
+        w = rng.normal(size=(4, 3))
+        gV = rng.normal()
+        b0, b1 = oracle.vt_backward(x0, x1, s, d, eps, dt, gV, w)
+        _, g0p, g1p = at(x0, x1 + h * w)
+        _, g0m, g1m = at(x0, x1 - h * w)
+        want1 = gV * g1 + (g1p - g1m) / (2 * h)
+        want0 = gV * g0 + (g0p - g0m) / (2 * h)
+        assert np.abs(b1 - want1).max() <= 1e-6 * np.abs(want1).max()
+        assert np.abs(b0 - want0).max() <= 1e-6 * np.abs(want0).max()
+        checked += 1
