@@ -143,6 +143,13 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *topo);
  * afterwards.  Results do not depend on it; speed does (see the autotuner). */
 stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch);
 
+/* Tuning options (results never depend on them): STIV_OPT_PATCH_TRI
+ * (16/32/64, as stiv_set_patch_size), STIV_OPT_PRIM_BLOCKS and
+ * STIV_OPT_NARROW_BLOCKS (workgroups of the persistent primitive and
+ * root-search kernels, 256..65536). */
+enum { STIV_OPT_PATCH_TRI = 1, STIV_OPT_PRIM_BLOCKS = 2, STIV_OPT_NARROW_BLOCKS = 3 };
+stiv_status stiv_set_option(stiv_ctx *ctx, int option, int64_t value);
+
 /* Pre-size the scratch arena for scenes of this shape (optional; detect
  * grows it on demand). */
 stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p);
@@ -152,6 +159,22 @@ stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *
  * call then synchronises the stream once to read the counts into *out. */
 stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out,
                         void *stream);
+
+/* Graph-capturable detect.  Enqueues the same pipeline as stiv_detect on
+ * `stream` with no host synchronisation, no allocation, no host copies and
+ * no event records, so it can be captured into a hipGraph and replayed.
+ * Requires a prior stiv_detect (or stiv_reserve) on a scene with the same
+ * structural arrays, which sizes the arena; the counts stay on the device
+ * until stiv_collect.  Candidate lists (STIV_EMIT_CANDIDATES) are not
+ * available here. */
+stiv_status stiv_detect_async(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out,
+                              void *stream);
+
+/* Synchronise `stream` and read the counts of the last stiv_detect_async (or
+ * graph replay) into *out.  STIV_E_CAPACITY if an internal buffer or an
+ * output array was too small (run stiv_detect once to grow the arena, then
+ * capture again). */
+stiv_status stiv_collect(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, void *stream);
 
 /* Backward pass (adjoint) of a detect.  `res` is the complete result of a
  * stiv_detect on the same scene and parameters (its device arrays must be

@@ -150,21 +150,21 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
 
 }  // namespace
 
-static int grid_for(int64_t n) {
+static int grid_for(int64_t n, int max_blocks) {
   int64_t g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
+  if (g > max_blocks) g = max_blocks;
   if (g < 1) g = 1;
   return (int)g;
 }
 
-void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
+void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
                    int64_t ct_cap, Counters *cnt, hipStream_t st) {
   if (d == 0.0)
-    k_narrow<3><<<grid_for(hard_cap), 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
+    k_narrow<3><<<grid_for(hard_cap, blocks), 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
                                                     ct_grad, ct_cap, cnt);
   else
-    k_narrow<6><<<grid_for(hard_cap), 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
+    k_narrow<6><<<grid_for(hard_cap, blocks), 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
                                                     ct_grad, ct_cap, cnt);
 }
 

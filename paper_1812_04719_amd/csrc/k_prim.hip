@@ -436,26 +436,26 @@ void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pair
 }
 
 template <int TILE>
-static void launch_tile(const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
+static void launch_tile(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
                         const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
                         int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (d == 0.0)
-    k_prim_cand<3, TILE><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
+    k_prim_cand<3, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
                                               list_cap, cnt);
   else
-    k_prim_cand<6, TILE><<<8192, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
+    k_prim_cand<6, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
                                               list_cap, cnt);
 }
 
-void launch_prim_cand(int tile, const DevScene &S, const DevTopo &T, const PairRec *pairs,
+void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,
                       const int64_t *ves_patch_off, const uint64_t *work, int64_t work_cap, double d, Cand *hard,
                       int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (tile <= 16)
-    launch_tile<16>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+    launch_tile<16>(blocks, S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
   else if (tile <= 32)
-    launch_tile<32>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+    launch_tile<32>(blocks, S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
   else
-    launch_tile<64>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+    launch_tile<64>(blocks, S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
 }
 
 }  // namespace stiv

@@ -141,12 +141,12 @@ void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
                         uint64_t *work, int64_t work_cap, Counters *cnt, hipStream_t st);
-void launch_prim_cand(int tile, const DevScene &S, const DevTopo &T, const PairRec *pairs,
+void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,
                       const int64_t *ves_patch_off, const uint64_t *work, int64_t work_cap, double d, Cand *hard,
                       int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st);
 
 // K3 + K4: root search on the queued candidates, volumes and gradients
-void launch_narrow(const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
+void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
                    int64_t ct_cap, Counters *cnt, hipStream_t st);
 

@@ -60,7 +60,9 @@ struct stiv_ctx {
   DevTopo topo{};
   std::vector<int> h_npatch;  // patches per topology
   int max_patches = 0;
-  int tile = 64;  // triangles per patch (16, 32 or 64)
+  int tile = 64;            // triangles per patch (16, 32 or 64)
+  int prim_blocks = 8192;   // workgroups of the primitive-candidate kernel
+  int narrow_blocks = 8192; // upper bound on workgroups of the root-search kernel
   // arena
   Buf counters, ves_box, ves_scene, grid, cp_cnt, cp_off, cp_keys, cp_vals, cp_tk, cp_tv, hash, uniq, sorted,
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
@@ -68,6 +70,7 @@ struct stiv_ctx {
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
       row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx;
   int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0, cap_list = 0;
+  int64_t arena_n_ves = 0, arena_max_patches = 0;
   Counters *h_cnt = nullptr;  // pinned
   // last structurally validated scene (pointers + sizes); see check_structure
   const void *val_ptr[4] = {};
@@ -391,6 +394,8 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->row_off, 8 * (ctx->cap_pairs + 2)));
   HIPCHK(ensure(ctx->row_vtx, 4 * 4 * ctx->cap_ct));
   HIPCHK(ensure(ctx->row_g, 3 * 8 * 4 * ctx->cap_ct));
+  ctx->arena_n_ves = std::max<int64_t>(ctx->arena_n_ves, N);
+  ctx->arena_max_patches = ctx->max_patches;
   return STIV_OK;
 }
 
@@ -455,20 +460,21 @@ stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *
   return arena(ctx, s);
 }
 
-static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p, stiv_result *out, hipStream_t st) {
+static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p, stiv_result *out, hipStream_t st,
+                         bool timed) {
   const double h = 0.5 * p->d;
   const int64_t N = S.n_ves;
   Counters *cnt = P<Counters>(ctx->counters);
   const DevTopo &T = ctx->topo;
   const int64_t hash_cap = pow2_at_least(4 * ctx->cap_pairs);
-  hipEventRecord(ctx->ev[8], st);
+  if (timed) (void)hipEventRecord(ctx->ev[8], st);
   launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 0ull, sizeof(Counters) / 8, st);
   launch_ves_patch_count(S, T, P<int64_t>(ctx->ves_patch_cnt), st);
   launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, st);
   // ---- K0 boxes
-  hipEventRecord(ctx->ev[0], st);
+  if (timed) (void)hipEventRecord(ctx->ev[0], st);
   launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box), cnt, st);
-  hipEventRecord(ctx->ev[1], st);
+  if (timed) (void)hipEventRecord(ctx->ev[1], st);
   // ---- K1 vesicle broad phase
   launch_ves_scene(S, P<int>(ctx->ves_scene), st);
   launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), st);
@@ -496,22 +502,23 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                              P<int32_t>(ctx->cursor_a), P<uint64_t>(ctx->sorted), cnt, st);
   launch_pair_bucket_sort_emit(S, P<int>(ctx->ves_scene), P<int64_t>(ctx->off_a), P<uint64_t>(ctx->sorted), (int)N,
                                P<PairRec>(ctx->pairs), out->pair_ab, out->pair_shift, out->cap_pairs, st);
-  hipEventRecord(ctx->ev[2], st);
+  if (timed) (void)hipEventRecord(ctx->ev[2], st);
   // ---- K2 primitive broad phase
   launch_patch_pairs(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, P<double>(ctx->ves_box),
                      P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<uint64_t>(ctx->work),
                      ctx->cap_work, cnt, st);
-  hipEventRecord(ctx->ev[3], st);
+  if (timed) (void)hipEventRecord(ctx->ev[3], st);
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
-  launch_prim_cand(ctx->tile, S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<uint64_t>(ctx->work),
+  launch_prim_cand(ctx->tile, ctx->prim_blocks, S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<uint64_t>(ctx->work),
                    ctx->cap_work, p->d, P<Cand>(ctx->cand), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
                    emit ? ctx->cap_list : 0, cnt, st);
-  hipEventRecord(ctx->ev[4], st);
+  if (timed) (void)hipEventRecord(ctx->ev[4], st);
   // ---- K3 + K4 root search, volumes and gradients
-  launch_narrow(S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps, p->dt,
+  launch_narrow(ctx->narrow_blocks, S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps,
+                p->dt,
                 P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
                 cnt, st);
-  hipEventRecord(ctx->ev[5], st);
+  if (timed) (void)hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
   launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
   launch_fill_i32(P<int32_t>(ctx->pair_cursor), 0, ctx->cap_pairs + 1, st);
@@ -534,7 +541,29 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                        out->vol_V, out->cap_vol, out->j_vol, out->j_vtx, out->j_g, out->cap_jrow, st);
   launch_finalize(cnt, P<int64_t>(ctx->vol_off), P<int64_t>(ctx->row_off), ctx->cap_pairs, P<int64_t>(ctx->cp_off) + N,
                   st);
-  hipEventRecord(ctx->ev[6], st);
+  if (timed) (void)hipEventRecord(ctx->ev[6], st);
+}
+
+// Counts of the last pipeline run into *out; STIV_E_CAPACITY when an internal
+// buffer or a caller array was too small.
+static stiv_status read_counts(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, bool *internal_overflow) {
+  const Counters &c = *ctx->h_cnt;
+  *internal_overflow = (int64_t)c.n_cp > ctx->cap_cp || (int64_t)c.n_pairs > ctx->cap_pairs || c.hash_overflow ||
+                       (int64_t)c.n_work > ctx->cap_work || (int64_t)c.n_hard > ctx->cap_cand ||
+                       (int64_t)c.n_ct > ctx->cap_ct ||
+                       ((p->flags & STIV_EMIT_CANDIDATES) && (int64_t)c.n_cand_list > ctx->cap_list);
+  if (c.nonfinite) return fail(ctx, STIV_E_NUMERIC, "a position is NaN or infinite");
+  if (c.shift_overflow) return fail(ctx, STIV_E_ARG, "periodic box too small: image shifts beyond +-7 box lengths");
+  out->n_pairs = (int64_t)c.n_pairs;
+  out->n_cand_vt = (int64_t)c.n_cand_vt;
+  out->n_cand_ee = (int64_t)c.n_cand_ee;
+  out->n_ct_vt = (int64_t)c.n_ct_vt;
+  out->n_ct_ee = (int64_t)c.n_ct_ee;
+  out->n_vol = (int64_t)c.n_vol;
+  out->n_jrow = (int64_t)c.n_jrow;
+  out->n_initially_within_d = (int64_t)c.within_d;
+  out->n_degenerate_skipped = (int64_t)c.degenerate;
+  return STIV_OK;
 }
 
 stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out, void *stream) {
@@ -562,15 +591,15 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
       if (ctx->cap_list == 0) ctx->cap_list = 4 * ctx->cap_cand;
       HIPCHK(ensure(ctx->cand_list, sizeof(Cand) * ctx->cap_list));
     }
-    run_pipeline(ctx, S, p, out, st);
+    run_pipeline(ctx, S, p, out, st, true);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const Counters &c = *ctx->h_cnt;
+    bool grow = false;
     if (c.nonfinite) return fail(ctx, STIV_E_NUMERIC, "a position is NaN or infinite");
     if (c.shift_overflow)
       return fail(ctx, STIV_E_ARG, "periodic box too small: image shifts beyond +-7 box lengths");
-    bool grow = false;
     const int64_t need_cp = (int64_t)c.n_cp;
     if (need_cp > ctx->cap_cp) { ctx->cap_cp = need_cp + need_cp / 4; grow = true; }
     if ((int64_t)c.n_pairs > ctx->cap_pairs || c.hash_overflow) {
@@ -585,15 +614,9 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
     }
     if ((int64_t)c.n_ct > ctx->cap_ct) { ctx->cap_ct = (int64_t)c.n_ct + c.n_ct / 4 + 1024; grow = true; }
     if (grow) continue;
-    out->n_pairs = (int64_t)c.n_pairs;
-    out->n_cand_vt = (int64_t)c.n_cand_vt;
-    out->n_cand_ee = (int64_t)c.n_cand_ee;
-    out->n_ct_vt = (int64_t)c.n_ct_vt;
-    out->n_ct_ee = (int64_t)c.n_ct_ee;
-    out->n_vol = (int64_t)c.n_vol;
-    out->n_jrow = (int64_t)c.n_jrow;
-    out->n_initially_within_d = (int64_t)c.within_d;
-    out->n_degenerate_skipped = (int64_t)c.degenerate;
+    bool internal = false;
+    stiv_status sr = read_counts(ctx, p, out, &internal);
+    if (sr != STIV_OK) return sr;
     float ms[8] = {};
     for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&ms[k], ctx->ev[k], ctx->ev[k + 1]);
     (void)hipEventElapsedTime(&ms[6], ctx->ev[8], ctx->ev[6]);
@@ -613,6 +636,67 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
     return STIV_OK;
   }
   return fail(ctx, STIV_E_CAPACITY, "internal buffers did not converge after growing");
+}
+
+stiv_status stiv_detect_async(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, stiv_result *out,
+                              void *stream) {
+  if (!ctx) return STIV_E_ARG;
+  if (!out) return fail(ctx, STIV_E_ARG, "null result");
+  stiv_status st0 = check_args(ctx, s, p);
+  if (st0 != STIV_OK) return st0;
+  if (p->flags & STIV_EMIT_CANDIDATES) return fail(ctx, STIV_E_ARG, "candidate lists need the synchronous stiv_detect");
+  const void *ptrs[4] = {s->vtx_off, s->topo_id, s->scene_off, s->box_len};
+  const int64_t sizes[3] = {s->n_ves, s->n_vtx, s->n_scenes};
+  if (std::memcmp(ptrs, ctx->val_ptr, sizeof ptrs) != 0 || std::memcmp(sizes, ctx->val_size, sizeof sizes) != 0)
+    return fail(ctx, STIV_E_STATE, "stiv_detect_async needs a prior stiv_detect or stiv_reserve on this scene");
+  if (ctx->cap_cp == 0 || !ctx->counters.p || ctx->arena_n_ves < s->n_ves ||
+      ctx->arena_max_patches < ctx->max_patches)
+    return fail(ctx, STIV_E_STATE, "the arena is not sized: call stiv_detect once first");
+  if (s->n_ves == 0) return STIV_OK;
+  DevScene S;
+  S.n_ves = s->n_ves; S.n_vtx = s->n_vtx; S.n_scenes = s->n_scenes;
+  S.vtx_off = s->vtx_off; S.topo_id = s->topo_id; S.scene_off = s->scene_off;
+  S.box_len = s->box_len; S.x0 = s->x0; S.x1 = s->x1;
+  run_pipeline(ctx, S, p, out, reinterpret_cast<hipStream_t>(stream), false);
+  HIPCHK(hipGetLastError());
+  return STIV_OK;
+}
+
+stiv_status stiv_collect(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, void *stream) {
+  if (!ctx || !p || !out) return STIV_E_ARG;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool internal = false;
+  stiv_status sr = read_counts(ctx, p, out, &internal);
+  if (sr != STIV_OK) return sr;
+  if (internal)
+    return fail(ctx, STIV_E_CAPACITY, "internal buffers overflowed: run stiv_detect to grow them, then capture again");
+  const bool over = out->n_pairs > out->cap_pairs || out->n_ct_vt + out->n_ct_ee > out->cap_ct ||
+                    out->n_vol > out->cap_vol || out->n_jrow > out->cap_jrow;
+  if (over) return fail(ctx, STIV_E_CAPACITY, "an output array is too small; n_* hold the required sizes");
+  return STIV_OK;
+}
+
+stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch);
+
+stiv_status stiv_set_option(stiv_ctx *ctx, int option, int64_t value) {
+  if (!ctx) return STIV_E_ARG;
+  switch (option) {
+    case STIV_OPT_PATCH_TRI:
+      return stiv_set_patch_size(ctx, (int)value);
+    case STIV_OPT_PRIM_BLOCKS:
+      if (value < 256 || value > 65536) return fail(ctx, STIV_E_ARG, "prim blocks out of range [256, 65536]");
+      ctx->prim_blocks = (int)value;
+      return STIV_OK;
+    case STIV_OPT_NARROW_BLOCKS:
+      if (value < 256 || value > 65536) return fail(ctx, STIV_E_ARG, "narrow blocks out of range [256, 65536]");
+      ctx->narrow_blocks = (int)value;
+      return STIV_OK;
+    default:
+      return fail(ctx, STIV_E_ARG, "unknown option");
+  }
 }
 
 stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n) {

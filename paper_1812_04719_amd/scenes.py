@@ -29,6 +29,7 @@ has a periodic box ``box_len[s]`` (0 on an axis means free space).
 from __future__ import annotations
 
 import dataclasses
+import functools
 import hashlib
 import json
 import math
@@ -108,6 +109,7 @@ def grid_topology(p: int) -> Topology:
     return topo
 
 
+@functools.lru_cache(maxsize=None)
 def grid_angles(p: int):
     """(theta, phi) of every vertex of the order-p grid (poles last)."""
     x, _ = np.polynomial.legendre.leggauss(p + 1)
@@ -178,6 +180,7 @@ def spheroid_axes(reduced_volume=REDUCED_VOLUME, r0=R0_PAPER):
     return ar * b, b
 
 
+@functools.lru_cache(maxsize=None)
 def spheroid_body_points(p: int, a: float, b: float) -> np.ndarray:
     """[nv, 3] body-frame points of the spheroid with semi-axes (b, b, a)."""
     th, ph = grid_angles(p)
@@ -196,14 +199,21 @@ def _pw_max(r, Ainv, Binv):
 
     r: [k,3]; Ainv: [3,3] or [k,3,3]; Binv: [k,3,3].  The max over a grid is
     below the true max, so "overlap" (value < 1) is reported conservatively.
+    The 3x3 systems are solved in closed form (adjugate / determinant).
     """
     lam = _LAM[None, :, None, None]
     A = np.broadcast_to(Ainv, Binv.shape)[:, None]
     C = (1.0 - lam) * A + lam * Binv[:, None]
-    rr = np.broadcast_to(r[:, None, :], C.shape[:-1])
-    sol = np.linalg.solve(C, rr[..., None])[..., 0]
-    f = _LAM[None, :] * (1.0 - _LAM[None, :]) * np.einsum("kli,kli->kl", rr, sol)
-    return f.max(axis=1)
+    a, b, c = C[..., 0, 0], C[..., 0, 1], C[..., 0, 2]
+    d, e, f = C[..., 1, 1], C[..., 1, 2], C[..., 2, 2]
+    # adjugate of the symmetric matrix [[a b c] [b d e] [c e f]]
+    A00, A01, A02 = d * f - e * e, c * e - b * f, b * e - c * d
+    A11, A12, A22 = a * f - c * c, b * c - a * e, a * d - b * b
+    det = a * A00 + b * A01 + c * A02
+    x, y, z = r[:, None, 0], r[:, None, 1], r[:, None, 2]
+    quad = (A00 * x * x + A11 * y * y + A22 * z * z + 2.0 * (A01 * x * y + A02 * x * z + A12 * y * z)) / det
+    f_l = _LAM[None, :] * (1.0 - _LAM[None, :]) * quad
+    return f_l.max(axis=1)
 
 
 def _shape_inv(R, a, b, inflate):

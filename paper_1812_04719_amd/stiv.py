@@ -18,11 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libstiv.so")
 
 STIV_OK, STIV_E_ARG, STIV_E_CAPACITY, STIV_E_HIP, STIV_E_NUMERIC, STIV_E_STATE = 0, -1, -2, -3, -4, -5
 STIV_EMIT_CANDIDATES = 1
+STIV_OPT_PATCH_TRI, STIV_OPT_PRIM_BLOCKS, STIV_OPT_NARROW_BLOCKS = 1, 2, 3
 _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HIP", -4: "STIV_E_NUMERIC",
            -5: "STIV_E_STATE"}
 
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
-           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_sort_pairs_u64", "stiv_last_error")
+           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_detect_async",
+           "stiv_collect", "stiv_set_option", "stiv_sort_pairs_u64", "stiv_last_error")
 STAT_NAMES = ("check_points", "vesicle_pairs", "work_items", "pre_candidates", "candidates_vt", "candidates_ee",
               "root_searches", "contacts")
 
@@ -82,6 +84,10 @@ def lib():
             L.stiv_get_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int]
             L.stiv_get_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int]
             L.stiv_set_patch_size.argtypes = [C.c_void_p, C.c_int]
+            L.stiv_set_option.argtypes = [C.c_void_p, C.c_int, C.c_int64]
+            L.stiv_detect_async.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_params),
+                                            C.POINTER(stiv_result), C.c_void_p]
+            L.stiv_collect.argtypes = [C.c_void_p, C.POINTER(stiv_params), C.POINTER(stiv_result), C.c_void_p]
             L.stiv_backward.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_params),
                                         C.POINTER(stiv_result), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p]
@@ -147,6 +153,11 @@ class Context:
     def set_patch_size(self, tri_per_patch):
         self._check(lib().stiv_set_patch_size(self._h, int(tri_per_patch)))
         self._topo_key = None
+
+    def set_option(self, option, value):
+        self._check(lib().stiv_set_option(self._h, int(option), int(value)))
+        if option == STIV_OPT_PATCH_TRI:
+            self._topo_key = None
 
     def stage_times(self):
         ms = (C.c_float * 7)()
@@ -255,6 +266,33 @@ def detect(ctx: Context, dscene: DeviceScene, d, eps, dt, outputs: Outputs = Non
     res = _collect(r, outputs, emit_candidates, to_numpy)
     res["_struct"] = r
     return res, outputs
+
+
+class AsyncDetect:
+    """Graph-capturable detect: enqueue() only launches kernels (capture it in
+    a torch.cuda.CUDAGraph / hipGraph and replay), collect() synchronises and
+    reads the counts.  Needs one synchronous detect on the same scene first."""
+
+    def __init__(self, ctx, dscene, d, eps, dt, outputs):
+        self.ctx, self.dscene, self.outputs = ctx, dscene, outputs
+        self.params = stiv_params(float(d), float(eps), float(dt), 0)
+        self.scene_struct = dscene.struct()
+        self.result = outputs.struct()
+
+    def enqueue(self, stream=None):
+        torch = _torch()
+        st_ptr = stream if stream is not None else torch.cuda.current_stream(self.dscene.x0.device).cuda_stream
+        self.ctx._check(lib().stiv_detect_async(self.ctx._h, C.byref(self.scene_struct), C.byref(self.params),
+                                                C.byref(self.result), C.c_void_p(st_ptr)))
+
+    def collect(self, stream=None, to_numpy=True):
+        torch = _torch()
+        st_ptr = stream if stream is not None else torch.cuda.current_stream(self.dscene.x0.device).cuda_stream
+        self.ctx._check(lib().stiv_collect(self.ctx._h, C.byref(self.params), C.byref(self.result),
+                                           C.c_void_p(st_ptr)))
+        res = _collect(self.result, self.outputs, False, to_numpy)
+        res["_struct"] = self.result
+        return res
 
 
 def backward(ctx: Context, dscene: DeviceScene, d, eps, dt, result_struct, dL_dV=None, dL_dG=None, stream=None):
