@@ -997,3 +997,82 @@ void oracle_vt_backward(const double *x0, const double *x1, double s, double d, 
     gx1[k] = gV * creal(b[k]) + cimag(b[k]) / h;
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Training samples for the learned contact-time bracket.                    */
+/* For each candidate key (pair, kind, i, j): 18 features -- the other three */
+/* vertices relative to vertex a (vertex-triangle: b-a, c-a, p-a; edge-edge: */
+/* b-a, c-a, e-a) at t_n then at t_{n+1}, divided by the mean edge length of  */
+/* the primitives at t_n -- and the label: the first root of F in [0,1]      */
+/* (-1 if none, -2 if the vertex starts within d).                           */
+/* ------------------------------------------------------------------------ */
+void oracle_toi_samples(const oracle_scene *S, double d, const int32_t *keys, int64_t n, const int32_t *pair_ab,
+                        const int32_t *pair_shift, float *feat, double *root, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t *key = keys + 4 * k;
+    int p = key[0], kind = key[1], i = key[2], j = key[3];
+    int a = pair_ab[2 * p], b = pair_ab[2 * p + 1];
+    int sc = 0;
+    while (!(a >= S->scene_off[sc] && a < S->scene_off[sc + 1])) ++sc;
+    double sh[3];
+    for (int c = 0; c < 3; ++c) sh[c] = (double)pair_shift[3 * p + c] * S->box_len[3 * sc + c];
+    const double zero[3] = {0, 0, 0};
+    int64_t g[4];
+    const double *shk[4];
+    prim4 P;
+    if (kind == 2) {
+      const int32_t *e0 = S->edge + 2 * ((int64_t)S->edge_off[S->topo_id[a]] + i);
+      const int32_t *e1 = S->edge + 2 * ((int64_t)S->edge_off[S->topo_id[b]] + j);
+      g[0] = S->vtx_off[a] + e0[0]; g[1] = S->vtx_off[a] + e0[1];
+      g[2] = S->vtx_off[b] + e1[0]; g[3] = S->vtx_off[b] + e1[1];
+      shk[0] = shk[1] = zero; shk[2] = shk[3] = sh;
+      P.kind_ee = 1;
+    } else {
+      int vv = kind ? b : a, vt = kind ? a : b;
+      const int32_t *tri = S->tri + 3 * ((int64_t)S->tri_off[S->topo_id[vt]] + j);
+      g[0] = S->vtx_off[vv] + i;
+      for (int r = 0; r < 3; ++r) g[1 + r] = S->vtx_off[vt] + tri[r];
+      shk[0] = kind ? sh : zero;
+      shk[1] = shk[2] = shk[3] = kind ? zero : sh;
+      P.kind_ee = 0;
+    }
+    double shv[4][3];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 3; ++c) shv[r][c] = shk[r][c];
+    load_prim(S, &P, g, shv);
+    /* features: anchor = vertex a of the primitive pair (index 1 for VT, 0 for EE) */
+    int anc = P.kind_ee ? 0 : 1;
+    int others[3];
+    if (P.kind_ee) { others[0] = 1; others[1] = 2; others[2] = 3; }
+    else { others[0] = 2; others[1] = 3; others[2] = 0; }
+    double ell;
+    if (P.kind_ee) {
+      ell = 0.5 * (sqrt(dot(sub(P.X0[1], P.X0[0]), sub(P.X0[1], P.X0[0]))) +
+                   sqrt(dot(sub(P.X0[3], P.X0[2]), sub(P.X0[3], P.X0[2]))));
+    } else {
+      ell = (sqrt(dot(sub(P.X0[2], P.X0[1]), sub(P.X0[2], P.X0[1]))) +
+             sqrt(dot(sub(P.X0[3], P.X0[1]), sub(P.X0[3], P.X0[1]))) +
+             sqrt(dot(sub(P.X0[3], P.X0[2]), sub(P.X0[3], P.X0[2])))) / 3.0;
+    }
+    if (!(ell > 0)) ell = 1.0;
+    for (int t = 0; t < 2; ++t)
+      for (int r = 0; r < 3; ++r) {
+        v3 A = t ? add(P.X0[anc], P.D[anc]) : P.X0[anc];
+        v3 B = t ? add(P.X0[others[r]], P.D[others[r]]) : P.X0[others[r]];
+        v3 rel = sub(B, A);
+        feat[18 * k + 9 * t + 3 * r + 0] = (float)(rel.x / ell);
+        feat[18 * k + 9 * t + 3 * r + 1] = (float)(rel.y / ell);
+        feat[18 * k + 9 * t + 3 * r + 2] = (float)(rel.z / ell);
+      }
+    double gco[4], q[5], f[7];
+    int deg = build_poly(&P, d, gco, q, f);
+    if (d > 0.0 && f[0] < 0.0) { root[k] = -2.0; continue; }
+    double r[8];
+    int nr = roots01(f, deg, r, NULL);
+    root[k] = nr > 0 ? r[0] : -1.0;
+  }
+}

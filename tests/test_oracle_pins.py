@@ -111,6 +111,35 @@ def test_translating_planes_closed_form():
     assert np.allclose(r.ct_tau, s_exact * sc.dt, rtol=0, atol=1e-13)
 
 
+def test_toi_samples_translating_planes():
+    """Training samples of the learned contact-time bracket: every candidate of
+    two translating planes has its first root of F at s* = (gap - d)/closing,
+    and its features are the other vertices relative to the anchor vertex at
+    both times, over the mean edge length of the primitives at t_n."""
+    gap, closing, d = 0.05, 0.1, 0.01
+    sc = T.translating_planes(gap=gap, closing=closing, d=d)
+    feat, root = oracle.toi_samples(sc)
+    r = oracle.detect(sc, emit_candidates=True)
+    assert feat.shape == (len(r.cand), 18)
+    assert np.all(np.abs(root - (gap - d) / closing) <= 1e-12)
+    n_a = sc.vtx_off[1]
+    rng = np.random.default_rng(5)
+    for k in rng.choice(len(r.cand), 40, replace=False):
+        _, kind, i, j = r.cand[k]
+        if kind == 2:
+            ea, eb = sc.topos[0].edge[i], sc.topos[1].edge[j] + n_a
+            ids = [ea[0], ea[1], eb[0], eb[1]]
+            ell = 0.5 * sum(np.linalg.norm(sc.x0[:, q[1]] - sc.x0[:, q[0]]) for q in (ids[:2], ids[2:]))
+            anchor, others = ids[0], ids[1:]
+        else:
+            vv, vt_off, vt_topo = (i, n_a, 1) if kind == 0 else (i + n_a, 0, 0)
+            tri = sc.topos[vt_topo].tri[j] + vt_off
+            ell = np.mean([np.linalg.norm(sc.x0[:, tri[u]] - sc.x0[:, tri[(u + 1) % 3]]) for u in range(3)])
+            anchor, others = tri[0], [tri[1], tri[2], vv]
+        want = np.concatenate([(X[:, others] - X[:, [anchor]]).T.ravel() / ell for X in (sc.x0, sc.x1)])
+        assert np.allclose(feat[k], want, rtol=1e-6, atol=1e-6)
+
+
 def test_translating_planes_vt_set_geometric():
     """Each vertex of the moving square whose projection is strictly inside
     the fixed square has exactly one (or on a diagonal, two) VT contacts."""
