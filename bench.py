@@ -28,6 +28,16 @@ BYTES_PER_VERTEX_BOXES = 48.0       # X0 and X1, 3 doubles each, read once by th
 BYTES_PER_BOX_OUT = 48.0            # 6 doubles per vesicle or patch box written
 FLOPS_PER_CANDIDATE = 152.0         # coefficients of F = g^2 - d^2 q (counted from the formulas)
 FLOPS_PER_VT_CONTACT = 300.0        # volume and gradient of one vertex-triangle contact
+OPS_PER_BOX_TEST = 6.0              # 3 axes x 2 interval-end comparisons of two FP32 boxes
+LDS_BYTES_PER_BOX_TEST = 48.0       # two 6-float boxes read from LDS
+# One VALU lane-operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (an FP32 compare or an FP64 add/mul each take one; FMA and packed FP32 double it).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS: 128 bytes per clock per CU
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE + WRITE_SIZE on this workload,
+# scaled by the copy-kernel calibration factor (kept with the profile summaries)
+TRAFFIC_BYTES = {}
 
 
 def log(msg):
@@ -42,6 +52,9 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--plain-only", action="store_true", help="skip the learned-bracket timing")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the contact path here runs on a single MI355X "
@@ -53,6 +66,16 @@ def main():
 
     from paper_1812_04719_amd import scenes, stiv
 
+    if args.copy_probe:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "copy_probe_bytes_written": y.numel() * 8,
+                          "launches": 3}), flush=True)
+        return
+
     t0 = time.time()
     sc = scenes.make_config(args.config)
     log("scene: %d vesicles, %d vertices, %d triangles (%.1fs)" % (sc.n_ves, sc.n_vtx, sc.n_tri(), time.time() - t0))
@@ -62,18 +85,38 @@ def main():
     outs = None
     res, outs = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False)
     # stage times measured by the library with HIP events on the same stream
-    stage_sum = np.zeros(7)
-    for _ in range(args.warmup):
-        res, outs = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        res, outs = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False)
-        stage_sum += np.array(ctx.stage_times())
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
+    def timed(learned):
+        st_sum = np.zeros(7)
+        r = None
+        for _ in range(args.warmup):
+            r, _o = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False, learned_bracket=learned)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for _ in range(args.steps):
+            r, _o = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False, learned_bracket=learned)
+            st_sum += np.array(ctx.stage_times())
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t_a, st_sum / args.steps, ctx.stats()
+
+    res, t_total, stages, work = timed(False)
+    learned = None
+    from paper_1812_04719_amd import toi_model
+    if os.path.exists(toi_model.DEFAULT_WEIGHTS) and not args.plain_only:
+        toi_model.install(ctx)
+        res_l, t_l, stages_l, work_l = timed(True)
+        same = bool(torch.equal(res_l["ct_key"], res["ct_key"]))
+        learned = {"ms_per_step": round(1e3 * t_l / args.steps, 4),
+                   "narrow_ms": round(float(stages_l[4]), 4), "narrow_ms_plain": round(float(stages[4]), 4),
+                   "narrow_speedup": round(float(stages[4] / stages_l[4]), 4),
+                   "bracket_certified": int(work_l["bracket_certified"]),
+                   "root_searches": int(work_l["root_searches"]), "same_contacts": same}
+        log("learned bracket: %s" % learned)
+        if not same:
+            raise SystemExit("learned bracket changed the contact set")
+        if t_l < t_total:
+            res, t_total, stages, work = res_l, t_l, stages_l, work_l
+    mode = "learned" if (learned and t_total == t_l) else "plain"
     ms_step = 1e3 * t_total / args.steps
-    stages = stage_sum / args.steps
     n_cand = res["n_cand_vt"] + res["n_cand_ee"]
     n_ct = res["n_ct"]
     pairs_per_s = n_cand / (ms_step * 1e-3)
@@ -82,12 +125,10 @@ def main():
              "aggregation", "device_total"]
     stage_ms = {n: round(float(v), 4) for n, v in zip(names, stages)}
     log("stages (ms): %s" % stage_ms)
-    work = ctx.stats()
     log("work: %s" % work)
 
-    # roofline of the dominant kernel
-    n_patches = int(sum(ctx_patch for ctx_patch in [0]))  # patch boxes: counted below
-    per_topo_patches = None
+    # roofline of the dominant kernel (k_prim_cand: primitive box-pair sweep,
+    # exact FP64 box test and polynomial screen of every candidate)
     dom = int(np.argmax(stages[:6]))
     if dom == 0:
         n_patch_boxes = sc.n_ves * math.ceil(sc.topos[0].nt / 64)
@@ -96,12 +137,21 @@ def main():
         roof = {"kernel": "k_boxes", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     else:
-        flops = FLOPS_PER_CANDIDATE * n_cand + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
-        t_k = stages[4] * 1e-3
-        achieved = flops / t_k / 1e12
-        roof = {"kernel": "k_narrow", "stage": names[dom], "bound": "alu", "achieved": round(achieved, 3),
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None}
+        kern = {3: "k_prim_cand", 4: "k_narrow"}.get(dom, names[dom])
+        if dom == 3:
+            ops = OPS_PER_BOX_TEST * work["box_tests"] + FLOPS_PER_CANDIDATE * n_cand
+        else:
+            ops = FLOPS_PER_CANDIDATE * n_cand + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
+        achieved = ops / (stages[dom] * 1e-3) / 1e12
+        roof = {"kernel": kern, "stage": names[dom], "bound": "alu", "achieved": round(achieved, 4),
+                "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": TRAFFIC_BYTES.get(kern), "ops_per_launch": int(ops),
+                "avg_launch_ms": round(float(stages[dom]), 4)}
+        if dom == 3:
+            # the sweep reads two 24-byte boxes from LDS per test
+            lds = LDS_BYTES_PER_BOX_TEST * work["box_tests"] / (stages[dom] * 1e-3) / 1e12
+            roof["lds_tbs"] = round(lds, 3)
+            roof["lds_frac"] = round(lds / LDS_PEAK_TBS, 4)
 
     out = {
         "metric": METRIC,
@@ -126,6 +176,8 @@ def main():
         "stages_ms": stage_ms,
         "work": work,
         "roofline": roof,
+        "toi_search": mode,
+        "learned_vs_plain": learned,
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -91,7 +91,10 @@ typedef struct {
 
 /* d: minimum separation of the triangle meshes, (1 + 2 alpha) d_m (Sec. 3.1.2);
  * eps: velocity scale of the space-time metric (App. A), > 0; dt: time step, > 0. */
-enum { STIV_EMIT_CANDIDATES = 1u };
+/* flags: STIV_EMIT_CANDIDATES also writes the list of primitive candidates;
+ * STIV_LEARNED_BRACKET searches each root first inside the bracket predicted
+ * by the model set with stiv_set_toi_model (same contacts, see there). */
+enum { STIV_EMIT_CANDIDATES = 1u, STIV_LEARNED_BRACKET = 2u };
 typedef struct {
   double d, eps, dt;
   uint32_t flags;
@@ -199,14 +202,65 @@ stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n);
 /* Work counts of the last detect (diagnostics, tuning): 0 check points,
  * 1 candidate vesicle pairs, 2 patch-pair work items, 3 FP32 pre-candidates
  * (a superset of the candidates), 4 vertex-triangle candidates, 5 edge-edge
- * candidates, 6 candidates whose polynomial needed a root search, 7 contacts.
- * Fills min(n, 8) values. */
+ * candidates, 6 candidates whose polynomial needed a root search, 7 contacts,
+ * 8 primitive box-pair tests made by the candidate sweep, 9 root searches
+ * whose learned bracket was certified (STIV_LEARNED_BRACKET).
+ * Fills min(n, 10) values. */
 stiv_status stiv_get_stats(stiv_ctx *ctx, int64_t *vals, int n);
 
 /* Device pointers to the library's internal Morton sort (tests only need
  * it for the worked example of Alg. 1 / Table 3): stable sort of n 64-bit
  * keys with 32-bit values, ascending, equal keys keep input order. */
 stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned contact-time bracket (a learned heuristic on top of the root search
+ * of Eq. 3.1, not part of the paper's method; it never changes results).
+ *
+ * Model: perceptron 18 -> 64 -> 64 -> 2 with ReLU, evaluated with bf16
+ * weights and activations and FP32 accumulation.  Parameters, FP32, flat:
+ * W1[18][64] b1[64] W2[64][64] b2[64] W3[64][2] b3[2] (y = x W + b).
+ * Input features of a candidate: the other three vertices relative to the
+ * first vertex of the triangle (vertex-triangle: b - a, c - a, p - a) or of
+ * the first edge (edge-edge: b - a, c - a, e - a), at t_n then at t_{n+1}
+ * (images shifted by sigma L), divided by the mean edge length of the two
+ * primitives at t_n.  Outputs o: predicted first root mu = sigmoid(o0) in
+ * [0,1] and spread sd = softplus(o1) + 1e-3.  Training loss per sample with
+ * first root s: 0.5 ((s - mu) / sd)^2 + log sd (Gaussian negative
+ * log-likelihood), averaged over the samples.
+ * ------------------------------------------------------------------------- */
+
+/* Number of model parameters (5506). */
+int stiv_mlp_nparam(void);
+
+/* Install (copy from HOST memory) the model used with STIV_LEARNED_BRACKET;
+ * params NULL removes it.  The search of a candidate then starts in
+ * [mu - kwidth sd, mu + kwidth sd] clipped to [0,1]: when the Bernstein
+ * coefficients of F on [0, lo] all have one strict sign there is no root
+ * before lo and the earliest valid root is the first found in [lo, hi], else
+ * in [hi, 1]; otherwise all of [0,1] is searched.  Contacts, their times (up
+ * to the final rounding of the refinement) and all other outputs are those
+ * of the search without the model.  E_ARG: n != stiv_mlp_nparam(), kwidth
+ * <= 0 or a non-finite parameter. */
+stiv_status stiv_set_toi_model(stiv_ctx *ctx, const float *params, int n, float kwidth);
+
+/* Model outputs o [n][2] (raw, before the head) for features x [n][18];
+ * all DEVICE pointers, asynchronous on stream. */
+stiv_status stiv_mlp_forward(stiv_ctx *ctx, const float *params, const float *x, int64_t n, float *out, void *stream);
+
+/* Gradient of the mean training loss over n samples (features x [n][18],
+ * targets [n] in [0,1]) with respect to the parameters, into grad
+ * [stiv_mlp_nparam()]; the mean loss into *loss (may be NULL).  Backward
+ * products also run on bf16 tiles with FP32 accumulation; the cross-workgroup
+ * sum is in a fixed order.  DEVICE pointers, asynchronous on stream; uses a
+ * scratch buffer owned by ctx (calls on one ctx must not overlap). */
+stiv_status stiv_mlp_grad(stiv_ctx *ctx, const float *params, const float *x, const float *target, int64_t n,
+                          float *grad, float *loss, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on params with moments m, v,
+ * all [stiv_mlp_nparam()] FP32 DEVICE arrays, asynchronous on stream. */
+stiv_status stiv_mlp_adam(stiv_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t step, float lr,
+                          float beta1, float beta2, float eps, void *stream);
 
 /* Message of the last error on this context (never NULL). */
 const char *stiv_last_error(const stiv_ctx *ctx);

@@ -75,7 +75,7 @@ def lib():
             L.oracle_vt_grad_full.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
                                               C.c_void_p, C.c_void_p, C.c_void_p]
             L.oracle_toi_samples.argtypes = [C.POINTER(_Scene), C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
-                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
             L.oracle_vt_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
                                              C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
             _lib = L
@@ -242,17 +242,19 @@ def vt_backward(x0, x1, s, d, eps, dt, gV, w):
 def toi_samples(scene, d=None, threads=0):
     """Training samples of the learned contact-time bracket for every
     primitive candidate of the scene: (features [n,18] float32, first root of
-    F in [0,1] [n] float64, -1 none, -2 starts within d)."""
+    F in [0,1] [n] float64, -1 none; hard [n] bool: the
+    Bernstein coefficients of F on [0,1] do not exclude a root)."""
     d = scene.d if d is None else d
     r = detect(scene, d=d, emit_candidates=True, threads=threads)
     keys = np.ascontiguousarray(r["cand"], dtype=np.int32)
     n = keys.shape[0]
     feat = np.zeros((n, 18), dtype=np.float32)
     root = np.zeros(n, dtype=np.float64)
+    hard = np.zeros(n, dtype=np.int8)
     s, keep = _scene_struct(scene)
     pab = np.ascontiguousarray(r["pair_ab"], dtype=np.int32)
     psh = np.ascontiguousarray(r["pair_shift"], dtype=np.int32)
     lib().oracle_toi_samples(C.byref(s), float(d), _ptr(keys), n, _ptr(pab), _ptr(psh), _ptr(feat), _ptr(root),
-                             int(threads))
+                             _ptr(hard), int(threads))
     del keep
-    return feat, root
+    return feat, root, hard.astype(bool)

@@ -1004,10 +1004,18 @@ void oracle_vt_backward(const double *x0, const double *x1, double s, double d, 
 /* vertices relative to vertex a (vertex-triangle: b-a, c-a, p-a; edge-edge: */
 /* b-a, c-a, e-a) at t_n then at t_{n+1}, divided by the mean edge length of  */
 /* the primitives at t_n -- and the label: the first root of F in [0,1]      */
-/* (-1 if none, -2 if the vertex starts within d).                           */
+/* (-1 if none).  hard[k] = 1 unless the                                     */
+/* Bernstein coefficients of F on [0,1] are all positive (d > 0) or all of   */
+/* one strict sign (d = 0), which excludes any root without a search.        */
 /* ------------------------------------------------------------------------ */
+static double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+  return r;
+}
+
 void oracle_toi_samples(const oracle_scene *S, double d, const int32_t *keys, int64_t n, const int32_t *pair_ab,
-                        const int32_t *pair_shift, float *feat, double *root, int nthreads) {
+                        const int32_t *pair_shift, float *feat, double *root, int8_t *hard, int nthreads) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
@@ -1070,7 +1078,17 @@ void oracle_toi_samples(const oracle_scene *S, double d, const int32_t *keys, in
       }
     double gco[4], q[5], f[7];
     int deg = build_poly(&P, d, gco, q, f);
-    if (d > 0.0 && f[0] < 0.0) { root[k] = -2.0; continue; }
+    {
+      /* Bernstein coefficients on [0,1]: b_j = sum_{i<=j} C(j,i)/C(deg,i) f_i */
+      int pos = 1, neg = 1;
+      for (int j = 0; j <= deg; ++j) {
+        double bj = 0.0;
+        for (int i = 0; i <= j; ++i) bj += binom(j, i) / binom(deg, i) * f[i];
+        pos &= bj > 0.0;
+        neg &= bj < 0.0;
+      }
+      hard[k] = (int8_t)!(pos || (d == 0.0 && neg));
+    }
     double r[8];
     int nr = roots01(f, deg, r, NULL);
     root[k] = nr > 0 ? r[0] : -1.0;

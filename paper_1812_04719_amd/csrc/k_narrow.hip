@@ -25,6 +25,15 @@
 // U = D_p / dt; the gradient w.r.t. X1 (X0 fixed) adds the explicit
 // dependence through P(s*) and U to dV/ds * ds/dX1, with ds/dX1 from the
 // implicit function theorem on F(s*, X1) = 0.
+//
+// Learned bracket (optional): a small perceptron (mlp_tile.h) predicts the
+// contact time of each queued candidate from its shape (the other three
+// vertices relative to the first vertex of the triangle, resp. of the first
+// edge, at both ends of the step, over the mean edge length at t_n).  The
+// search then certifies [0, lo) root-free with one Bernstein test and looks
+// in [lo, hi] first (earliest_bracket in narrow_math.h); the contacts found
+// are the same as without the prediction.
+#include "mlp_tile.h"
 #include "narrow_math.h"
 
 namespace stiv {
@@ -95,16 +104,62 @@ __device__ inline bool load_quad(const DevScene &S, const PairRec &pr, const int
   return l0.x <= u1.x && l1.x <= u0.x && l0.y <= u1.y && l1.y <= u0.y && l0.z <= u1.z && l1.z <= u0.z;
 }
 
+__device__ inline double len3(const d3 &v) { return sqrt(dotp(v, v)); }
+
+// Features of the learned bracket from the candidate's positions (selects,
+// not indices, pick the vertices so that Q stays in registers).
+__device__ inline void bracket_features(const Quad &Q, float out[mlp::kIn]) {
+  const bool ee = Q.ee;
+  double ell;
+  if (ee) {
+    ell = 0.5 * (len3(Q.X0[1] - Q.X0[0]) + len3(Q.X0[3] - Q.X0[2]));
+  } else {
+    ell = (len3(Q.X0[2] - Q.X0[1]) + len3(Q.X0[3] - Q.X0[1]) + len3(Q.X0[3] - Q.X0[2])) / 3.0;
+  }
+  const double inv = ell > 0.0 ? 1.0 / ell : 1.0;
+  const d3 A0 = ee ? Q.X0[0] : Q.X0[1], AD = ee ? Q.D[0] : Q.D[1];
+  const d3 P0[3] = {ee ? Q.X0[1] : Q.X0[2], ee ? Q.X0[2] : Q.X0[3], ee ? Q.X0[3] : Q.X0[0]};
+  const d3 PD[3] = {ee ? Q.D[1] : Q.D[2], ee ? Q.D[2] : Q.D[3], ee ? Q.D[3] : Q.D[0]};
+  const d3 A1 = A0 + AD;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const d3 a = P0[r] - A0;
+    const d3 b = (P0[r] + PD[r]) - A1;
+    out[3 * r + 0] = (float)(a.x * inv);
+    out[3 * r + 1] = (float)(a.y * inv);
+    out[3 * r + 2] = (float)(a.z * inv);
+    out[9 + 3 * r + 0] = (float)(b.x * inv);
+    out[9 + 3 * r + 1] = (float)(b.y * inv);
+    out[9 + 3 * r + 2] = (float)(b.z * inv);
+  }
+}
+
+struct BracketLds {
+  mlp::Weights W;
+  unsigned short x[256][mlp::kInP];
+  mlp::Act act[4];
+  float br[256][2];
+};
+
 // Root search on the queued candidates, then volume and gradient on contact.
-template <int N>
+// LEARNED: the bracket of every candidate is predicted first (all 256
+// candidates of the workgroup through the perceptron on the matrix cores).
+template <int N, bool LEARNED>
 __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const PairRec *pairs, const Cand *hard,
                                                 int64_t hard_cap, double d, double eps,
                                                 double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                                                int64_t ct_cap, Counters *cnt) {
+                                                int64_t ct_cap, const float *mlp_params, float kwidth,
+                                                Counters *cnt) {
   int64_t nc = (int64_t)cnt->n_hard;
   nc = nc < hard_cap ? nc : hard_cap;
-  int within = 0, deg = 0;
+  int within = 0, deg = 0, cert = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  extern __shared__ char dyn_lds[];
+  BracketLds &L = *reinterpret_cast<BracketLds *>(dyn_lds);
+  if (LEARNED) {
+    if ((int64_t)blockIdx.x * blockDim.x >= nc) return;  // whole workgroup idle: uniform exit
+    mlp::stage_weights(L.W, mlp_params);
+  }
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {
     const int64_t i = base + threadIdx.x;
     int hit = 0;
@@ -112,17 +167,57 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
     Cand c;
     c.pair = c.kind = c.i = c.j = 0;
     for (int k = 0; k < 12; ++k) g[k] = 0.0;
+    Quad Q;
+    PairRec pr;
+    int64_t gid[4];
+    int side[4];
     if (i < nc) {
       c = hard[i];
-      const PairRec pr = pairs[c.pair];
-      int64_t gid[4];
-      int side[4];
+      pr = pairs[c.pair];
       cand_vertices(S, T, pr, c, gid, side);
-      Quad Q;
+    }
+    if (LEARNED) {
+      // features first; the positions are loaded again for the search so that
+      // they are not live (spilled) across the perceptron
+      {
+        float ft[mlp::kIn];
+        if (i < nc) {
+          Quad Qf;
+          load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Qf);
+          bracket_features(Qf, ft);
+        } else {
+#pragma unroll
+          for (int k = 0; k < mlp::kIn; ++k) ft[k] = 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < mlp::kInP; ++k) L.x[threadIdx.x][k] = k < mlp::kIn ? mlp::f2bf(ft[k]) : 0;
+      }
+      __syncthreads();
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      for (int q = 0; q < 4; ++q) {
+        const int row0 = 64 * wave + 16 * q;
+        const mlp::f32x4 o = mlp::forward16(L.W, &L.x[row0][0], L.act[wave]);
+        const int col = lane & 15, gq = lane >> 4;
+        if (col < 2)
+          for (int j = 0; j < 4; ++j) L.br[row0 + 4 * gq + j][col] = o[j];
+        __syncthreads();
+      }
+      if (i < nc) {
+        load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Q);
+        const float mu = mlp::head_mu(L.br[threadIdx.x][0]), sd = mlp::head_sd(L.br[threadIdx.x][1]);
+        double lo = (double)mu - (double)kwidth * (double)sd, hi = (double)mu + (double)kwidth * (double)sd;
+        lo = lo < 0.0 ? 0.0 : lo;
+        hi = hi > 1.0 ? 1.0 : hi;
+        int certified = 0;
+        hit = earliest_bracket<N>(Q, d, lo, hi, &s, &within, &deg, &certified);
+        cert += certified;
+      }
+      __syncthreads();
+    } else if (i < nc) {
       load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Q);
       hit = earliest<N>(Q, d, &s, &within, &deg);
-      if (hit && !Q.ee) volume_grad(Q, s, d, eps, dt, s == 0.0, &V, g);
     }
+    if (hit && !Q.ee) volume_grad(Q, s, d, eps, dt, s == 0.0, &V, g);
     const unsigned long long m = __ballot(hit != 0);
     const int nh = __popcll(m);
     const int leader = m ? __ffsll((long long)m) - 1 : 0;
@@ -146,6 +241,7 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
   }
   if (within) atomicAdd(&cnt->within_d, (unsigned long long)within);
   if (deg) atomicAdd(&cnt->degenerate, (unsigned long long)deg);
+  if (LEARNED && cert) atomicAdd(&cnt->n_bracket_ok, (unsigned long long)cert);
 }
 
 }  // namespace
@@ -159,13 +255,24 @@ static int grid_for(int64_t n, int max_blocks) {
 
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, Counters *cnt, hipStream_t st) {
-  if (d == 0.0)
-    k_narrow<3><<<grid_for(hard_cap, blocks), 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
-                                                    ct_grad, ct_cap, cnt);
-  else
-    k_narrow<6><<<grid_for(hard_cap, blocks), 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol,
-                                                    ct_grad, ct_cap, cnt);
+                   int64_t ct_cap, const float *mlp_params, float kwidth, Counters *cnt, hipStream_t st) {
+  const int g = grid_for(hard_cap, blocks);
+  const size_t lds = sizeof(BracketLds);
+  if (mlp_params) {
+    if (d == 0.0)
+      k_narrow<3, true><<<g, 256, lds, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+                                            mlp_params, kwidth, cnt);
+    else
+      k_narrow<6, true><<<g, 256, lds, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+                                            mlp_params, kwidth, cnt);
+  } else {
+    if (d == 0.0)
+      k_narrow<3, false><<<g, 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+                                           nullptr, 0.0f, cnt);
+    else
+      k_narrow<6, false><<<g, 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+                                           nullptr, 0.0f, cnt);
+  }
 }
 
 }  // namespace stiv

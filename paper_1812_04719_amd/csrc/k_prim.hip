@@ -306,7 +306,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   const double h = 0.5 * d;
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
-  unsigned long long nvt = 0, nee = 0;
+  unsigned long long nvt = 0, nee = 0, ntests = 0;
   for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
     const uint64_t wr = work[w];
     const int p = (int)(wr >> 32);
@@ -393,6 +393,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
       // all left x right pairs, 64 per round; t = x * nr + y, with x = t / nr
       // as (t * ceil(2^32 / nr)) >> 32, exact for t < 2^16 (t <= 128 * 128 here)
       const int tot = nl * nr;
+      ntests += (unsigned long long)tot;
       const unsigned long long magic = nr ? ((1ull << 32) + (unsigned long long)nr - 1ull) / (unsigned long long)nr : 0ull;
       for (int t0 = 0; t0 < tot; t0 += 64) {
         const unsigned int t = (unsigned int)(t0 + lane);
@@ -423,6 +424,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   if (lane == 0) {
     if (nvt) atomicAdd(&cnt->n_cand_vt, nvt);
     if (nee) atomicAdd(&cnt->n_cand_ee, nee);
+    if (ntests) atomicAdd(&cnt->n_tests, ntests);
   }
 }
 

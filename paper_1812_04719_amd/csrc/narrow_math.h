@@ -153,35 +153,29 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
   return x;
 }
 
-// Earliest valid root of F (degree N).  Returns 1 with *s on contact.
-// *deg counts degenerate skips (vanishing normal at a root, F == 0, or a
-// polynomial that stays zero up to rounding over a whole interval).
+// Earliest valid root of F (degree N, coefficients f) in [lo, hi] by
+// depth-first Bernstein subdivision of that interval into the pieces
+// lo + (hi - lo) [idx 2^-level, (idx + 1) 2^-level].  Returns 1 with *s_out on
+// contact.  *visits counts the intervals examined (shared budget across
+// calls); *deg counts degenerate skips.
 template <int N>
-__host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *within, int *deg) {
-  double f[N + 1];
-  poly_coeffs<N>(Q, d, f);
-  bool allzero = true;
-#pragma unroll
-  for (int k = 0; k <= N; ++k) allzero &= (f[k] == 0.0);
-  if (allzero) { (*deg)++; return 0; }
-  if (N == 6 && f[0] < 0.0 && inside_at(Q, 0.0) == 1) {
-    (*within)++;
-    *s_out = 0.0;
-    return 1;
-  }
+__host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double lo, double hi, double *s_out,
+                                  int *visits, int *deg) {
   const int kMaxLevel = 44;
   const int kMaxVisits = 4096;
-  int level = 0, visits = 0;
+  const double span = hi - lo;
+  int level = 0;
   long long idx = 0;
   while (true) {
-    if (++visits > kMaxVisits) {
+    if (++(*visits) > kMaxVisits) {
       (*deg)++;
       return 0;
     }
     const double wd = ldexp(1.0, -level);
-    const double u = (double)idx * wd;
+    const double u = lo + span * ((double)idx * wd);
+    const double v = lo + span * ((double)(idx + 1) * wd);
     double b[N + 1];
-    bernstein_on<N>(f, u, wd, b);
+    bernstein_on<N>(f, u, v - u, b);
     bool pos = true, neg = true;
     int changes = 0, last = 0;
 #pragma unroll
@@ -196,7 +190,6 @@ __host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *wi
     }
     bool descend = false;
     if (!(pos || neg)) {
-      const double v = u + wd;
       const double fu = horner<N>(f, u), fv = horner<N>(f, v);
       double root = -1.0;
       if (changes == 1 && b[0] != 0.0 && b[N] != 0.0 && fu != 0.0 && fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
@@ -226,6 +219,77 @@ __host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *wi
     while (level > 0 && (idx & 1)) { idx >>= 1; --level; }
     if (level == 0) break;
     ++idx;
+  }
+  return 0;
+}
+
+// Coefficients of F and the two cases settled before any search: F == 0
+// identically (degenerate, returns 0) and a vertex within d and inside at
+// s = 0 (contact at 0, returns 1).  Returns -1 when a search is needed.
+template <int N>
+__host__ __device__ inline int prepare(const Quad &Q, double d, double f[N + 1], double *s_out, int *within,
+                                       int *deg) {
+  poly_coeffs<N>(Q, d, f);
+  bool allzero = true;
+#pragma unroll
+  for (int k = 0; k <= N; ++k) allzero &= (f[k] == 0.0);
+  if (allzero) { (*deg)++; return 0; }
+  if (N == 6 && f[0] < 0.0 && inside_at(Q, 0.0) == 1) {
+    (*within)++;
+    *s_out = 0.0;
+    return 1;
+  }
+  return -1;
+}
+
+// Earliest valid root of F (degree N) on [0,1].  Returns 1 with *s on contact.
+// *deg counts degenerate skips (vanishing normal at a root, F == 0, or a
+// polynomial that stays zero up to rounding over a whole interval).
+template <int N>
+__host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *within, int *deg) {
+  double f[N + 1];
+  const int pre = prepare<N>(Q, d, f, s_out, within, deg);
+  if (pre >= 0) return pre;
+  int visits = 0;
+  return search_in<N>(Q, f, 0.0, 1.0, s_out, &visits, deg);
+}
+
+// The same earliest valid root, searched first inside a predicted bracket
+// [lo, hi] of [0,1]: when the Bernstein coefficients of F on [0, lo] all have
+// one strict sign, F has no root before lo, so the earliest valid root is
+// the first one found in [lo, hi], else in [hi, 1].  Without that
+// certificate the whole of [0,1] is searched.  The result is the root of
+// earliest() (up to the last bits of the final refinement, which starts
+// from a different enclosing interval).  *certified reports the path taken.
+template <int N>
+__host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, double hi, double *s_out, int *within,
+                                         int *deg, int *certified) {
+  double f[N + 1];
+  const int pre = prepare<N>(Q, d, f, s_out, within, deg);
+  *certified = 0;
+  if (pre >= 0) return pre;
+  // the intervals to search, in order: [lo, hi] then [hi, 1] when [0, lo) is
+  // certified root-free, else [0, 1] alone (one call site keeps the search inline)
+  bool ok = lo >= 0.0 && lo < hi && hi <= 1.0;
+  if (ok && lo > 0.0) {
+    double b[N + 1];
+    bernstein_on<N>(f, 0.0, lo, b);
+    bool pos = true, neg = true;
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      pos &= b[k] > 0.0;
+      neg &= b[k] < 0.0;
+    }
+    ok = pos || neg;
+  }
+  *certified = ok ? 1 : 0;
+  double a0 = ok ? lo : 0.0, a1 = ok ? hi : 1.0;
+  const int parts = (ok && hi < 1.0) ? 2 : 1;
+  int visits = 0;
+  for (int part = 0; part < parts; ++part) {
+    if (search_in<N>(Q, f, a0, a1, s_out, &visits, deg)) return 1;
+    a0 = a1;
+    a1 = 1.0;
   }
   return 0;
 }

@@ -89,7 +89,9 @@ struct Counters {
   unsigned long long n_vol, n_jrow;
   unsigned long long within_d, degenerate;
   unsigned long long hash_overflow, shift_overflow, nonfinite, lds_fallback;
-  unsigned long long pad[1];
+  unsigned long long n_tests;      // primitive box-pair tests of the candidate sweep
+  unsigned long long n_bracket_ok;  // root searches whose predicted bracket was certified
+  unsigned long long pad[2];
 };
 
 // Narrow-phase candidate record.
@@ -148,7 +150,16 @@ void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T,
 // K3 + K4: root search on the queued candidates, volumes and gradients
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, Counters *cnt, hipStream_t st);
+                   int64_t ct_cap, const float *mlp_params, float kwidth, Counters *cnt, hipStream_t st);
+
+// Learned contact-time bracket (perceptron kernels)
+int mlp_nparam();
+void launch_mlp_forward(const float *params, const float *x, int64_t n, float *out, hipStream_t st);
+int mlp_grad_blocks(int64_t n);
+void launch_mlp_grad(const float *params, const float *x, const float *target, int64_t n, float *part, float *grad,
+                     float *loss, hipStream_t st);
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t step, float lr, float b1, float b2, float eps,
+                 hipStream_t st);
 
 // K5
 void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st);

@@ -69,6 +69,10 @@ struct stiv_ctx {
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
       row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx;
+  // learned contact-time bracket: FP32 parameters on the device, width in units of sd
+  Buf toi_params, mlp_part;
+  bool have_model = false;
+  float toi_kwidth = 3.0f;
   int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0, cap_list = 0;
   int64_t arena_n_ves = 0, arena_max_patches = 0;
   Counters *h_cnt = nullptr;  // pinned
@@ -137,6 +141,7 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
                 &ctx->cand_list, &ctx->ct,
+                &ctx->toi_params, &ctx->mlp_part,
                 &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
                 &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
                 &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv,
@@ -409,6 +414,8 @@ static stiv_status check_args(stiv_ctx *ctx, const stiv_scene *s, const stiv_par
   if (s->n_ves >= (1 << 24)) return fail(ctx, STIV_E_ARG, "at most 2^24 - 1 vesicles");
   if (s->n_ves > 0 && (!s->vtx_off || !s->topo_id || !s->scene_off || !s->box_len || !s->x0 || !s->x1))
     return fail(ctx, STIV_E_ARG, "null scene array");
+  if ((p->flags & STIV_LEARNED_BRACKET) && !ctx->have_model)
+    return fail(ctx, STIV_E_STATE, "STIV_LEARNED_BRACKET needs a model (stiv_set_toi_model)");
   return STIV_OK;
 }
 
@@ -517,7 +524,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_narrow(ctx->narrow_blocks, S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps,
                 p->dt,
                 P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
-                cnt, st);
+                (p->flags & STIV_LEARNED_BRACKET) ? P<float>(ctx->toi_params) : nullptr, ctx->toi_kwidth, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
   launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
@@ -751,9 +758,11 @@ stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch) {
 stiv_status stiv_get_stats(stiv_ctx *ctx, int64_t *vals, int n) {
   if (!ctx || !vals) return STIV_E_ARG;
   const Counters &c = *ctx->h_cnt;
-  const int64_t v[8] = {(int64_t)c.n_cp, (int64_t)c.n_pairs, (int64_t)c.n_work, (int64_t)c.n_pre,
-                        (int64_t)c.n_cand_vt, (int64_t)c.n_cand_ee, (int64_t)c.n_hard, (int64_t)c.n_ct};
-  for (int k = 0; k < n && k < 8; ++k) vals[k] = v[k];
+  const int64_t v[10] = {(int64_t)c.n_cp,      (int64_t)c.n_pairs,   (int64_t)c.n_work,
+                         (int64_t)c.n_pre,     (int64_t)c.n_cand_vt, (int64_t)c.n_cand_ee,
+                         (int64_t)c.n_hard,    (int64_t)c.n_ct,      (int64_t)c.n_tests,
+                         (int64_t)c.n_bracket_ok};
+  for (int k = 0; k < n && k < 10; ++k) vals[k] = v[k];
   return STIV_OK;
 }
 
@@ -766,6 +775,57 @@ stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, i
   launch_radix_sort_u64(keys, vals, P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), nullptr, n, 64, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
+  return STIV_OK;
+}
+
+int stiv_mlp_nparam(void) { return mlp_nparam(); }
+
+stiv_status stiv_set_toi_model(stiv_ctx *ctx, const float *params, int n, float kwidth) {
+  if (!ctx) return STIV_E_ARG;
+  if (!params) {
+    ctx->have_model = false;
+    return STIV_OK;
+  }
+  if (n != mlp_nparam()) return fail(ctx, STIV_E_ARG, "model must have stiv_mlp_nparam() parameters");
+  if (!(kwidth > 0.0f) || !std::isfinite(kwidth)) return fail(ctx, STIV_E_ARG, "bracket width must be finite and > 0");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return fail(ctx, STIV_E_ARG, "model parameters must be finite");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(ensure(ctx->toi_params, sizeof(float) * (size_t)n));
+  HIPCHK(hipMemcpy(ctx->toi_params.p, params, sizeof(float) * (size_t)n, hipMemcpyHostToDevice));
+  ctx->toi_kwidth = kwidth;
+  ctx->have_model = true;
+  return STIV_OK;
+}
+
+stiv_status stiv_mlp_forward(stiv_ctx *ctx, const float *params, const float *x, int64_t n, float *out, void *stream) {
+  if (!ctx || n < 0 || !params || (n > 0 && (!x || !out))) return fail(ctx, STIV_E_ARG, "bad mlp_forward arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_mlp_forward(params, x, n, out, reinterpret_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return STIV_OK;
+}
+
+stiv_status stiv_mlp_grad(stiv_ctx *ctx, const float *params, const float *x, const float *target, int64_t n,
+                          float *grad, float *loss, void *stream) {
+  if (!ctx || n < 0 || !params || !grad || (n > 0 && (!x || !target)))
+    return fail(ctx, STIV_E_ARG, "bad mlp_grad arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t need = sizeof(float) * (size_t)mlp_grad_blocks(n) * (size_t)(mlp_nparam() + 1);
+  HIPCHK(ensure(ctx->mlp_part, need));
+  launch_mlp_grad(params, x, target, n, P<float>(ctx->mlp_part), grad, loss, reinterpret_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return STIV_OK;
+}
+
+stiv_status stiv_mlp_adam(stiv_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t step, float lr,
+                          float beta1, float beta2, float eps, void *stream) {
+  if (!ctx || !params || !grad || !m || !v || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(ctx, STIV_E_ARG, "bad adam arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_adam(params, grad, m, v, step, lr, beta1, beta2, eps, reinterpret_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
   return STIV_OK;
 }
 

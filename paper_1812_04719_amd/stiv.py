@@ -17,16 +17,17 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstiv.so")
 
 STIV_OK, STIV_E_ARG, STIV_E_CAPACITY, STIV_E_HIP, STIV_E_NUMERIC, STIV_E_STATE = 0, -1, -2, -3, -4, -5
-STIV_EMIT_CANDIDATES = 1
+STIV_EMIT_CANDIDATES, STIV_LEARNED_BRACKET = 1, 2
 STIV_OPT_PATCH_TRI, STIV_OPT_PRIM_BLOCKS, STIV_OPT_NARROW_BLOCKS = 1, 2, 3
 _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HIP", -4: "STIV_E_NUMERIC",
            -5: "STIV_E_STATE"}
 
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
            "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_detect_async",
-           "stiv_collect", "stiv_set_option", "stiv_sort_pairs_u64", "stiv_last_error")
+           "stiv_collect", "stiv_set_option", "stiv_sort_pairs_u64", "stiv_mlp_nparam", "stiv_set_toi_model",
+           "stiv_mlp_forward", "stiv_mlp_grad", "stiv_mlp_adam", "stiv_last_error")
 STAT_NAMES = ("check_points", "vesicle_pairs", "work_items", "pre_candidates", "candidates_vt", "candidates_ee",
-              "root_searches", "contacts")
+              "root_searches", "contacts", "box_tests", "bracket_certified")
 
 
 class StivError(RuntimeError):
@@ -92,6 +93,13 @@ def lib():
                                         C.POINTER(stiv_result), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p]
             L.stiv_sort_pairs_u64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+            L.stiv_mlp_nparam.argtypes = []
+            L.stiv_set_toi_model.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_float]
+            L.stiv_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+            L.stiv_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
+            L.stiv_mlp_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
             L.stiv_last_error.argtypes = [C.c_void_p]
             L.stiv_last_error.restype = C.c_char_p
             for n in EXPORTS:
@@ -165,9 +173,48 @@ class Context:
         return list(ms)
 
     def stats(self):
-        v = (C.c_int64 * 8)()
-        self._check(lib().stiv_get_stats(self._h, v, 8))
+        v = (C.c_int64 * len(STAT_NAMES))()
+        self._check(lib().stiv_get_stats(self._h, v, len(STAT_NAMES)))
         return dict(zip(STAT_NAMES, list(v)))
+
+    # -- learned contact-time bracket ------------------------------------
+    def set_toi_model(self, params, kwidth=3.0):
+        """Install the bracket model (host FP32 array of stiv_mlp_nparam()
+        values), or remove it with params=None."""
+        if params is None:
+            self._check(lib().stiv_set_toi_model(self._h, None, 0, 1.0))
+            return
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        self._check(lib().stiv_set_toi_model(self._h, C.c_void_p(p.ctypes.data), int(p.size), float(kwidth)))
+
+    def mlp_forward(self, params, x, out=None):
+        """Raw model outputs [n,2] for features x [n,18] (float32 device tensors)."""
+        torch = _torch()
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.float32, device=x.device)
+        st = torch.cuda.current_stream(x.device).cuda_stream
+        self._check(lib().stiv_mlp_forward(self._h, _ptr(params), _ptr(x), int(n), _ptr(out), C.c_void_p(st)))
+        return out
+
+    def mlp_grad(self, params, x, target, grad=None, loss=None):
+        """Gradient of the mean bracket loss (device tensors); returns (grad, loss)."""
+        torch = _torch()
+        n = x.shape[0]
+        if grad is None:
+            grad = torch.empty_like(params)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        st = torch.cuda.current_stream(x.device).cuda_stream
+        self._check(lib().stiv_mlp_grad(self._h, _ptr(params), _ptr(x), _ptr(target), int(n), _ptr(grad),
+                                        _ptr(loss), C.c_void_p(st)))
+        return grad, loss
+
+    def mlp_adam(self, params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        torch = _torch()
+        st = torch.cuda.current_stream(params.device).cuda_stream
+        self._check(lib().stiv_mlp_adam(self._h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                                        float(beta1), float(beta2), float(eps), C.c_void_p(st)))
 
     def sort_pairs_u64(self, keys, vals):
         """Stable sort of device uint64 keys (as int64 tensor bits) with uint32 values (as int32)."""
@@ -240,14 +287,18 @@ class DetectResult(dict):
     __getattr__ = dict.__getitem__
 
 
+def mlp_nparam():
+    return int(lib().stiv_mlp_nparam())
+
+
 def detect(ctx: Context, dscene: DeviceScene, d, eps, dt, outputs: Outputs = None, emit_candidates=False,
-           stream=None, to_numpy=True):
+           stream=None, to_numpy=True, learned_bracket=False):
     """Run stiv_detect; grows the output arrays and retries on STIV_E_CAPACITY."""
     torch = _torch()
     ctx.set_topology(dscene.scene.topos)
     if outputs is None:
         outputs = Outputs(dscene.x0.device, cap_cand=(1 << 20) if emit_candidates else 0)
-    flags = STIV_EMIT_CANDIDATES if emit_candidates else 0
+    flags = (STIV_EMIT_CANDIDATES if emit_candidates else 0) | (STIV_LEARNED_BRACKET if learned_bracket else 0)
     p = stiv_params(float(d), float(eps), float(dt), flags)
     s = dscene.struct()
     st_ptr = stream if stream is not None else torch.cuda.current_stream(dscene.x0.device).cuda_stream
@@ -273,9 +324,9 @@ class AsyncDetect:
     a torch.cuda.CUDAGraph / hipGraph and replay), collect() synchronises and
     reads the counts.  Needs one synchronous detect on the same scene first."""
 
-    def __init__(self, ctx, dscene, d, eps, dt, outputs):
+    def __init__(self, ctx, dscene, d, eps, dt, outputs, learned_bracket=False):
         self.ctx, self.dscene, self.outputs = ctx, dscene, outputs
-        self.params = stiv_params(float(d), float(eps), float(dt), 0)
+        self.params = stiv_params(float(d), float(eps), float(dt), STIV_LEARNED_BRACKET if learned_bracket else 0)
         self.scene_struct = dscene.struct()
         self.result = outputs.struct()
 

@@ -26,3 +26,9 @@ def test_header_symbols_exported():
 def test_binding_loads_library():
     L = stiv.lib()
     assert L.stiv_last_error(None) == b"null context"
+
+
+def test_mlp_nparam_matches_layout():
+    """The bracket model's parameter count (host-only call, no GPU work)."""
+    from paper_1812_04719_amd import toi_model
+    assert stiv.mlp_nparam() == toi_model.layout()[1] == 18 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2

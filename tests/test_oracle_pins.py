@@ -118,10 +118,11 @@ def test_toi_samples_translating_planes():
     both times, over the mean edge length of the primitives at t_n."""
     gap, closing, d = 0.05, 0.1, 0.01
     sc = T.translating_planes(gap=gap, closing=closing, d=d)
-    feat, root = oracle.toi_samples(sc)
+    feat, root, hard = oracle.toi_samples(sc)
     r = oracle.detect(sc, emit_candidates=True)
     assert feat.shape == (len(r.cand), 18)
     assert np.all(np.abs(root - (gap - d) / closing) <= 1e-12)
+    assert hard.all()  # every candidate has a root, so none is excluded by its coefficients
     n_a = sc.vtx_off[1]
     rng = np.random.default_rng(5)
     for k in rng.choice(len(r.cand), 40, replace=False):
