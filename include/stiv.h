@@ -214,6 +214,39 @@ stiv_status stiv_get_stats(stiv_ctx *ctx, int64_t *vals, int n);
 stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * LCP matrix (Sec. 3.3.3, Alg. 3).  B = J M J^T over the contact volumes of
+ * a stiv_detect result: B(j,k) = sum over vesicles i of g_j,i . M_i g_k,i,
+ * with g_j,i the Jacobian row of volume j restricted to the points of
+ * vesicle i and M_i the vesicle's block of the operator (A_ii^-1 G_ii in the
+ * paper's time stepping; supplied by the caller).  Only points that appear in
+ * J enter, so M_i is given on the vesicle's ACTIVE points.
+ * ------------------------------------------------------------------------- */
+
+/* Active points of every vesicle.  res: the (complete, device) output of
+ * stiv_detect on scene s.  Writes act_off [n_ves+1] (int64, DEVICE): the
+ * active list of vesicle i is act_vtx[act_off[i] .. act_off[i+1]) (global
+ * vertex ids, ascending); m_off [n_ves+1] (int64, DEVICE): offsets, in
+ * doubles, of the blocks M_i in the operator array, each M_i being
+ * [3 a_i][3 a_i] row-major with a_i = act_off[i+1] - act_off[i], rows and
+ * columns point-major (x, y, z of active point 0, then point 1, ...).
+ * *n_act, *n_m (HOST): totals.  E_CAPACITY (counts still written) when
+ * n_act > cap_act.  Synchronous on stream. */
+stiv_status stiv_lcp_layout(stiv_ctx *ctx, const stiv_scene *s, const stiv_result *res, int64_t *act_off,
+                            int64_t *m_off, int32_t *act_vtx, int64_t cap_act, int64_t *n_act, int64_t *n_m,
+                            void *stream);
+
+/* Assemble B (Alg. 3) from res and the operator blocks M (DEVICE doubles in
+ * the stiv_lcp_layout layout).  Output: the structural nonzeros of B (every
+ * (j,k) whose volumes share a vesicle) as COO b_row, b_col (int32), b_val
+ * (FP64), sorted by (row, col), DEVICE arrays of capacity cap_b; *n_b (HOST)
+ * their number.  Sums over vesicles run in vesicle order (reproducible).
+ * E_CAPACITY when n_b > cap_b (*n_b still written) or when a vesicle has
+ * more than 128 volumes or 2048 active points.  Synchronous on stream. */
+stiv_status stiv_form_lcp(stiv_ctx *ctx, const stiv_scene *s, const stiv_result *res, const int64_t *act_off,
+                          const int64_t *m_off, const int32_t *act_vtx, const double *M, int32_t *b_row,
+                          int32_t *b_col, double *b_val, int64_t cap_b, int64_t *n_b, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned contact-time bracket (a learned heuristic on top of the root search
  * of Eq. 3.1, not part of the paper's method; it never changes results).
  *

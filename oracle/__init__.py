@@ -258,3 +258,61 @@ def toi_samples(scene, d=None, threads=0):
                              _ptr(hard), int(threads))
     del keep
     return feat, root, hard.astype(bool)
+
+
+# ---------------------------------------------------------------------------
+# LCP matrix (Sec. 3.3.3, Alg. 3): B(j,k) = sum over vesicles i of
+# g_j,i . M_i g_k,i, with g_j,i the Jacobian row of volume j restricted to
+# vesicle i's points and M_i the vesicle's operator block on its active
+# points (the points that appear in J).
+# ---------------------------------------------------------------------------
+def lcp_layout(vtx_off, j_vtx):
+    """Active points per vesicle: (act_off [n_ves+1], act_vtx, m_off [n_ves+1])
+    with blocks M_i of size [3 a_i]^2 at m_off[i] (doubles)."""
+    vtx_off = np.asarray(vtx_off, dtype=np.int64)
+    act = np.unique(np.asarray(j_vtx, dtype=np.int64))
+    act_off = np.searchsorted(act, vtx_off).astype(np.int64)
+    a = np.diff(act_off)
+    m_off = np.concatenate([[0], np.cumsum(9 * a * a)]).astype(np.int64)
+    return act_off, act.astype(np.int32), m_off
+
+
+def lcp_matrix(n_vol, vtx_off, vol_pair, pair_ab, j_vol, j_vtx, j_g, act_off, act_vtx, m_off, M):
+    """Dense B [n_vol, n_vol] by the loop of Alg. 3 (per vesicle, per pair of
+    its volumes), and the structural pattern (bool) of pairs sharing a vesicle."""
+    vtx_off = np.asarray(vtx_off, dtype=np.int64)
+    n_ves = len(vtx_off) - 1
+    j_vol = np.asarray(j_vol, dtype=np.int64)
+    j_vtx = np.asarray(j_vtx, dtype=np.int64)
+    B = np.zeros((n_vol, n_vol))
+    S = np.zeros((n_vol, n_vol), dtype=bool)
+    ves_of_row = np.searchsorted(vtx_off, j_vtx, side="right") - 1
+    # volumes of each vesicle (a volume belongs to its vesicle pair) and rows of each volume
+    vols_of = {}
+    for j in range(n_vol):
+        a, b = int(pair_ab[vol_pair[j]][0]), int(pair_ab[vol_pair[j]][1])
+        for i in {a, b}:
+            vols_of.setdefault(i, []).append(j)
+    rows_of = {}
+    for r in range(len(j_vol)):
+        rows_of.setdefault(int(j_vol[r]), []).append(r)
+    for i in range(n_ves):
+        vols = vols_of.get(i, [])
+        if not vols:
+            continue
+        a = int(act_off[i + 1] - act_off[i])
+        Mi = np.asarray(M[m_off[i]:m_off[i + 1]], dtype=np.float64).reshape(3 * a, 3 * a)
+        loc = {int(v): q for q, v in enumerate(act_vtx[act_off[i]:act_off[i + 1]])}
+        g = {}
+        for j in vols:
+            gj = np.zeros(3 * a)
+            for r in rows_of.get(j, []):
+                if ves_of_row[r] == i:
+                    q = loc[int(j_vtx[r])]
+                    gj[3 * q:3 * q + 3] += j_g[r]
+            g[j] = gj
+        for j in vols:
+            for k in vols:
+                B[j, k] += g[j] @ Mi @ g[k]
+                S[j, k] = True
+    return B, S

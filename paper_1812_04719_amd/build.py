@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libstiv.so")
 SOURCES = ["stiv_host.hip", "k_scan_sort.hip", "k_boxes.hip", "k_broad.hip", "k_prim.hip", "k_narrow.hip",
-           "k_aggr.hip", "k_backward.hip", "k_mlp.hip"]
+           "k_aggr.hip", "k_backward.hip", "k_mlp.hip", "k_lcp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(HERE, "..", "include")]

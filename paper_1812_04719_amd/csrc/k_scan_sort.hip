@@ -128,6 +128,11 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     p[i] = v;
 }
 
+__global__ void k_iota_u32(uint32_t *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint32_t)i;
+}
+
 int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -151,6 +156,9 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
 }
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u64<<<grid_for(n, 256), 256, 0, st>>>(p, v, n);
+}
+void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st) {
+  if (n > 0) k_iota_u32<<<grid_for(n, 256), 256, 0, st>>>(p, n);
 }
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_i32<<<grid_for(n, 256), 256, 0, st>>>(p, v, n);

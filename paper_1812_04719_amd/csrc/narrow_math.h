@@ -91,9 +91,37 @@ __host__ __device__ inline int inside_at(const Quad &Q, double s) {
   return (uu >= 0.0 && uu <= q && vv >= 0.0 && vv <= q) ? 1 : 0;
 }
 
-// Bernstein coefficients of f restricted to [u, u + wd]: Taylor shift to u,
-// scale by wd, then b_j = sum_{k<=j} C(j,k)/C(N,k) c_k (j-fold prefix sums of
-// c_k / C(N,k)).
+// Positive multiples of Bernstein coefficients.  The coefficients in the
+// Bernstein basis are b_j = sum_{k<=j} C(j,k)/C(N,k) c_k (j-fold prefix sums
+// of c_k / C(N,k)).  Only their signs are used, so all of them are scaled by
+// L = lcm_k C(N,k): c_k is multiplied by the integer L / C(N,k) instead of
+// being divided (one rounding either way, no FP64 division).
+template <int N>
+struct BernScale {
+  double v[N + 1];
+  // C(N,k) and their lcm, exact in integers for the degrees used here
+  constexpr BernScale() : v() {
+    long long c[N + 1] = {};
+    c[0] = 1;
+    for (int i = 1; i <= N; ++i) c[i] = c[i - 1] * (N - i + 1) / i;
+    long long l = 1;
+    for (int i = 0; i <= N; ++i) {
+      long long a = l, b = c[i];
+      while (b) {
+        const long long t = a % b;
+        a = b;
+        b = t;
+      }
+      l = l / a * c[i];
+    }
+    for (int k = 0; k <= N; ++k) v[k] = (double)(l / c[k]);
+  }
+};
+static_assert(BernScale<6>().v[3] == 3.0 && BernScale<6>().v[0] == 60.0, "lcm of C(6,k) is 60");
+static_assert(BernScale<3>().v[1] == 1.0 && BernScale<3>().v[3] == 3.0, "lcm of C(3,k) is 3");
+
+// Bernstein coefficients (times L, see BernScale) of f restricted to
+// [u, u + wd]: Taylor shift to u, scale by wd^k, then the prefix sums.
 template <int N>
 __host__ __device__ void bernstein_on(const double f[N + 1], double u, double wd, double b[N + 1]) {
   double c[N + 1];
@@ -103,14 +131,12 @@ __host__ __device__ void bernstein_on(const double f[N + 1], double u, double wd
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int k = N - 1; k >= i; --k) c[k] += u * c[k + 1];
-  double p = wd;
+  constexpr BernScale<N> L{};
+  double p = 1.0;
 #pragma unroll
-  for (int k = 1; k <= N; ++k) { c[k] *= p; p *= wd; }
-  double binom = 1.0;
-#pragma unroll
-  for (int k = 1; k <= N; ++k) {
-    binom = binom * (double)(N - k + 1) / (double)k;
-    c[k] /= binom;
+  for (int k = 0; k <= N; ++k) {
+    c[k] *= p * L.v[k];
+    p *= wd;
   }
 #pragma unroll
   for (int j = 0; j <= N; ++j) b[j] = c[j];
@@ -352,14 +378,9 @@ template <int N>
 __host__ __device__ inline bool needs_root_search(const Quad &Q, double d) {
   double f[N + 1], b[N + 1];
   poly_coeffs<N>(Q, d, f);
-  double binom = 1.0;
+  constexpr BernScale<N> L{};
 #pragma unroll
-  for (int k = 1; k <= N; ++k) {
-    binom = binom * (double)(N - k + 1) / (double)k;
-    f[k] /= binom;
-  }
-#pragma unroll
-  for (int j = 0; j <= N; ++j) b[j] = f[j];
+  for (int j = 0; j <= N; ++j) b[j] = f[j] * L.v[j];
 #pragma unroll
   for (int r = 1; r <= N; ++r)
 #pragma unroll

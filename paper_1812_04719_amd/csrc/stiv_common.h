@@ -112,6 +112,7 @@ void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, hipStream_t st);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // K0
@@ -151,6 +152,24 @@ void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T,
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
                    int64_t ct_cap, const float *mlp_params, float kwidth, Counters *cnt, hipStream_t st);
+
+// LCP matrix assembly (Alg. 3)
+void launch_lcp_layout(const int *vtx_off, int n_ves, const int32_t *j_vtx, int64_t n_jrow, int32_t *flag,
+                       int32_t *a, int64_t *m9, hipStream_t st);
+void launch_lcp_emit(const int *vtx_off, int n_ves, const int32_t *flag, const int64_t *act_off, int32_t *act_vtx,
+                     hipStream_t st);
+void launch_lcp_vcount(const int32_t *vol_pair, const int32_t *pair_ab, int64_t n_vol, int32_t *vcnt, hipStream_t st);
+void launch_lcp_vscatter(const int32_t *vol_pair, const int32_t *pair_ab, int64_t n_vol, const int64_t *voff,
+                         int32_t *vcur, int32_t *vlist, int n_ves, int64_t *c2, hipStream_t st);
+void launch_lcp_block(const int *vtx_off, int n_ves, const int64_t *act_off, const int64_t *m_off,
+                      const int32_t *act_vtx, const double *M, const int64_t *voff, const int32_t *vlist,
+                      const int32_t *j_vol, const int32_t *j_vtx, const double *j_g, int64_t n_jrow,
+                      const int64_t *coff, uint64_t *ckey, double *cval, unsigned long long *overflow,
+                      hipStream_t st);
+void launch_lcp_runs(const uint64_t *key, int64_t n, int32_t *start, hipStream_t st);
+void launch_lcp_reduce(const uint64_t *key, const uint32_t *idx, const double *cval, int64_t n, const int32_t *start,
+                       const int64_t *pos, int32_t *b_row, int32_t *b_col, double *b_val, int64_t cap,
+                       hipStream_t st);
 
 // Learned contact-time bracket (perceptron kernels)
 int mlp_nparam();

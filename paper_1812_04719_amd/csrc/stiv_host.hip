@@ -71,6 +71,9 @@ struct stiv_ctx {
       row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
   Buf toi_params, mlp_part;
+  // LCP matrix assembly scratch
+  Buf lcp_flag, lcp_a, lcp_m9, lcp_vcnt, lcp_vcur, lcp_voff, lcp_vlist, lcp_c2, lcp_coff, lcp_ckey, lcp_cval,
+      lcp_cidx, lcp_tk, lcp_tv, lcp_start, lcp_pos, lcp_ovf;
   bool have_model = false;
   float toi_kwidth = 3.0f;
   int64_t cap_cp = 0, cap_pairs = 0, cap_work = 0, cap_cand = 0, cap_ct = 0, cap_patch = 0, cap_list = 0;
@@ -141,7 +144,10 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
                 &ctx->cand_list, &ctx->ct,
-                &ctx->toi_params, &ctx->mlp_part,
+                &ctx->toi_params, &ctx->mlp_part, &ctx->lcp_flag, &ctx->lcp_a, &ctx->lcp_m9, &ctx->lcp_vcnt,
+                &ctx->lcp_vcur, &ctx->lcp_voff, &ctx->lcp_vlist, &ctx->lcp_c2, &ctx->lcp_coff, &ctx->lcp_ckey,
+                &ctx->lcp_cval, &ctx->lcp_cidx, &ctx->lcp_tk, &ctx->lcp_tv, &ctx->lcp_start, &ctx->lcp_pos,
+                &ctx->lcp_ovf,
                 &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
                 &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
                 &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv,
@@ -775,6 +781,113 @@ stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, i
   launch_radix_sort_u64(keys, vals, P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), nullptr, n, 64, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
+  return STIV_OK;
+}
+
+static stiv_status check_lcp_args(stiv_ctx *ctx, const stiv_scene *s, const stiv_result *res) {
+  if (!ctx) return STIV_E_ARG;
+  if (!s || !res) return fail(ctx, STIV_E_ARG, "null scene or result");
+  if (s->n_ves < 0 || s->n_vtx < 0 || (s->n_ves > 0 && !s->vtx_off)) return fail(ctx, STIV_E_ARG, "bad scene");
+  if (res->n_vol < 0 || res->n_jrow < 0 || res->n_vol > res->cap_vol || res->n_jrow > res->cap_jrow ||
+      res->n_pairs > res->cap_pairs)
+    return fail(ctx, STIV_E_ARG, "result counts exceed its capacities (not a complete stiv_detect result)");
+  if (res->n_jrow > 0 && (!res->j_vol || !res->j_vtx || !res->j_g))
+    return fail(ctx, STIV_E_ARG, "null Jacobian arrays");
+  if (res->n_vol > 0 && (!res->vol_pair || !res->pair_ab)) return fail(ctx, STIV_E_ARG, "null volume arrays");
+  if (res->n_vol >= (1ll << 31)) return fail(ctx, STIV_E_ARG, "too many volumes");
+  return STIV_OK;
+}
+
+stiv_status stiv_lcp_layout(stiv_ctx *ctx, const stiv_scene *s, const stiv_result *res, int64_t *act_off,
+                            int64_t *m_off, int32_t *act_vtx, int64_t cap_act, int64_t *n_act, int64_t *n_m,
+                            void *stream) {
+  stiv_status stc = check_lcp_args(ctx, s, res);
+  if (stc != STIV_OK) return stc;
+  if (!act_off || !m_off || !n_act || !n_m || cap_act < 0 || (cap_act > 0 && !act_vtx))
+    return fail(ctx, STIV_E_ARG, "bad layout outputs");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int nv = s->n_ves;
+  HIPCHK(ensure(ctx->lcp_flag, 4 * (size_t)(s->n_vtx + 1)));
+  HIPCHK(ensure(ctx->lcp_a, 4 * (size_t)(nv + 1)));
+  HIPCHK(ensure(ctx->lcp_m9, 8 * (size_t)(nv + 1)));
+  launch_fill_i32(P<int32_t>(ctx->lcp_flag), 0, s->n_vtx + 1, st);
+  launch_lcp_layout(s->vtx_off, nv, res->j_vtx, res->n_jrow, P<int32_t>(ctx->lcp_flag), P<int32_t>(ctx->lcp_a),
+                    P<int64_t>(ctx->lcp_m9), st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_a), act_off, nullptr, nv, st);
+  launch_scan_i64(P<int64_t>(ctx->lcp_m9), m_off, nullptr, nv, st);
+  HIPCHK(hipGetLastError());
+  int64_t tot[2];
+  HIPCHK(hipMemcpyAsync(&tot[0], act_off + nv, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&tot[1], m_off + nv, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *n_act = tot[0];
+  *n_m = tot[1];
+  if (tot[0] > cap_act) return fail(ctx, STIV_E_CAPACITY, "act_vtx capacity too small");
+  launch_lcp_emit(s->vtx_off, nv, P<int32_t>(ctx->lcp_flag), act_off, act_vtx, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return STIV_OK;
+}
+
+stiv_status stiv_form_lcp(stiv_ctx *ctx, const stiv_scene *s, const stiv_result *res, const int64_t *act_off,
+                          const int64_t *m_off, const int32_t *act_vtx, const double *M, int32_t *b_row,
+                          int32_t *b_col, double *b_val, int64_t cap_b, int64_t *n_b, void *stream) {
+  stiv_status stc = check_lcp_args(ctx, s, res);
+  if (stc != STIV_OK) return stc;
+  if (!act_off || !m_off || !n_b || cap_b < 0 || (cap_b > 0 && (!b_row || !b_col || !b_val)))
+    return fail(ctx, STIV_E_ARG, "bad LCP outputs");
+  if (res->n_jrow > 0 && (!act_vtx || !M)) return fail(ctx, STIV_E_ARG, "null active list or operator blocks");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int nv = s->n_ves;
+  const int64_t n_vol = res->n_vol;
+  HIPCHK(ensure(ctx->lcp_vcnt, 4 * (size_t)(nv + 1)));
+  HIPCHK(ensure(ctx->lcp_vcur, 4 * (size_t)(nv + 1)));
+  HIPCHK(ensure(ctx->lcp_voff, 8 * (size_t)(nv + 1)));
+  HIPCHK(ensure(ctx->lcp_c2, 8 * (size_t)(nv + 1)));
+  HIPCHK(ensure(ctx->lcp_coff, 8 * (size_t)(nv + 1)));
+  HIPCHK(ensure(ctx->lcp_vlist, 4 * (size_t)(2 * n_vol + 1)));
+  HIPCHK(ensure(ctx->lcp_ovf, 8));
+  launch_fill_i32(P<int32_t>(ctx->lcp_vcnt), 0, nv + 1, st);
+  launch_fill_i32(P<int32_t>(ctx->lcp_vcur), 0, nv + 1, st);
+  launch_fill_u64(P<uint64_t>(ctx->lcp_ovf), 0ull, 1, st);
+  launch_lcp_vcount(res->vol_pair, res->pair_ab, n_vol, P<int32_t>(ctx->lcp_vcnt), st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_vcnt), P<int64_t>(ctx->lcp_voff), nullptr, nv, st);
+  launch_lcp_vscatter(res->vol_pair, res->pair_ab, n_vol, P<int64_t>(ctx->lcp_voff), P<int32_t>(ctx->lcp_vcur),
+                      P<int32_t>(ctx->lcp_vlist), nv, P<int64_t>(ctx->lcp_c2), st);
+  launch_scan_i64(P<int64_t>(ctx->lcp_c2), P<int64_t>(ctx->lcp_coff), nullptr, nv, st);
+  HIPCHK(hipGetLastError());
+  int64_t nc = 0;
+  HIPCHK(hipMemcpyAsync(&nc, P<int64_t>(ctx->lcp_coff) + nv, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (nc >= (1ll << 32)) return fail(ctx, STIV_E_CAPACITY, "too many LCP contributions");
+  HIPCHK(ensure(ctx->lcp_ckey, 8 * (size_t)(nc + 1)));
+  HIPCHK(ensure(ctx->lcp_cval, 8 * (size_t)(nc + 1)));
+  HIPCHK(ensure(ctx->lcp_cidx, 4 * (size_t)(nc + 1)));
+  HIPCHK(ensure(ctx->lcp_tk, 8 * (size_t)(nc + 1)));
+  HIPCHK(ensure(ctx->lcp_tv, 4 * (size_t)(nc + 1)));
+  HIPCHK(ensure(ctx->lcp_start, 4 * (size_t)(nc + 1)));
+  HIPCHK(ensure(ctx->lcp_pos, 8 * (size_t)(nc + 1)));
+  launch_lcp_block(s->vtx_off, nv, act_off, m_off, act_vtx, M, P<int64_t>(ctx->lcp_voff), P<int32_t>(ctx->lcp_vlist),
+                   res->j_vol, res->j_vtx, res->j_g, res->n_jrow, P<int64_t>(ctx->lcp_coff),
+                   P<uint64_t>(ctx->lcp_ckey), P<double>(ctx->lcp_cval), P<unsigned long long>(ctx->lcp_ovf), st);
+  launch_iota_u32(P<uint32_t>(ctx->lcp_cidx), nc, st);
+  launch_radix_sort_u64(P<uint64_t>(ctx->lcp_ckey), P<uint32_t>(ctx->lcp_cidx), P<uint64_t>(ctx->lcp_tk),
+                        P<uint32_t>(ctx->lcp_tv), nullptr, nc, 64, st);
+  launch_lcp_runs(P<uint64_t>(ctx->lcp_ckey), nc, P<int32_t>(ctx->lcp_start), st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_start), P<int64_t>(ctx->lcp_pos), nullptr, nc, st);
+  launch_lcp_reduce(P<uint64_t>(ctx->lcp_ckey), P<uint32_t>(ctx->lcp_cidx), P<double>(ctx->lcp_cval), nc,
+                    P<int32_t>(ctx->lcp_start), P<int64_t>(ctx->lcp_pos), b_row, b_col, b_val, cap_b, st);
+  HIPCHK(hipGetLastError());
+  int64_t nb = 0;
+  unsigned long long ovf = 0;
+  HIPCHK(hipMemcpyAsync(&nb, P<int64_t>(ctx->lcp_pos) + nc, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&ovf, ctx->lcp_ovf.p, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *n_b = nb;
+  if (ovf) return fail(ctx, STIV_E_CAPACITY, "a vesicle has more than 128 volumes or 2048 active points");
+  if (nb > cap_b) return fail(ctx, STIV_E_CAPACITY, "B capacity too small");
   return STIV_OK;
 }
 

@@ -550,3 +550,27 @@ def make_config(k: int, **overrides) -> Scene:
     kw = dict(spec["kw"])
     kw.update(overrides)
     return globals()[spec["fn"]](**kw)
+
+
+def lcp_blocks(x, vtx_off, act_off, act_vtx, ell=0.5, seed=11):
+    """Synthetic operator blocks for the LCP matrix, one per vesicle on its
+    active points (layout of the LCP matrix entry points): a Gaussian kernel
+    of width ell between the points (x [3][n_vtx]) times a seeded random SPD
+    3x3 matrix, plus a small diagonal shift; symmetric positive definite,
+    smooth in space like a mobility operator.  Returns a flat float64 array."""
+    rng = np.random.default_rng(seed)
+    act_off = np.asarray(act_off, dtype=np.int64)
+    out = []
+    for i in range(len(act_off) - 1):
+        ids = np.asarray(act_vtx[act_off[i]:act_off[i + 1]], dtype=np.int64)
+        a = ids.size
+        if a == 0:
+            continue
+        P = np.asarray(x)[:, ids].T
+        d2 = ((P[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+        K = np.exp(-d2 / (2.0 * ell * ell))
+        Q = rng.normal(size=(3, 3))
+        C3 = Q @ Q.T + 0.5 * np.eye(3)
+        Mi = np.kron(K, C3) + 1e-3 * np.eye(3 * a)
+        out.append(Mi.ravel())
+    return np.concatenate(out) if out else np.zeros(0)

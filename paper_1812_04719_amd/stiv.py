@@ -25,7 +25,8 @@ _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HI
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
            "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_detect_async",
            "stiv_collect", "stiv_set_option", "stiv_sort_pairs_u64", "stiv_mlp_nparam", "stiv_set_toi_model",
-           "stiv_mlp_forward", "stiv_mlp_grad", "stiv_mlp_adam", "stiv_last_error")
+           "stiv_mlp_forward", "stiv_mlp_grad", "stiv_mlp_adam", "stiv_lcp_layout", "stiv_form_lcp",
+           "stiv_last_error")
 STAT_NAMES = ("check_points", "vesicle_pairs", "work_items", "pre_candidates", "candidates_vt", "candidates_ee",
               "root_searches", "contacts", "box_tests", "bracket_certified")
 
@@ -100,6 +101,12 @@ def lib():
                                         C.c_void_p, C.c_void_p]
             L.stiv_mlp_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                         C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
+            L.stiv_lcp_layout.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_result), C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_int64), C.c_void_p]
+            L.stiv_form_lcp.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_result), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_int64, C.POINTER(C.c_int64), C.c_void_p]
             L.stiv_last_error.argtypes = [C.c_void_p]
             L.stiv_last_error.restype = C.c_char_p
             for n in EXPORTS:
@@ -383,3 +390,48 @@ def _collect(r, o, emit, to_numpy):
             if hasattr(v, "cpu"):
                 out[k] = v.cpu().numpy()
     return out
+
+
+def lcp_layout(ctx: Context, dscene: DeviceScene, result_struct, stream=None):
+    """Active points of every vesicle for the LCP matrix: (act_off, m_off,
+    act_vtx) device tensors (layout of the operator blocks in include/stiv.h)."""
+    torch = _torch()
+    dev = dscene.x0.device
+    nv = dscene.n_ves
+    act_off = torch.empty(nv + 1, dtype=torch.int64, device=dev)
+    m_off = torch.empty(nv + 1, dtype=torch.int64, device=dev)
+    cap = max(int(result_struct.n_jrow), 1)
+    act_vtx = torch.empty(cap, dtype=torch.int32, device=dev)
+    n_act, n_m = C.c_int64(), C.c_int64()
+    s = dscene.struct()
+    st_ptr = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    ctx._check(lib().stiv_lcp_layout(ctx._h, C.byref(s), C.byref(result_struct), _ptr(act_off), _ptr(m_off),
+                                     _ptr(act_vtx), cap, C.byref(n_act), C.byref(n_m), C.c_void_p(st_ptr)))
+    return act_off, m_off, act_vtx[: n_act.value]
+
+
+def form_lcp(ctx: Context, dscene: DeviceScene, result_struct, act_off, m_off, act_vtx, M, cap_b=None,
+             stream=None):
+    """Sparse B = J M J^T (Alg. 3) as COO device tensors (rows, cols, vals),
+    sorted by (row, col); grows the output and retries on STIV_E_CAPACITY."""
+    torch = _torch()
+    dev = dscene.x0.device
+    cap = cap_b or max(4 * int(result_struct.n_vol), 16)
+    s = dscene.struct()
+    st_ptr = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    Mc = M.contiguous()
+    for _ in range(3):
+        rows = torch.empty(cap, dtype=torch.int32, device=dev)
+        cols = torch.empty(cap, dtype=torch.int32, device=dev)
+        vals = torch.empty(cap, dtype=torch.float64, device=dev)
+        n_b = C.c_int64()
+        st = lib().stiv_form_lcp(ctx._h, C.byref(s), C.byref(result_struct), _ptr(act_off), _ptr(m_off),
+                                 _ptr(act_vtx), _ptr(Mc), _ptr(rows), _ptr(cols), _ptr(vals), cap, C.byref(n_b),
+                                 C.c_void_p(st_ptr))
+        if st == STIV_E_CAPACITY and n_b.value > cap:
+            cap = n_b.value
+            continue
+        ctx._check(st)
+        n = n_b.value
+        return rows[:n], cols[:n], vals[:n]
+    raise StivError(STIV_E_CAPACITY, "LCP output did not fit after growing")
