@@ -202,7 +202,8 @@ stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n);
 /* Work counts of the last detect (diagnostics, tuning): 0 check points,
  * 1 candidate vesicle pairs, 2 patch-pair work items, 3 FP32 pre-candidates
  * (a superset of the candidates), 4 vertex-triangle candidates, 5 edge-edge
- * candidates, 6 candidates whose polynomial needed a root search, 7 contacts,
+ * candidates, 6 candidates that needed a root search (F may vanish on [0,1]
+ * and the closest-point test may pass somewhere on [0,1]), 7 contacts,
  * 8 primitive box-pair tests made by the candidate sweep, 9 root searches
  * whose learned bracket was certified (STIV_LEARNED_BRACKET).
  * Fills min(n, 10) values. */

@@ -47,61 +47,18 @@ __device__ inline unsigned long long lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-__device__ inline d3 load_pos(const double *x, int64_t nv, int64_t gid) {
-  return mk(x[gid], x[nv + gid], x[2 * nv + gid]);
-}
 
-// Global vertex ids and per-vertex image shifts of a candidate; order
-// (p, a, b, c) for vertex-triangle, (a, b, c, e) for edge-edge.  side[k] is 1
-// for vertices of the pair's second vesicle (shifted by sigma L).
-__device__ inline void cand_vertices(const DevScene &S, const DevTopo &T, const PairRec &pr, const Cand &c,
-                                     int64_t gid[4], int side[4]) {
-  if (c.kind == 2) {
-    const int ta = S.topo_id[pr.a], tb = S.topo_id[pr.b];
-    const int *ea = T.edge + 2 * ((int64_t)T.edge_off[ta] + c.i);
-    const int *eb = T.edge + 2 * ((int64_t)T.edge_off[tb] + c.j);
-    gid[0] = S.vtx_off[pr.a] + ea[0]; gid[1] = S.vtx_off[pr.a] + ea[1];
-    gid[2] = S.vtx_off[pr.b] + eb[0]; gid[3] = S.vtx_off[pr.b] + eb[1];
-    side[0] = side[1] = 0; side[2] = side[3] = 1;
-  } else {
-    const int vv = c.kind ? pr.b : pr.a, vt = c.kind ? pr.a : pr.b;
-    const int *tri = T.tri + 3 * ((int64_t)T.tri_off[S.topo_id[vt]] + c.j);
-    gid[0] = S.vtx_off[vv] + c.i;
-    for (int q = 0; q < 3; ++q) gid[1 + q] = S.vtx_off[vt] + tri[q];
-    side[0] = c.kind ? 1 : 0;
-    side[1] = side[2] = side[3] = c.kind ? 0 : 1;
-  }
-}
-
-// Load the candidate's vertices; Q gets X0 + shift and D = X1 - X0.  Returns
-// whether the FP64 primitive boxes overlap, box = ((min over the primitive's
-// vertices of min(X0, X1)) - h) + shift, likewise for the max.  The first
-// primitive is vertex 0 (vertex-triangle) or vertices 0-1 (edge-edge); the
-// second is vertices 1-3 or 2-3.
-__device__ inline bool load_quad(const DevScene &S, const PairRec &pr, const int64_t gid[4], const int side[4],
-                                 bool ee, double h, Quad &Q) {
-  const int64_t NV = S.n_vtx;
-  d3 a[4], b[4];
+// Geometry of queued candidate i (written by the primitive kernel, structure
+// of arrays [24][cap]): X0 of vertices 0..3 (image shift applied), then
+// D = X1 - X0; order (p, a, b, c) for vertex-triangle, (a, b, c, e) for
+// edge-edge.  Coalesced: consecutive threads read consecutive candidates.
+__device__ inline void load_geo(const double *geo, int64_t cap, int64_t i, bool ee, Quad &Q) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    a[k] = load_pos(S.x0, NV, gid[k]);
-    b[k] = load_pos(S.x1, NV, gid[k]);
-    const double sx = side[k] ? pr.sh[0] : 0.0, sy = side[k] ? pr.sh[1] : 0.0, sz = side[k] ? pr.sh[2] : 0.0;
-    Q.X0[k] = mk(a[k].x + sx, a[k].y + sy, a[k].z + sz);
-    Q.D[k] = b[k] - a[k];
+  for (int v = 0; v < 4; ++v) {
+    Q.X0[v] = mk(geo[(3 * v + 0) * cap + i], geo[(3 * v + 1) * cap + i], geo[(3 * v + 2) * cap + i]);
+    Q.D[v] = mk(geo[(12 + 3 * v + 0) * cap + i], geo[(12 + 3 * v + 1) * cap + i], geo[(12 + 3 * v + 2) * cap + i]);
   }
   Q.ee = ee;
-  const d3 lo0 = vmin(a[0], b[0]), hi0 = vmax(a[0], b[0]);
-  const d3 lo1 = vmin(a[1], b[1]), hi1 = vmax(a[1], b[1]);
-  const d3 lo2 = vmin(vmin(a[2], b[2]), vmin(a[3], b[3])), hi2 = vmax(vmax(a[2], b[2]), vmax(a[3], b[3]));
-  // vertex 1 belongs to the first primitive for edge-edge, to the triangle otherwise
-  const d3 lA = ee ? vmin(lo0, lo1) : lo0, hA = ee ? vmax(hi0, hi1) : hi0;
-  const d3 lB = ee ? lo2 : vmin(lo1, lo2), hB = ee ? hi2 : vmax(hi1, hi2);
-  const d3 sA = side[0] ? mk(pr.sh[0], pr.sh[1], pr.sh[2]) : mk(0.0, 0.0, 0.0);
-  const d3 sB = side[3] ? mk(pr.sh[0], pr.sh[1], pr.sh[2]) : mk(0.0, 0.0, 0.0);
-  const d3 l0 = (lA - mk(h, h, h)) + sA, u0 = (hA + mk(h, h, h)) + sA;
-  const d3 l1 = (lB - mk(h, h, h)) + sB, u1 = (hB + mk(h, h, h)) + sB;
-  return l0.x <= u1.x && l1.x <= u0.x && l0.y <= u1.y && l1.y <= u0.y && l0.z <= u1.z && l1.z <= u0.z;
 }
 
 __device__ inline double len3(const d3 &v) { return sqrt(dotp(v, v)); }
@@ -145,8 +102,8 @@ struct BracketLds {
 // LEARNED: the bracket of every candidate is predicted first (all 256
 // candidates of the workgroup through the perceptron on the matrix cores).
 template <int N, bool LEARNED>
-__global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const PairRec *pairs, const Cand *hard,
-                                                int64_t hard_cap, double d, double eps,
+__global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *geo, int64_t hard_cap, double d,
+                                                double eps,
                                                 double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
                                                 int64_t ct_cap, const float *mlp_params, float kwidth,
                                                 Counters *cnt) {
@@ -168,22 +125,15 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
     c.pair = c.kind = c.i = c.j = 0;
     for (int k = 0; k < 12; ++k) g[k] = 0.0;
     Quad Q;
-    PairRec pr;
-    int64_t gid[4];
-    int side[4];
-    if (i < nc) {
-      c = hard[i];
-      pr = pairs[c.pair];
-      cand_vertices(S, T, pr, c, gid, side);
-    }
+    if (i < nc) c = hard[i];
     if (LEARNED) {
-      // features first; the positions are loaded again for the search so that
-      // they are not live (spilled) across the perceptron
+      // features first; the geometry is loaded again for the search so that
+      // it is not live (spilled) across the perceptron
       {
         float ft[mlp::kIn];
         if (i < nc) {
           Quad Qf;
-          load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Qf);
+          load_geo(geo, hard_cap, i, c.kind == 2, Qf);
           bracket_features(Qf, ft);
         } else {
 #pragma unroll
@@ -203,7 +153,7 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
         __syncthreads();
       }
       if (i < nc) {
-        load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Q);
+        load_geo(geo, hard_cap, i, c.kind == 2, Q);
         const float mu = mlp::head_mu(L.br[threadIdx.x][0]), sd = mlp::head_sd(L.br[threadIdx.x][1]);
         double lo = (double)mu - (double)kwidth * (double)sd, hi = (double)mu + (double)kwidth * (double)sd;
         lo = lo < 0.0 ? 0.0 : lo;
@@ -214,7 +164,7 @@ __global__ __launch_bounds__(256) void k_narrow(DevScene S, DevTopo T, const Pai
       }
       __syncthreads();
     } else if (i < nc) {
-      load_quad(S, pr, gid, side, c.kind == 2, 0.5 * d, Q);
+      load_geo(geo, hard_cap, i, c.kind == 2, Q);
       hit = earliest<N>(Q, d, &s, &within, &deg);
     }
     if (hit && !Q.ee) volume_grad(Q, s, d, eps, dt, s == 0.0, &V, g);
@@ -253,24 +203,26 @@ static int grid_for(int64_t n, int max_blocks) {
   return (int)g;
 }
 
-void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
-                   double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, const float *mlp_params, float kwidth, Counters *cnt, hipStream_t st) {
+void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard,
+                   const double *hard_geo, int64_t hard_cap, double d, double eps, double dt, Cand *ct, double *ct_s,
+                   double *ct_vol, double *ct_grad, int64_t ct_cap, const float *mlp_params, float kwidth,
+                   Counters *cnt, hipStream_t st) {
+  (void)S; (void)T; (void)pairs;
   const int g = grid_for(hard_cap, blocks);
   const size_t lds = sizeof(BracketLds);
   if (mlp_params) {
     if (d == 0.0)
-      k_narrow<3, true><<<g, 256, lds, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+      k_narrow<3, true><<<g, 256, lds, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
                                             mlp_params, kwidth, cnt);
     else
-      k_narrow<6, true><<<g, 256, lds, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+      k_narrow<6, true><<<g, 256, lds, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
                                             mlp_params, kwidth, cnt);
   } else {
     if (d == 0.0)
-      k_narrow<3, false><<<g, 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+      k_narrow<3, false><<<g, 256, 0, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
                                            nullptr, 0.0f, cnt);
     else
-      k_narrow<6, false><<<g, 256, 0, st>>>(S, T, pairs, hard, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
+      k_narrow<6, false><<<g, 256, 0, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
                                            nullptr, 0.0f, cnt);
   }
 }

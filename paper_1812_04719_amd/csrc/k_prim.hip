@@ -41,7 +41,7 @@ __device__ inline unsigned long long wave_append(bool want, unsigned long long *
 }
 
 constexpr int kPPThreads = 256;
-constexpr int kPPBuf = 1024;
+constexpr int kPPBuf = 512;
 
 __device__ inline bool ov6f_(const float *A, const float *B) {
   return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
@@ -54,11 +54,11 @@ __device__ inline bool ov6f_(const float *A, const float *B) {
 // LDS and written with one atomic per flush.
 __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo T, const PairRec *pairs,
                                                             const double *ves_box, const int64_t *ves_patch_off,
-                                                            const double *patch_box, uint64_t *work,
+                                                            const double *patch_box, WorkRec *work,
                                                             int64_t work_cap, Counters *cnt, int64_t pairs_cap) {
   __shared__ float bA[kMaxPatchesPerVes][6], bB[kMaxPatchesPerVes][6];
   __shared__ short iA[kMaxPatchesPerVes], iB[kMaxPatchesPerVes];
-  __shared__ uint64_t buf[kPPBuf];
+  __shared__ WorkRec buf[kPPBuf];
   __shared__ int nA, nB, nbuf;
   __shared__ unsigned long long base_sh;
   int64_t np = (int64_t)cnt->n_pairs;
@@ -73,6 +73,8 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
       boxB[3 + c] = ves_box[6 * (int64_t)pr.b + 3 + c] + pr.sh[c];
     }
     const int64_t pa0 = ves_patch_off[pr.a], pb0 = ves_patch_off[pr.b];
+    const int ptA = T.patch_off[S.topo_id[pr.a]], ptB = T.patch_off[S.topo_id[pr.b]];
+    const int vbA = S.vtx_off[pr.a], vbB = S.vtx_off[pr.b];
     const int na = (int)(ves_patch_off[pr.a + 1] - pa0), nb = (int)(ves_patch_off[pr.b + 1] - pb0);
     if (threadIdx.x == 0) { nA = 0; nB = 0; }
     __syncthreads();
@@ -109,7 +111,14 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
         const int x = t / mb, y = t - x * mb;
         if (ov6f_(bA[x], bB[y])) {
           const int q = atomicAdd(&nbuf, 1);
-          buf[q] = ((uint64_t)p << 32) | ((uint64_t)(uint16_t)iA[x] << 16) | (uint64_t)(uint16_t)iB[y];
+          WorkRec w;
+          w.p = (int)p;
+          w.pa = ptA + iA[x];
+          w.pb = ptB + iB[y];
+          w.base_a = vbA;
+          w.base_b = vbB;
+          w.pad[0] = w.pad[1] = w.pad[2] = 0;
+          buf[q] = w;
         }
       }
       __syncthreads();
@@ -135,33 +144,40 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 }
 
 // --------------------------------------------------------------------------
-// Per work item: one wavefront, FP64 positions of both patches in LDS.
-//
-// 1. Stage X0 and X1 of every vertex referenced by the two patches.
+// Per work item: one wavefront, both patches staged in LDS.
+// 1. Both patch blobs (ids and slots, see BlobLayout) arrive with one round
+//    of coalesced loads; then X0 and X1 of every referenced vertex.  A work
+//    item thus waits for three dependent rounds of global loads: the work
+//    record, the blobs, the positions.
 // 2. Per kind, build the left list (owned vertices, or owned edges) and the
 //    right list (triangles, or owned edges) of primitives whose boxes meet
 //    the other patch's box; boxes are FP32 rounded outward from the FP64
 //    boxes, so the filter keeps a superset.
-// 3. Each lane holds one left box in registers and sweeps the right list in
-//    LDS; FP32 hits are buffered in LDS.
+// 3. All left x right pairs of the lists, 64 per round, FP32 box test; hits
+//    are buffered in LDS.
 // 4. Buffered hits are processed 64 at a time with all lanes busy: the exact
-//    FP64 box test (the candidate definition), then the polynomial screen.
-//    Candidates whose polynomial can have a root on [0,1] are queued for the
-//    root-search kernel; the rest are finished here.
+//    FP64 box test (the candidate definition), then the screens: candidates
+//    whose polynomial can have a root on [0,1] and whose closest-point test
+//    can pass somewhere on [0,1] are queued for the
+//    root-search kernel together with their FP64 geometry (structure of
+//    arrays), so the root search reads them coalesced; the rest are
+//    finished here.
 // --------------------------------------------------------------------------
 constexpr int kHitBuf = 256;
 
 template <int TILE>
 struct WaveLds {
+  using Lay = BlobLayout<TILE>;
   static constexpr int kRef = TileCaps<TILE>::ref;
   static constexpr int kL = TileCaps<TILE>::owne > TileCaps<TILE>::ownv ? TileCaps<TILE>::owne : TileCaps<TILE>::ownv;
   static constexpr int kR = TileCaps<TILE>::owne > TILE ? TileCaps<TILE>::owne : TILE;
-  double pos[2][kRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
-  float lbox[kL][6];       // left-hand list of the current kind: FP32 boxes
-  float rbox[kR][6];       // right-hand list
-  int lk[kL];              // patch-table indices of the left-hand list
-  int rk[kR];              // and of the right-hand list
-  int4 hits[kHitBuf];      // (kind, left index, right index, -)
+  double pos[2][kRef][6];      // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
+  float lbox[kL][6];           // left-hand list of the current kind: FP32 boxes
+  float rbox[kR][6];           // right-hand list
+  uint8_t lk[kL];              // patch-local indices of the left-hand list
+  uint8_t rk[kR];              // and of the right-hand list
+  uint32_t hits[kHitBuf];      // kind << 16 | left << 8 | right (patch-local indices)
+  alignas(16) int blob[2][Lay::stride];  // the two patch blobs
 };
 
 __device__ inline bool ov6f(const float *A, const float *B) {
@@ -199,12 +215,18 @@ __device__ inline float wave_maxf(float v) {
   return v;
 }
 
+template <int TILE>
+__device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, int off) {
+  return reinterpret_cast<const uint8_t *>(&W.blob[side][off]);
+}
+
 // Exact FP64 box test of a buffered hit and the polynomial screen; queue the
 // candidates that need a root search.  All 64 lanes take part.
 template <int N, int TILE>
-__device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &pr, int p, const int P[2], double d,
-                             Cand *hard, int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt,
-                             unsigned long long &nvt, unsigned long long &nee, int nh) {
+__device__ void process_hits(WaveLds<TILE> &W, const double *sh, int p, double d, Cand *hard, double *geo,
+                             int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, unsigned long long &nvt,
+                             unsigned long long &nee, int nh) {
+  using Lay = BlobLayout<TILE>;
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
   __syncthreads();
@@ -213,22 +235,25 @@ __device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &
     bool is_cand = false, need = false;
     Cand c;
     c.pair = p; c.kind = 0; c.i = 0; c.j = 0;
+    int slots[4] = {0, 0, 0, 0}, sl = 0, sr = 1;
     if (k < nh) {
-      const int4 hv = W.hits[k];
-      const int kind = hv.x, kl = hv.y, kr = hv.z;
-      const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
-      int slots[4];
-      if (kind == 2) {
-        slots[0] = T.pedge_slot[2 * kl]; slots[1] = T.pedge_slot[2 * kl + 1];
-        slots[2] = T.pedge_slot[2 * kr]; slots[3] = T.pedge_slot[2 * kr + 1];
-      } else {
-        slots[0] = T.pvtx_slot[kl];
-        slots[1] = T.ptri_slot[3 * kr]; slots[2] = T.ptri_slot[3 * kr + 1]; slots[3] = T.ptri_slot[3 * kr + 2];
-      }
+      nm::Quad Q;
+      const uint32_t hv = W.hits[k];
+      const int kind = (int)(hv >> 16), kl = (int)((hv >> 8) & 0xffu), kr = (int)(hv & 0xffu);
+      sl = (kind == 1) ? 1 : 0;
+      sr = 1 - sl;
       const bool ee = kind == 2;
+      if (ee) {
+        const uint8_t *el = blob_bytes(W, sl, Lay::eslot), *er = blob_bytes(W, sr, Lay::eslot);
+        slots[0] = el[2 * kl]; slots[1] = el[2 * kl + 1];
+        slots[2] = er[2 * kr]; slots[3] = er[2 * kr + 1];
+      } else {
+        const uint8_t *vl = blob_bytes(W, sl, Lay::vslot), *tr = blob_bytes(W, sr, Lay::tslot);
+        slots[0] = vl[kl];
+        slots[1] = tr[3 * kr]; slots[2] = tr[3 * kr + 1]; slots[3] = tr[3 * kr + 2];
+      }
       // vertex k belongs to side sl for the first primitive, sr for the second
       const int nfirst = ee ? 2 : 1;
-      nm::Quad Q;
       Q.ee = ee;
       double lo[2][3], hi[2][3];
 #pragma unroll
@@ -240,7 +265,7 @@ __device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &
         const bool second = v >= nfirst;
         const int side = second ? sr : sl;
         const double *pp = W.pos[side][slots[v]];
-        const double shx = side ? pr.sh[0] : 0.0, shy = side ? pr.sh[1] : 0.0, shz = side ? pr.sh[2] : 0.0;
+        const double shx = side ? sh[0] : 0.0, shy = side ? sh[1] : 0.0, shz = side ? sh[2] : 0.0;
         Q.X0[v] = nm::mk(pp[0] + shx, pp[1] + shy, pp[2] + shz);
         Q.D[v] = nm::mk(pp[3] - pp[0], pp[4] - pp[1], pp[5] - pp[2]);
 #pragma unroll
@@ -253,7 +278,7 @@ __device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &
       bool ov = true;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const double s0 = sl ? pr.sh[q] : 0.0, s1 = sr ? pr.sh[q] : 0.0;
+        const double s0 = sl ? sh[q] : 0.0, s1 = sr ? sh[q] : 0.0;
         const double l0 = (lo[0][q] - h) + s0, u0 = (hi[0][q] + h) + s0;
         const double l1 = (lo[1][q] - h) + s1, u1 = (hi[1][q] + h) + s1;
         ov = ov && l0 <= u1 && l1 <= u0;
@@ -262,9 +287,9 @@ __device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &
         is_cand = true;
         if (ee) ++nee; else ++nvt;
         c.kind = kind;
-        c.i = ee ? T.pedge[kl] : T.pvtx[kl];
-        c.j = ee ? T.pedge[kr] : T.ptri[kr];
-        need = nm::needs_root_search<N>(Q, d);
+        c.i = ee ? W.blob[sl][Lay::pedge + kl] : W.blob[sl][Lay::pvtx + kl];
+        c.j = ee ? W.blob[sr][Lay::pedge + kr] : W.blob[sr][Lay::ptri + kr];
+        need = nm::needs_root_search<N>(Q, d) && nm::may_be_inside(Q);
       }
     }
     const unsigned long long mh = __ballot(need);
@@ -275,7 +300,22 @@ __device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &
       b = __shfl(b, leader, 64);
       if (need) {
         const unsigned long long slot = b + __popcll(mh & lanemask_lt());
-        if ((int64_t)slot < hard_cap) hard[slot] = c;
+        if ((int64_t)slot < hard_cap) {
+          hard[slot] = c;
+          // the geometry again from LDS (same arithmetic as above), so that it
+          // is not held in registers through the screen
+          const int nfirst = c.kind == 2 ? 2 : 1;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int side = v >= nfirst ? sr : sl;
+            const double *pp = W.pos[side][slots[v]];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? sh[q] : 0.0);
+              geo[(12 + 3 * v + q) * hard_cap + slot] = pp[3 + q] - pp[q];
+            }
+          }
+        }
       }
     }
     if (list) {
@@ -297,10 +337,10 @@ __device__ void process_hits(WaveLds<TILE> &W, const DevTopo &T, const PairRec &
 }
 
 template <int N, int TILE>
-__global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const PairRec *pairs,
-                                                  const int64_t *ves_patch_off, const uint64_t *work,
-                                                  int64_t work_cap, double d, Cand *hard, int64_t hard_cap,
-                                                  Cand *list, int64_t list_cap, Counters *cnt) {
+__global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const PairRec *pairs, const WorkRec *work,
+                                                  int64_t work_cap, double d, Cand *hard, double *geo,
+                                                  int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt) {
+  using Lay = BlobLayout<TILE>;
   __shared__ WaveLds<TILE> W;
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
@@ -308,30 +348,38 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   nw = nw < work_cap ? nw : work_cap;
   unsigned long long nvt = 0, nee = 0, ntests = 0;
   for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
-    const uint64_t wr = work[w];
-    const int p = (int)(wr >> 32);
-    const int pk[2] = {(int)((wr >> 16) & 0xffffu), (int)(wr & 0xffffu)};
-    const PairRec pr = pairs[p];
-    const int ves[2] = {pr.a, pr.b};
+    const WorkRec wr = work[w];
+    const int p = wr.p;
+    const int P[2] = {wr.pa, wr.pb};
+    const int base[2] = {wr.base_a, wr.base_b};
+    double sh[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[c] = pairs[p].sh[c];
+    // both blobs: one round of 16-byte loads
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int4 *src = reinterpret_cast<const int4 *>(T.blob + (int64_t)P[side] * Lay::stride);
+      int4 *dst = reinterpret_cast<int4 *>(&W.blob[side][0]);
+#pragma unroll
+      for (int i = lane; i < Lay::stride / 4; i += 64) dst[i] = src[i];
+    }
+    __syncthreads();
     const double zero[3] = {0.0, 0.0, 0.0};
-    int P[2];
     float pb[2][6];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      P[side] = T.patch_off[S.topo_id[ves[side]]] + pk[side];
-      const int base = S.vtx_off[ves[side]];
-      const int r0 = T.pref_off[P[side]], nref = T.pref_off[P[side] + 1] - r0;
-      const double *sh = side ? pr.sh : zero;
+      const int nref = W.blob[side][Lay::hdr + 0];
+      const double *shs = side ? sh : zero;
       float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
       for (int r = lane; r < nref; r += 64) {
-        const int64_t g = base + T.pref[r0 + r];
+        const int64_t g = base[side] + W.blob[side][Lay::pref + r];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const double a = S.x0[c * (int64_t)S.n_vtx + g], b = S.x1[c * (int64_t)S.n_vtx + g];
           W.pos[side][r][c] = a;
           W.pos[side][r][3 + c] = b;
-          lo[c] = fminf(lo[c], __double2float_rd((fmin(a, b) - h) + sh[c]));
-          hi[c] = fmaxf(hi[c], __double2float_ru((fmax(a, b) + h) + sh[c]));
+          lo[c] = fminf(lo[c], __double2float_rd((fmin(a, b) - h) + shs[c]));
+          hi[c] = fmaxf(hi[c], __double2float_ru((fmax(a, b) + h) + shs[c]));
         }
       }
 #pragma unroll
@@ -344,23 +392,21 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     int nh = 0;  // buffered hits (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
-      const int lbeg = kind == 2 ? T.pedge_off[P[sl]] : T.pvtx_off[P[sl]];
-      const int lend = kind == 2 ? T.pedge_off[P[sl] + 1] : T.pvtx_off[P[sl] + 1];
-      const uint8_t *lslot = kind == 2 ? T.pedge_slot : T.pvtx_slot;
+      const int lcount = kind == 2 ? W.blob[sl][Lay::hdr + 3] : W.blob[sl][Lay::hdr + 1];
+      const int rcount = kind == 2 ? W.blob[sr][Lay::hdr + 3] : W.blob[sr][Lay::hdr + 2];
+      const uint8_t *lslot = blob_bytes(W, sl, kind == 2 ? Lay::eslot : Lay::vslot);
+      const uint8_t *rslot = blob_bytes(W, sr, kind == 2 ? Lay::eslot : Lay::tslot);
       const int lnv = kind == 2 ? 2 : 1;
-      const int rbeg = kind == 2 ? T.pedge_off[P[sr]] : T.ptri_off[P[sr]];
-      const int rend = kind == 2 ? T.pedge_off[P[sr] + 1] : T.ptri_off[P[sr] + 1];
-      const uint8_t *rslot = kind == 2 ? T.pedge_slot : T.ptri_slot;
       const int rnv = kind == 2 ? 2 : 3;
-      const double *shl = sl ? pr.sh : zero, *shr = sr ? pr.sh : zero;
+      const double *shl = sl ? sh : zero, *shr = sr ? sh : zero;
       // compact the primitives whose box meets the other patch's box (ballot + prefix count)
       int nl = 0, nr = 0;
-      for (int k0 = lbeg; k0 < lend; k0 += 64) {
+      for (int k0 = 0; k0 < lcount; k0 += 64) {
         const int k = k0 + lane;
         float bx[6];
         bool keep = false;
-        if (k < lend) {
-          prim_box32(W.pos[sl], lslot + (int64_t)lnv * k, lnv, h, shl, bx);
+        if (k < lcount) {
+          prim_box32(W.pos[sl], lslot + lnv * k, lnv, h, shl, bx);
           keep = ov6f(bx, pb[sr]);
         }
         const unsigned long long m = __ballot(keep);
@@ -368,16 +414,16 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           const int q = nl + __popcll(m & lanemask_lt());
 #pragma unroll
           for (int c = 0; c < 6; ++c) W.lbox[q][c] = bx[c];
-          W.lk[q] = k;
+          W.lk[q] = (uint8_t)k;
         }
         nl += __popcll(m);
       }
-      for (int k0 = rbeg; k0 < rend; k0 += 64) {
+      for (int k0 = 0; k0 < rcount; k0 += 64) {
         const int k = k0 + lane;
         float bx[6];
         bool keep = false;
-        if (k < rend) {
-          prim_box32(W.pos[sr], rslot + (int64_t)rnv * k, rnv, h, shr, bx);
+        if (k < rcount) {
+          prim_box32(W.pos[sr], rslot + rnv * k, rnv, h, shr, bx);
           keep = ov6f(bx, pb[sl]);
         }
         const unsigned long long m = __ballot(keep);
@@ -385,7 +431,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           const int q = nr + __popcll(m & lanemask_lt());
 #pragma unroll
           for (int c = 0; c < 6; ++c) W.rbox[q][c] = bx[c];
-          W.rk[q] = k;
+          W.rk[q] = (uint8_t)k;
         }
         nr += __popcll(m);
       }
@@ -405,17 +451,19 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           hit = ov6f(W.lbox[x], W.rbox[y]);
         }
         const unsigned long long m = __ballot(hit);
-        if (hit) W.hits[nh + __popcll(m & lanemask_lt())] = make_int4(kind, W.lk[x], W.rk[y], 0);
+        if (hit)
+          W.hits[nh + __popcll(m & lanemask_lt())] =
+              ((uint32_t)kind << 16) | ((uint32_t)W.lk[x] << 8) | (uint32_t)W.rk[y];
         nh += __popcll(m);
         if (nh > kHitBuf - 64) {
-          process_hits<N, TILE>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+          process_hits<N, TILE>(W, sh, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
           nh = 0;
         }
       }
       __syncthreads();
     }
-    // the buffered hits refer to this work item's LDS positions: finish them now
-    if (nh) process_hits<N, TILE>(W, T, pr, p, P, d, hard, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+    // the buffered hits refer to this work item's LDS data: finish them now
+    if (nh) process_hits<N, TILE>(W, sh, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
   }
   for (int off = 32; off > 0; off >>= 1) {
     nvt += __shfl_xor(nvt, off, 64);
@@ -432,32 +480,32 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
 
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
-                        uint64_t *work, int64_t work_cap, Counters *cnt, hipStream_t st) {
+                        WorkRec *work, int64_t work_cap, Counters *cnt, hipStream_t st) {
   k_patch_pairs<<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap, cnt,
                                              pairs_cap);
 }
 
 template <int TILE>
-static void launch_tile(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const int64_t *ves_patch_off,
-                        const uint64_t *work, int64_t work_cap, double d, Cand *hard, int64_t hard_cap, Cand *list,
+static void launch_tile(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const WorkRec *work,
+                        int64_t work_cap, double d, Cand *hard, double *geo, int64_t hard_cap, Cand *list,
                         int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (d == 0.0)
-    k_prim_cand<3, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
-                                              list_cap, cnt);
+    k_prim_cand<3, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, work, work_cap, d, hard, geo, hard_cap, list, list_cap,
+                                              cnt);
   else
-    k_prim_cand<6, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list,
-                                              list_cap, cnt);
+    k_prim_cand<6, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, work, work_cap, d, hard, geo, hard_cap, list, list_cap,
+                                              cnt);
 }
 
 void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,
-                      const int64_t *ves_patch_off, const uint64_t *work, int64_t work_cap, double d, Cand *hard,
+                      const WorkRec *work, int64_t work_cap, double d, Cand *hard, double *hard_geo,
                       int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (tile <= 16)
-    launch_tile<16>(blocks, S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+    launch_tile<16>(blocks, S, T, pairs, work, work_cap, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
   else if (tile <= 32)
-    launch_tile<32>(blocks, S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+    launch_tile<32>(blocks, S, T, pairs, work, work_cap, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
   else
-    launch_tile<64>(blocks, S, T, pairs, ves_patch_off, work, work_cap, d, hard, hard_cap, list, list_cap, cnt, st);
+    launch_tile<64>(blocks, S, T, pairs, work, work_cap, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
 }
 
 }  // namespace stiv

@@ -146,35 +146,35 @@ __host__ __device__ void bernstein_on(const double f[N + 1], double u, double wd
     for (int j = N; j >= r; --j) b[j] += b[j - 1];
 }
 
-// Root of f in [lo, hi] where f(lo) = flo != 0 and f changes sign: Newton
-// steps kept inside the shrinking bracket, bisection when a step would leave
-// it or converge too slowly; stops at a step below 2^-52 or a bracket of
-// width 2^-50.
+// Root of f in [lo, hi] where f(lo) = flo != 0 and f changes sign, by the
+// Illinois variant of regula falsi: the secant point of the bracket, with the
+// value kept at an end that was not replaced twice in a row halved, which
+// restores superlinear convergence where plain regula falsi stalls.  Stops at
+// an exact zero or a bracket of width 2^-50.  Chosen over safeguarded Newton
+// for its short tail: the slowest of 64 lanes decides the cost on a wavefront.
 template <int N>
 __host__ __device__ double refine(const double f[N + 1], double lo, double hi, double flo) {
   const double tol = 8.881784197001252e-16;
-  double x = 0.5 * (lo + hi), dx = hi - lo, dxold = dx;
+  double fhi = horner<N>(f, hi);
+  int side = 0;
+  double x = 0.5 * (lo + hi);
   for (int it = 0; it < 100; ++it) {
-    double fx = f[N], dfx = 0.0;
-#pragma unroll
-    for (int k = N - 1; k >= 0; --k) {
-      dfx = dfx * x + fx;
-      fx = fx * x + f[k];
-    }
+    x = (lo * fhi - hi * flo) / (fhi - flo);
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+    const double fx = horner<N>(f, x);
     if (fx == 0.0) return x;
-    if ((fx < 0.0) == (flo < 0.0)) { lo = x; flo = fx; } else { hi = x; }
-    if (hi - lo <= tol) break;
-    const double xn = (dfx != 0.0) ? x - fx / dfx : x;
-    if (!(xn > lo && xn < hi) || fabs(2.0 * fx) > fabs(dxold * dfx)) {
-      dxold = dx;
-      dx = 0.5 * (hi - lo);
-      x = lo + dx;
+    if ((fx < 0.0) == (flo < 0.0)) {
+      lo = x;
+      flo = fx;
+      if (side == -1) fhi *= 0.5;
+      side = -1;
     } else {
-      dxold = dx;
-      dx = xn - x;
-      x = xn;
-      if (fabs(dx) <= 2.220446049250313e-16 * fmax(fabs(x), 1e-300)) break;
+      hi = x;
+      fhi = fx;
+      if (side == 1) flo *= 0.5;
+      side = 1;
     }
+    if (hi - lo <= tol) break;
   }
   return x;
 }
@@ -184,6 +184,13 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
 // lo + (hi - lo) [idx 2^-level, (idx + 1) 2^-level].  Returns 1 with *s_out on
 // contact.  *visits counts the intervals examined (shared budget across
 // calls); *deg counts degenerate skips.
+//
+// The search alternates two phases: subdivide until the next interval that
+// isolates a root (or the end), then refine that root and test it.  On a
+// wavefront, lanes that have isolated a root wait at the end of the first
+// phase, so the refinements of all lanes run together once per root instead
+// of once per subdivision step of any lane.  The intervals visited and the
+// roots computed are those of a plain depth-first traversal.
 template <int N>
 __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double lo, double hi, double *s_out,
                                   int *visits, int *deg) {
@@ -192,59 +199,67 @@ __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double l
   const double span = hi - lo;
   int level = 0;
   long long idx = 0;
-  while (true) {
-    if (++(*visits) > kMaxVisits) {
-      (*deg)++;
-      return 0;
-    }
-    const double wd = ldexp(1.0, -level);
-    const double u = lo + span * ((double)idx * wd);
-    const double v = lo + span * ((double)(idx + 1) * wd);
-    double b[N + 1];
-    bernstein_on<N>(f, u, v - u, b);
-    bool pos = true, neg = true;
-    int changes = 0, last = 0;
+  bool done = false;
+  while (!done) {
+    // phase 1: next isolated root (u, v, fu) or a root found directly (root >= 0)
+    bool iso = false;
+    double u = 0.0, v = 0.0, fu = 0.0, root = -1.0;
+    while (!done && !iso) {
+      if (++(*visits) > kMaxVisits) {
+        (*deg)++;
+        return 0;
+      }
+      const double wd = ldexp(1.0, -level);
+      u = lo + span * ((double)idx * wd);
+      v = lo + span * ((double)(idx + 1) * wd);
+      double b[N + 1];
+      bernstein_on<N>(f, u, v - u, b);
+      bool pos = true, neg = true;
+      int changes = 0, last = 0;
 #pragma unroll
-    for (int k = 0; k <= N; ++k) {
-      pos &= b[k] > 0.0;
-      neg &= b[k] < 0.0;
-      const int sg = (b[k] > 0.0) - (b[k] < 0.0);
-      if (sg != 0) {
-        if (last != 0 && sg != last) ++changes;
-        last = sg;
-      }
-    }
-    bool descend = false;
-    if (!(pos || neg)) {
-      const double fu = horner<N>(f, u), fv = horner<N>(f, v);
-      double root = -1.0;
-      if (changes == 1 && b[0] != 0.0 && b[N] != 0.0 && fu != 0.0 && fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
-        root = refine<N>(f, u, v, fu);
-      } else if (level < kMaxLevel) {
-        descend = true;
-      } else if (fu == 0.0) {
-        root = u;
-      } else if (fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
-        root = refine<N>(f, u, v, fu);
-      }
-      if (root >= 0.0) {
-        const int in = inside_at(Q, root);
-        if (in < 0) (*deg)++;
-        if (in == 1) {
-          *s_out = root;
-          return 1;
+      for (int k = 0; k <= N; ++k) {
+        pos &= b[k] > 0.0;
+        neg &= b[k] < 0.0;
+        const int sg = (b[k] > 0.0) - (b[k] < 0.0);
+        if (sg != 0) {
+          if (last != 0 && sg != last) ++changes;
+          last = sg;
         }
       }
+      bool descend = false;
+      if (!(pos || neg)) {
+        fu = horner<N>(f, u);
+        const double fv = horner<N>(f, v);
+        if (changes == 1 && b[0] != 0.0 && b[N] != 0.0 && fu != 0.0 && fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
+          iso = true;
+        } else if (level < kMaxLevel) {
+          descend = true;
+        } else if (fu == 0.0) {
+          root = u;
+          iso = true;
+        } else if (fv != 0.0 && ((fu < 0.0) != (fv < 0.0))) {
+          iso = true;
+        }
+      }
+      if (descend) {
+        ++level;
+        idx <<= 1;
+        continue;
+      }
+      // move past this interval (the traversal resumes there if the root is not valid)
+      while (level > 0 && (idx & 1)) { idx >>= 1; --level; }
+      if (level == 0) done = true;
+      else ++idx;
     }
-    if (descend) {
-      ++level;
-      idx <<= 1;
-      continue;
+    if (!iso) break;
+    // phase 2: refine and test
+    if (root < 0.0) root = refine<N>(f, u, v, fu);
+    const int in = inside_at(Q, root);
+    if (in < 0) (*deg)++;
+    if (in == 1) {
+      *s_out = root;
+      return 1;
     }
-    // next interval in left-to-right order
-    while (level > 0 && (idx & 1)) { idx >>= 1; --level; }
-    if (level == 0) break;
-    ++idx;
   }
   return 0;
 }
@@ -368,6 +383,87 @@ __host__ __device__ inline void volume_grad(const Quad &Q, double s, double d, d
   g[3] = ga.x; g[4] = ga.y; g[5] = ga.z;
   g[6] = gb.x; g[7] = gb.y; g[8] = gb.z;
   g[9] = gc.x; g[10] = gc.y; g[11] = gc.z;
+}
+
+// Bernstein coefficients on [0,1] of a degree-4 polynomial c (times 12, the
+// lcm of C(4,k)).
+__host__ __device__ inline void bern4(const double c[5], double b[5]) {
+  constexpr BernScale<4> L{};
+#pragma unroll
+  for (int k = 0; k <= 4; ++k) b[k] = c[k] * L.v[k];
+#pragma unroll
+  for (int r = 1; r <= 4; ++r)
+#pragma unroll
+    for (int j = 4; j >= r; --j) b[j] += b[j - 1];
+}
+
+// True if c < -tol on all of [0,1], proved by its Bernstein coefficients
+// (times 12: tol is scaled the same way).
+__host__ __device__ inline bool below_on01(const double c[5], double tol) {
+  double b[5];
+  bern4(c, b);
+  bool all = true;
+#pragma unroll
+  for (int k = 0; k <= 4; ++k) all &= b[k] < -12.0 * tol;
+  return all;
+}
+
+__host__ __device__ inline double norm1(const d3 &a) { return fabs(a.x) + fabs(a.y) + fabs(a.z); }
+
+// False when the closest-point test of the narrow phase fails at every s in
+// [0,1], so that no root of F can be a contact.  With the edge vectors u, v,
+// w and normal n = u x v of poly_coeffs (all polynomials in s):
+// alpha = (w x v).n, beta = (w x u).n, q = |n|^2 (degree 4).  Vertex-triangle
+// inside test: alpha >= 0, -beta >= 0, alpha - beta <= q; edge-edge:
+// 0 <= alpha <= q and 0 <= beta <= q.  One of these failing with a margin on
+// all of [0,1] (Bernstein coefficients) excludes every root.  The margin,
+// 1e-10 of a bound on the magnitude of each polynomial on [0,1], is far above
+// the rounding of these coefficients and of the test at a root, so the
+// decision agrees with the test itself.
+__host__ __device__ inline bool may_be_inside(const Quad &Q) {
+  d3 u0, u1, v0, v1, w0, w1;
+  if (!Q.ee) {
+    u0 = Q.X0[2] - Q.X0[1]; u1 = Q.D[2] - Q.D[1];
+    v0 = Q.X0[3] - Q.X0[1]; v1 = Q.D[3] - Q.D[1];
+    w0 = Q.X0[0] - Q.X0[1]; w1 = Q.D[0] - Q.D[1];
+  } else {
+    u0 = Q.X0[1] - Q.X0[0]; u1 = Q.D[1] - Q.D[0];
+    v0 = Q.X0[3] - Q.X0[2]; v1 = Q.D[3] - Q.D[2];
+    w0 = Q.X0[2] - Q.X0[0]; w1 = Q.D[2] - Q.D[0];
+  }
+  const d3 n0 = crossp(u0, v0), n1 = crossp(u0, v1) + crossp(u1, v0), n2 = crossp(u1, v1);
+  const d3 a0 = crossp(w0, v0), a1 = crossp(w0, v1) + crossp(w1, v0), a2 = crossp(w1, v1);
+  const d3 c0 = crossp(w0, u0), c1 = crossp(w0, u1) + crossp(w1, u0), c2 = crossp(w1, u1);
+  const double al[5] = {dotp(a0, n0), dotp(a0, n1) + dotp(a1, n0), dotp(a0, n2) + dotp(a1, n1) + dotp(a2, n0),
+                        dotp(a1, n2) + dotp(a2, n1), dotp(a2, n2)};
+  const double be[5] = {dotp(c0, n0), dotp(c0, n1) + dotp(c1, n0), dotp(c0, n2) + dotp(c1, n1) + dotp(c2, n0),
+                        dotp(c1, n2) + dotp(c2, n1), dotp(c2, n2)};
+  const double qq[5] = {dotp(n0, n0), 2.0 * dotp(n0, n1), dotp(n1, n1) + 2.0 * dotp(n0, n2), 2.0 * dotp(n1, n2),
+                        dotp(n2, n2)};
+  const double Nn = norm1(n0) + norm1(n1) + norm1(n2);
+  const double Ma = (norm1(w0) + norm1(w1)) * (norm1(v0) + norm1(v1)) * Nn;
+  const double Mb = (norm1(w0) + norm1(w1)) * (norm1(u0) + norm1(u1)) * Nn;
+  const double Mq = Nn * Nn;
+  const double e = 1e-10;
+  double t[5];
+  if (below_on01(al, e * Ma)) return false;  // alpha < 0 throughout
+  if (!Q.ee) {
+#pragma unroll
+    for (int k = 0; k <= 4; ++k) t[k] = -be[k];
+    if (below_on01(t, e * Mb)) return false;  // -beta < 0 throughout
+#pragma unroll
+    for (int k = 0; k <= 4; ++k) t[k] = (qq[k] - al[k]) + be[k];
+    if (below_on01(t, e * (Ma + Mb + Mq))) return false;  // alpha - beta > q throughout
+    return true;
+  }
+  if (below_on01(be, e * Mb)) return false;  // beta < 0 throughout
+#pragma unroll
+  for (int k = 0; k <= 4; ++k) t[k] = qq[k] - al[k];
+  if (below_on01(t, e * (Ma + Mq))) return false;  // alpha > q throughout
+#pragma unroll
+  for (int k = 0; k <= 4; ++k) t[k] = qq[k] - be[k];
+  if (below_on01(t, e * (Mb + Mq))) return false;  // beta > q throughout
+  return true;
 }
 
 // Screen of one candidate: true if F may have a root in [0,1] or the vertex

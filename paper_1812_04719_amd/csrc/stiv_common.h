@@ -29,6 +29,30 @@ template <>
 struct TileCaps<64> {
   static constexpr int ref = 64, ownv = 64, owne = 128;
 };
+// Per-patch blob: everything the primitive kernel needs about one patch in
+// one contiguous, fixed-stride block of ints, so a work item stages both
+// patches with one round of coalesced loads.  Layout (ints): header (number
+// of referenced vertices, owned vertices, triangles, owned edges), the
+// referenced vertices' local ids, owned vertex ids, triangle ids, owned edge
+// ids, then byte arrays packed four to an int: slot (index into the
+// referenced list) of every owned vertex, of the three corners of every
+// triangle and of the two ends of every owned edge.
+template <int TILE>
+struct BlobLayout {
+  static constexpr int ref = TileCaps<TILE>::ref, ownv = TileCaps<TILE>::ownv, owne = TileCaps<TILE>::owne;
+  static constexpr int hdr = 0, pref = 4, pvtx = pref + ref, ptri = pvtx + ownv, pedge = ptri + TILE,
+                       vslot = pedge + owne, tslot = vslot + ownv / 4, eslot = tslot + 3 * TILE / 4,
+                       used = eslot + 2 * owne / 4, stride = (used + 63) / 64 * 64;
+  static_assert(ownv % 4 == 0 && (3 * TILE) % 4 == 0 && (2 * owne) % 4 == 0, "byte arrays fill whole ints");
+};
+
+// Patch-pair work item: pair index, global patch-table indices of the two
+// patches and the first global vertex of each vesicle.
+struct __align__(16) WorkRec {
+  int p, pa, pb, base_a;
+  int base_b, pad[3];
+};
+
 constexpr int kMaxPatchTri = 64;   // largest supported patch
 constexpr int kMaxPatchRef = 64;
 constexpr int kMaxPatchesPerVes = 1024;
@@ -53,6 +77,8 @@ struct DevTopo {
   const int *pref_off, *pref;          // referenced vertices (local ids)
   const int *vbase;                    // [n_topo] first row of each topology in vp_off
   const int *vp_off, *vp;              // vertex -> patches (local patch index) referencing it
+  const int *blob;                     // [n_ptab][blob_stride] patch blobs (BlobLayout of the current tile)
+  int blob_stride;
 };
 
 struct DevScene {
@@ -143,13 +169,16 @@ void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const
 // K2
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
-                        uint64_t *work, int64_t work_cap, Counters *cnt, hipStream_t st);
+                        WorkRec *work, int64_t work_cap, Counters *cnt, hipStream_t st);
+// hard_geo: geometry of the queued candidates for the root search, SoA
+// [24][hard_cap]: X0 (shifted) x, y, z of vertices 0..3, then D = X1 - X0.
 void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,
-                      const int64_t *ves_patch_off, const uint64_t *work, int64_t work_cap, double d, Cand *hard,
+                      const WorkRec *work, int64_t work_cap, double d, Cand *hard, double *hard_geo,
                       int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st);
 
 // K3 + K4: root search on the queued candidates, volumes and gradients
-void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard, int64_t hard_cap,
+void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard,
+                   const double *hard_geo, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
                    int64_t ct_cap, const float *mlp_params, float kwidth, Counters *cnt, hipStream_t st);
 

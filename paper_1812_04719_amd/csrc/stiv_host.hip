@@ -56,7 +56,7 @@ struct stiv_ctx {
   // topology (device)
   Buf t_nv, t_nt, t_ne, t_tri_off, t_edge_off, t_tri, t_edge, t_patch_off, t_ptri_off, t_ptri, t_ptri_slot,
       t_pvtx_off, t_pvtx, t_pvtx_slot, t_pedge_off, t_pedge, t_pedge_slot, t_pref_off, t_pref, t_vbase, t_vp_off,
-      t_vp;
+      t_vp, t_blob;
   DevTopo topo{};
   std::vector<int> h_npatch;  // patches per topology
   int max_patches = 0;
@@ -68,7 +68,7 @@ struct stiv_ctx {
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
-      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx;
+      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
   Buf toi_params, mlp_part;
   // LCP matrix assembly scratch
@@ -139,7 +139,8 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
   Buf *all[] = {&ctx->t_nv, &ctx->t_nt, &ctx->t_ne, &ctx->t_tri_off, &ctx->t_edge_off, &ctx->t_tri, &ctx->t_edge,
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
-                &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->t_blob,
+                &ctx->hard_geo, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
@@ -315,6 +316,43 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
     }
     patch_off.push_back(patch_off.back() + np);
   }
+  // fixed-stride patch blobs for the current tile size
+  int bs = 0;
+  {
+    auto build_blobs = [&](auto layout_tag) {
+      using Lay = decltype(layout_tag);
+      const int n_ptab = (int)ptri_off.size() - 1;
+      std::vector<int> blob((size_t)n_ptab * Lay::stride, 0);
+      for (int P = 0; P < n_ptab; ++P) {
+        int *B = blob.data() + (size_t)P * Lay::stride;
+        const int r0 = pref_off[P], nr = pref_off[P + 1] - r0;
+        const int v0 = pvtx_off[P], nvx = pvtx_off[P + 1] - v0;
+        const int t0 = ptri_off[P], ntr = ptri_off[P + 1] - t0;
+        const int e0 = pedge_off[P], ned = pedge_off[P + 1] - e0;
+        B[Lay::hdr + 0] = nr; B[Lay::hdr + 1] = nvx; B[Lay::hdr + 2] = ntr; B[Lay::hdr + 3] = ned;
+        uint8_t *vs = reinterpret_cast<uint8_t *>(B + Lay::vslot);
+        uint8_t *ts = reinterpret_cast<uint8_t *>(B + Lay::tslot);
+        uint8_t *es = reinterpret_cast<uint8_t *>(B + Lay::eslot);
+        for (int k = 0; k < nr; ++k) B[Lay::pref + k] = pref[r0 + k];
+        for (int k = 0; k < nvx; ++k) { B[Lay::pvtx + k] = pvtx[v0 + k]; vs[k] = pvtx_slot[v0 + k]; }
+        for (int k = 0; k < ntr; ++k) {
+          B[Lay::ptri + k] = ptri[t0 + k];
+          for (int r = 0; r < 3; ++r) ts[3 * k + r] = ptri_slot[3 * (size_t)(t0 + k) + r];
+        }
+        for (int k = 0; k < ned; ++k) {
+          B[Lay::pedge + k] = pedge[e0 + k];
+          es[2 * k] = pedge_slot[2 * (size_t)(e0 + k)];
+          es[2 * k + 1] = pedge_slot[2 * (size_t)(e0 + k) + 1];
+        }
+      }
+      bs = Lay::stride;
+      return upload(ctx->t_blob, blob);
+    };
+    hipError_t e = ctx->tile == 16 ? build_blobs(BlobLayout<16>{})
+                   : ctx->tile == 32 ? build_blobs(BlobLayout<32>{})
+                                     : build_blobs(BlobLayout<64>{});
+    HIPCHK(e);
+  }
   HIPCHK(upload(ctx->t_nv, nv));
   HIPCHK(upload(ctx->t_nt, ntv));
   HIPCHK(upload(ctx->t_ne, nev));
@@ -349,6 +387,8 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   D.pedge_slot = P<uint8_t>(ctx->t_pedge_slot);
   D.pref_off = P<int>(ctx->t_pref_off); D.pref = P<int>(ctx->t_pref);
   D.vbase = P<int>(ctx->t_vbase); D.vp_off = P<int>(ctx->t_vp_off); D.vp = P<int>(ctx->t_vp);
+  D.blob = P<int>(ctx->t_blob);
+  D.blob_stride = bs;
   ctx->have_topo = true;
   return STIV_OK;
 }
@@ -386,8 +426,9 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->ves_patch_cnt, 8 * (N + 1)));
   HIPCHK(ensure(ctx->ves_patch_off, 8 * (N + 2)));
   HIPCHK(ensure(ctx->patch_box, 6 * 8 * (ctx->cap_patch + 1)));
-  HIPCHK(ensure(ctx->work, 8 * ctx->cap_work));
+  HIPCHK(ensure(ctx->work, sizeof(WorkRec) * ctx->cap_work));
   HIPCHK(ensure(ctx->cand, sizeof(Cand) * ctx->cap_cand));
+  HIPCHK(ensure(ctx->hard_geo, 24 * sizeof(double) * ctx->cap_cand));
   HIPCHK(ensure(ctx->ct, sizeof(Cand) * ctx->cap_ct));
   HIPCHK(ensure(ctx->ct_s, 8 * ctx->cap_ct));
   HIPCHK(ensure(ctx->ct_vol, 8 * ctx->cap_ct));
@@ -518,16 +559,17 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   if (timed) (void)hipEventRecord(ctx->ev[2], st);
   // ---- K2 primitive broad phase
   launch_patch_pairs(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, P<double>(ctx->ves_box),
-                     P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<uint64_t>(ctx->work),
+                     P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<WorkRec>(ctx->work),
                      ctx->cap_work, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[3], st);
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
-  launch_prim_cand(ctx->tile, ctx->prim_blocks, S, T, P<PairRec>(ctx->pairs), P<int64_t>(ctx->ves_patch_off), P<uint64_t>(ctx->work),
-                   ctx->cap_work, p->d, P<Cand>(ctx->cand), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
+  launch_prim_cand(ctx->tile, ctx->prim_blocks, S, T, P<PairRec>(ctx->pairs), P<WorkRec>(ctx->work),
+                   ctx->cap_work, p->d, P<Cand>(ctx->cand), P<double>(ctx->hard_geo), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
                    emit ? ctx->cap_list : 0, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[4], st);
   // ---- K3 + K4 root search, volumes and gradients
-  launch_narrow(ctx->narrow_blocks, S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), ctx->cap_cand, p->d, p->eps,
+  launch_narrow(ctx->narrow_blocks, S, T, P<PairRec>(ctx->pairs), P<Cand>(ctx->cand), P<double>(ctx->hard_geo),
+                ctx->cap_cand, p->d, p->eps,
                 p->dt,
                 P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
                 (p->flags & STIV_LEARNED_BRACKET) ? P<float>(ctx->toi_params) : nullptr, ctx->toi_kwidth, cnt, st);
