@@ -36,8 +36,10 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # LDS: 128 bytes per clock per CU
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE + WRITE_SIZE on this workload,
-# scaled by the copy-kernel calibration factor (kept with the profile summaries)
-TRAFFIC_BYTES = {}
+# each scaled by the counter's reading for a plain 1 GiB copy (factors 2.0 and 1.0), for the
+# kernel as it was built when the counters were taken (profiles/, HBM traffic summary);
+# an entry is removed whenever its kernel changes.
+TRAFFIC_BYTES = {"k_prim_cand": 2.5429e9}
 
 
 def log(msg):

@@ -29,17 +29,6 @@ __device__ inline unsigned long long lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Wavefront-aggregated append: returns this lane's slot (valid iff `want`).
-__device__ inline unsigned long long wave_append(bool want, unsigned long long *counter) {
-  const unsigned long long m = __ballot(want);
-  const int n = __popcll(m);
-  unsigned long long base = 0;
-  const int leader = m ? __ffsll((long long)m) - 1 : 0;
-  if ((int)(threadIdx.x & 63) == leader && n) base = atomicAdd(counter, (unsigned long long)n);
-  base = __shfl(base, leader, 64);
-  return base + __popcll(m & lanemask_lt());
-}
-
 constexpr int kPPThreads = 256;
 constexpr int kPPBuf = 512;
 
@@ -165,45 +154,50 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 // --------------------------------------------------------------------------
 constexpr int kHitBuf = 256;
 
+// Up to kSlots work items can keep their FP64 positions and slot tables in
+// LDS until their hits are processed, so that one round of the exact test
+// and screens serves the hits of several work items (a work item has about
+// 20 hits on average).  Measured at 1440 vesicles, 2 or 3 slots cost more
+// (lower occupancy from the larger LDS footprint) than the fuller rounds
+// save, so one slot is used.
+constexpr int kSlots = 1;
+
 template <int TILE>
 struct WaveLds {
   using Lay = BlobLayout<TILE>;
   static constexpr int kRef = TileCaps<TILE>::ref;
-  static constexpr int kL = TileCaps<TILE>::owne > TileCaps<TILE>::ownv ? TileCaps<TILE>::owne : TileCaps<TILE>::ownv;
+  static constexpr int kL = 64;  // the left-hand list is built 64 primitives at a time
   static constexpr int kR = TileCaps<TILE>::owne > TILE ? TileCaps<TILE>::owne : TILE;
-  double pos[2][kRef][6];      // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
-  float lbox[kL][6];           // left-hand list of the current kind: FP32 boxes
-  float rbox[kR][6];           // right-hand list
-  uint8_t lk[kL];              // patch-local indices of the left-hand list
-  uint8_t rk[kR];              // and of the right-hand list
-  uint32_t hits[kHitBuf];      // kind << 16 | left << 8 | right (patch-local indices)
-  alignas(16) int blob[2][Lay::stride];  // the two patch blobs
+  double pos[kSlots][2][kRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
+  double sh[kSlots][3];            // image shift of each slot's pair
+  int P[kSlots][2], pair[kSlots];  // patch-table indices and pair of each slot
+  float vbox[2][kRef][6];          // FP32 space-time box of each referenced vertex (current work item)
+  float lbox[kL][6];               // left-hand list (current chunk) of the current kind: FP32 boxes
+  float rbox[kR][6];               // right-hand list
+  uint8_t lk[kL];                  // patch-local indices of the left-hand list
+  uint8_t rk[kR];                  // and of the right-hand list
+  uint32_t hits[kHitBuf];          // slot << 18 | kind << 16 | left << 8 | right (patch-local indices)
+  alignas(16) int blob[kSlots][2][Lay::lds];  // header and slot arrays of the two patch blobs
 };
 
 __device__ inline bool ov6f(const float *A, const float *B) {
   return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
 }
 
-// FP64 box of a primitive (min - h + sh, max + h + sh), rounded outward to FP32.
-__device__ inline void prim_box32(const double (*pos)[6], const uint8_t *slot, int nvert, double h, const double *sh,
-                                  float *out) {
-  double lo[3], hi[3];
+// FP64 box of a primitive (min - h + sh, max + h + sh), rounded outward to
+// FP32, as the min / max of its vertices' FP32 boxes.  The map
+// m -> round_down(fl(fl(m - h) + sh)) is monotone, so the min over vertices
+// of the rounded vertex bounds is the rounded bound of the min: the same box
+// as rounding the primitive's FP64 box.
+__device__ inline void prim_box32(const float (*vbox)[6], const uint8_t *slot, int nvert, float *out) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    lo[c] = fmin(pos[slot[0]][c], pos[slot[0]][3 + c]);
-    hi[c] = fmax(pos[slot[0]][c], pos[slot[0]][3 + c]);
-  }
+  for (int c = 0; c < 6; ++c) out[c] = vbox[slot[0]][c];
   for (int k = 1; k < nvert; ++k)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      lo[c] = fmin(lo[c], fmin(pos[slot[k]][c], pos[slot[k]][3 + c]));
-      hi[c] = fmax(hi[c], fmax(pos[slot[k]][c], pos[slot[k]][3 + c]));
+      out[c] = fminf(out[c], vbox[slot[k]][c]);
+      out[3 + c] = fmaxf(out[3 + c], vbox[slot[k]][3 + c]);
     }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    out[c] = __double2float_rd((lo[c] - h) + sh[c]);
-    out[3 + c] = __double2float_ru((hi[c] + h) + sh[c]);
-  }
 }
 
 __device__ inline float wave_minf(float v) {
@@ -216,14 +210,14 @@ __device__ inline float wave_maxf(float v) {
 }
 
 template <int TILE>
-__device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, int off) {
-  return reinterpret_cast<const uint8_t *>(&W.blob[side][off]);
+__device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int slot, int side, int off) {
+  return reinterpret_cast<const uint8_t *>(&W.blob[slot][side][off]);
 }
 
 // Exact FP64 box test of a buffered hit and the polynomial screen; queue the
 // candidates that need a root search.  All 64 lanes take part.
 template <int N, int TILE>
-__device__ void process_hits(WaveLds<TILE> &W, const double *sh, int p, double d, Cand *hard, double *geo,
+__device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand *hard, double *geo,
                              int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, unsigned long long &nvt,
                              unsigned long long &nee, int nh) {
   using Lay = BlobLayout<TILE>;
@@ -234,21 +228,24 @@ __device__ void process_hits(WaveLds<TILE> &W, const double *sh, int p, double d
     const int k = r0 + lane;
     bool is_cand = false, need = false;
     Cand c;
-    c.pair = p; c.kind = 0; c.i = 0; c.j = 0;
-    int slots[4] = {0, 0, 0, 0}, sl = 0, sr = 1;
+    c.pair = 0; c.kind = 0; c.i = 0; c.j = 0;
+    int slots[4] = {0, 0, 0, 0}, sl = 0, sr = 1, ws = 0;
     if (k < nh) {
       nm::Quad Q;
       const uint32_t hv = W.hits[k];
-      const int kind = (int)(hv >> 16), kl = (int)((hv >> 8) & 0xffu), kr = (int)(hv & 0xffu);
+      ws = (int)(hv >> 18);
+      const int kind = (int)((hv >> 16) & 3u), kl = (int)((hv >> 8) & 0xffu), kr = (int)(hv & 0xffu);
+      const double *sh = W.sh[ws];
+      c.pair = W.pair[ws];
       sl = (kind == 1) ? 1 : 0;
       sr = 1 - sl;
       const bool ee = kind == 2;
       if (ee) {
-        const uint8_t *el = blob_bytes(W, sl, Lay::eslot), *er = blob_bytes(W, sr, Lay::eslot);
+        const uint8_t *el = blob_bytes(W, ws, sl, Lay::eslot), *er = blob_bytes(W, ws, sr, Lay::eslot);
         slots[0] = el[2 * kl]; slots[1] = el[2 * kl + 1];
         slots[2] = er[2 * kr]; slots[3] = er[2 * kr + 1];
       } else {
-        const uint8_t *vl = blob_bytes(W, sl, Lay::vslot), *tr = blob_bytes(W, sr, Lay::tslot);
+        const uint8_t *vl = blob_bytes(W, ws, sl, Lay::vslot), *tr = blob_bytes(W, ws, sr, Lay::tslot);
         slots[0] = vl[kl];
         slots[1] = tr[3 * kr]; slots[2] = tr[3 * kr + 1]; slots[3] = tr[3 * kr + 2];
       }
@@ -264,7 +261,7 @@ __device__ void process_hits(WaveLds<TILE> &W, const double *sh, int p, double d
       for (int v = 0; v < 4; ++v) {
         const bool second = v >= nfirst;
         const int side = second ? sr : sl;
-        const double *pp = W.pos[side][slots[v]];
+        const double *pp = W.pos[ws][side][slots[v]];
         const double shx = side ? sh[0] : 0.0, shy = side ? sh[1] : 0.0, shz = side ? sh[2] : 0.0;
         Q.X0[v] = nm::mk(pp[0] + shx, pp[1] + shy, pp[2] + shz);
         Q.D[v] = nm::mk(pp[3] - pp[0], pp[4] - pp[1], pp[5] - pp[2]);
@@ -287,8 +284,8 @@ __device__ void process_hits(WaveLds<TILE> &W, const double *sh, int p, double d
         is_cand = true;
         if (ee) ++nee; else ++nvt;
         c.kind = kind;
-        c.i = ee ? W.blob[sl][Lay::pedge + kl] : W.blob[sl][Lay::pvtx + kl];
-        c.j = ee ? W.blob[sr][Lay::pedge + kr] : W.blob[sr][Lay::ptri + kr];
+        c.i = gblob[(int64_t)W.P[ws][sl] * Lay::stride + (ee ? Lay::pedge : Lay::pvtx) + kl];
+        c.j = gblob[(int64_t)W.P[ws][sr] * Lay::stride + (ee ? Lay::pedge : Lay::ptri) + kr];
         need = nm::needs_root_search<N>(Q, d) && nm::may_be_inside(Q);
       }
     }
@@ -308,10 +305,10 @@ __device__ void process_hits(WaveLds<TILE> &W, const double *sh, int p, double d
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int side = v >= nfirst ? sr : sl;
-            const double *pp = W.pos[side][slots[v]];
+            const double *pp = W.pos[ws][side][slots[v]];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-              geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? sh[q] : 0.0);
+              geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? W.sh[ws][q] : 0.0);
               geo[(12 + 3 * v + q) * hard_cap + slot] = pp[3 + q] - pp[q];
             }
           }
@@ -347,39 +344,56 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
   unsigned long long nvt = 0, nee = 0, ntests = 0;
+  static_assert(kSlots <= 3, "slot id takes two bits of a hit record");
+  int nh = 0;   // buffered hits (wave-uniform)
+  int cur = 0;  // LDS slot of the current work item
   for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+    if (cur == kSlots) {  // all slots hold work items with pending hits: process them
+      if (nh) process_hits<N, TILE>(W, T.blob, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+      nh = 0;
+      cur = 0;
+    }
     const WorkRec wr = work[w];
-    const int p = wr.p;
     const int P[2] = {wr.pa, wr.pb};
     const int base[2] = {wr.base_a, wr.base_b};
     double sh[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sh[c] = pairs[p].sh[c];
-    // both blobs: one round of 16-byte loads
+    for (int c = 0; c < 3; ++c) sh[c] = pairs[wr.p].sh[c];
+    // header and slots of both blobs (16-byte loads), and the referenced
+    // vertex ids of both patches: one round of independent loads
+    int ref[2] = {-1, -1};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int4 *src = reinterpret_cast<const int4 *>(T.blob + (int64_t)P[side] * Lay::stride);
-      int4 *dst = reinterpret_cast<int4 *>(&W.blob[side][0]);
+      const int *gb = T.blob + (int64_t)P[side] * Lay::stride;
+      const int4 *src = reinterpret_cast<const int4 *>(gb);
+      int4 *dst = reinterpret_cast<int4 *>(&W.blob[cur][side][0]);
 #pragma unroll
-      for (int i = lane; i < Lay::stride / 4; i += 64) dst[i] = src[i];
+      for (int i = lane; i < Lay::lds / 4; i += 64) dst[i] = src[i];
+      if (lane < Lay::ref) ref[side] = gb[Lay::pref + lane];
     }
+    if (lane < 3) W.sh[cur][lane] = sh[lane];
+    if (lane < 2) W.P[cur][lane] = P[lane];
+    if (lane == 0) W.pair[cur] = wr.p;
     __syncthreads();
-    const double zero[3] = {0.0, 0.0, 0.0};
     float pb[2][6];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int nref = W.blob[side][Lay::hdr + 0];
-      const double *shs = side ? sh : zero;
+      const int nref = W.blob[cur][side][Lay::hdr + 0];
       float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-      for (int r = lane; r < nref; r += 64) {
-        const int64_t g = base[side] + W.blob[side][Lay::pref + r];
+      static_assert(Lay::ref <= 64, "one referenced vertex per lane");
+      if (lane < nref) {
+        const int r = lane;
+        const int64_t g = base[side] + ref[side];
+        const double sc[3] = {side ? sh[0] : 0.0, side ? sh[1] : 0.0, side ? sh[2] : 0.0};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const double a = S.x0[c * (int64_t)S.n_vtx + g], b = S.x1[c * (int64_t)S.n_vtx + g];
-          W.pos[side][r][c] = a;
-          W.pos[side][r][3 + c] = b;
-          lo[c] = fminf(lo[c], __double2float_rd((fmin(a, b) - h) + shs[c]));
-          hi[c] = fmaxf(hi[c], __double2float_ru((fmax(a, b) + h) + shs[c]));
+          W.pos[cur][side][r][c] = a;
+          W.pos[cur][side][r][3 + c] = b;
+          lo[c] = __double2float_rd((fmin(a, b) - h) + sc[c]);
+          hi[c] = __double2float_ru((fmax(a, b) + h) + sc[c]);
+          W.vbox[side][r][c] = lo[c];
+          W.vbox[side][r][3 + c] = hi[c];
         }
       }
 #pragma unroll
@@ -389,41 +403,23 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
       }
     }
     __syncthreads();
-    int nh = 0;  // buffered hits (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
-      const int lcount = kind == 2 ? W.blob[sl][Lay::hdr + 3] : W.blob[sl][Lay::hdr + 1];
-      const int rcount = kind == 2 ? W.blob[sr][Lay::hdr + 3] : W.blob[sr][Lay::hdr + 2];
-      const uint8_t *lslot = blob_bytes(W, sl, kind == 2 ? Lay::eslot : Lay::vslot);
-      const uint8_t *rslot = blob_bytes(W, sr, kind == 2 ? Lay::eslot : Lay::tslot);
+      const int lcount = kind == 2 ? W.blob[cur][sl][Lay::hdr + 3] : W.blob[cur][sl][Lay::hdr + 1];
+      const int rcount = kind == 2 ? W.blob[cur][sr][Lay::hdr + 3] : W.blob[cur][sr][Lay::hdr + 2];
+      const uint8_t *lslot = blob_bytes(W, cur, sl, kind == 2 ? Lay::eslot : Lay::vslot);
+      const uint8_t *rslot = blob_bytes(W, cur, sr, kind == 2 ? Lay::eslot : Lay::tslot);
       const int lnv = kind == 2 ? 2 : 1;
       const int rnv = kind == 2 ? 2 : 3;
-      const double *shl = sl ? sh : zero, *shr = sr ? sh : zero;
-      // compact the primitives whose box meets the other patch's box (ballot + prefix count)
-      int nl = 0, nr = 0;
-      for (int k0 = 0; k0 < lcount; k0 += 64) {
-        const int k = k0 + lane;
-        float bx[6];
-        bool keep = false;
-        if (k < lcount) {
-          prim_box32(W.pos[sl], lslot + lnv * k, lnv, h, shl, bx);
-          keep = ov6f(bx, pb[sr]);
-        }
-        const unsigned long long m = __ballot(keep);
-        if (keep) {
-          const int q = nl + __popcll(m & lanemask_lt());
-#pragma unroll
-          for (int c = 0; c < 6; ++c) W.lbox[q][c] = bx[c];
-          W.lk[q] = (uint8_t)k;
-        }
-        nl += __popcll(m);
-      }
+      // compact the primitives whose box meets the other patch's box (ballot +
+      // prefix count): the right-hand list whole, the left-hand list 64 at a time
+      int nr = 0;
       for (int k0 = 0; k0 < rcount; k0 += 64) {
         const int k = k0 + lane;
         float bx[6];
         bool keep = false;
         if (k < rcount) {
-          prim_box32(W.pos[sr], rslot + rnv * k, rnv, h, shr, bx);
+          prim_box32(W.vbox[sr], rslot + rnv * k, rnv, bx);
           keep = ov6f(bx, pb[sl]);
         }
         const unsigned long long m = __ballot(keep);
@@ -435,36 +431,54 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
         }
         nr += __popcll(m);
       }
-      __syncthreads();
-      // all left x right pairs, 64 per round; t = x * nr + y, with x = t / nr
-      // as (t * ceil(2^32 / nr)) >> 32, exact for t < 2^16 (t <= 128 * 128 here)
-      const int tot = nl * nr;
-      ntests += (unsigned long long)tot;
       const unsigned long long magic = nr ? ((1ull << 32) + (unsigned long long)nr - 1ull) / (unsigned long long)nr : 0ull;
-      for (int t0 = 0; t0 < tot; t0 += 64) {
-        const unsigned int t = (unsigned int)(t0 + lane);
-        bool hit = false;
-        int x = 0, y = 0;
-        if ((int)t < tot) {
-          x = (int)(((unsigned long long)t * magic) >> 32);
-          y = (int)t - x * nr;
-          hit = ov6f(W.lbox[x], W.rbox[y]);
+      for (int l0 = 0; l0 < (nr ? lcount : 0); l0 += 64) {
+        const int k = l0 + lane;
+        float bx[6];
+        bool keep = false;
+        if (k < lcount) {
+          prim_box32(W.vbox[sl], lslot + lnv * k, lnv, bx);
+          keep = ov6f(bx, pb[sr]);
         }
-        const unsigned long long m = __ballot(hit);
-        if (hit)
-          W.hits[nh + __popcll(m & lanemask_lt())] =
-              ((uint32_t)kind << 16) | ((uint32_t)W.lk[x] << 8) | (uint32_t)W.rk[y];
-        nh += __popcll(m);
-        if (nh > kHitBuf - 64) {
-          process_hits<N, TILE>(W, sh, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
-          nh = 0;
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+          const int q = __popcll(m & lanemask_lt());
+#pragma unroll
+          for (int c = 0; c < 6; ++c) W.lbox[q][c] = bx[c];
+          W.lk[q] = (uint8_t)k;
         }
+        const int nl = __popcll(m);
+        __syncthreads();
+        // all left x right pairs, 64 per round; t = x * nr + y, with x = t / nr
+        // as (t * ceil(2^32 / nr)) >> 32, exact for t < 2^16 (t <= 64 * 128 here)
+        const int tot = nl * nr;
+        ntests += (unsigned long long)tot;
+        for (int t0 = 0; t0 < tot; t0 += 64) {
+          const unsigned int t = (unsigned int)(t0 + lane);
+          bool hit = false;
+          int x = 0, y = 0;
+          if ((int)t < tot) {
+            x = (int)(((unsigned long long)t * magic) >> 32);
+            y = (int)t - x * nr;
+            hit = ov6f(W.lbox[x], W.rbox[y]);
+          }
+          const unsigned long long mh = __ballot(hit);
+          if (hit)
+            W.hits[nh + __popcll(mh & lanemask_lt())] =
+                ((uint32_t)cur << 18) | ((uint32_t)kind << 16) | ((uint32_t)W.lk[x] << 8) | (uint32_t)W.rk[y];
+          nh += __popcll(mh);
+          if (nh > kHitBuf - 64) {
+            process_hits<N, TILE>(W, T.blob, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+            nh = 0;
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
-    // the buffered hits refer to this work item's LDS data: finish them now
-    if (nh) process_hits<N, TILE>(W, sh, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+    ++cur;
   }
+  // hits still buffered refer to LDS data of this wavefront's last work items
+  if (nh) process_hits<N, TILE>(W, T.blob, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
   for (int off = 32; off > 0; off >>= 1) {
     nvt += __shfl_xor(nvt, off, 64);
     nee += __shfl_xor(nee, off, 64);

@@ -30,19 +30,20 @@ struct TileCaps<64> {
   static constexpr int ref = 64, ownv = 64, owne = 128;
 };
 // Per-patch blob: everything the primitive kernel needs about one patch in
-// one contiguous, fixed-stride block of ints, so a work item stages both
-// patches with one round of coalesced loads.  Layout (ints): header (number
-// of referenced vertices, owned vertices, triangles, owned edges), the
-// referenced vertices' local ids, owned vertex ids, triangle ids, owned edge
-// ids, then byte arrays packed four to an int: slot (index into the
-// referenced list) of every owned vertex, of the three corners of every
-// triangle and of the two ends of every owned edge.
+// one contiguous, fixed-stride block of ints.  Layout (ints): header (number
+// of referenced vertices, owned vertices, triangles, owned edges); byte
+// arrays packed four to an int: slot (index into the referenced list) of
+// every owned vertex, of the three corners of every triangle and of the two
+// ends of every owned edge; then the referenced vertices' local ids and the
+// owned vertex, triangle and owned edge ids.  The header and slots (the
+// first `lds` ints) are what a work item keeps in LDS; the ids are read from
+// global memory where needed.
 template <int TILE>
 struct BlobLayout {
   static constexpr int ref = TileCaps<TILE>::ref, ownv = TileCaps<TILE>::ownv, owne = TileCaps<TILE>::owne;
-  static constexpr int hdr = 0, pref = 4, pvtx = pref + ref, ptri = pvtx + ownv, pedge = ptri + TILE,
-                       vslot = pedge + owne, tslot = vslot + ownv / 4, eslot = tslot + 3 * TILE / 4,
-                       used = eslot + 2 * owne / 4, stride = (used + 63) / 64 * 64;
+  static constexpr int hdr = 0, vslot = 4, tslot = vslot + ownv / 4, eslot = tslot + 3 * TILE / 4,
+                       lds = (eslot + 2 * owne / 4 + 3) / 4 * 4, pref = lds, pvtx = pref + ref, ptri = pvtx + ownv,
+                       pedge = ptri + TILE, used = pedge + owne, stride = (used + 63) / 64 * 64;
   static_assert(ownv % 4 == 0 && (3 * TILE) % 4 == 0 && (2 * owne) % 4 == 0, "byte arrays fill whole ints");
 };
 
