@@ -15,7 +15,7 @@ using namespace mlp;
 constexpr int kWaves = 4, kThreads = 64 * kWaves;
 
 struct WaveBuf {
-  unsigned short x[16][kInP];  // [sample][k]
+  alignas(16) unsigned short x[16][kXS];  // [sample][k]
   Act a;
   float o[16][kOut];
 };
@@ -81,11 +81,12 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float *params, cons
                                                        int64_t n, float *part) {
   __shared__ Weights W;
   __shared__ WaveBuf buf[kWaves];
-  __shared__ unsigned short dO[kWaves][16][kOutP];  // output gradient (bf16), columns 0..1
-  __shared__ unsigned short d2[kWaves][16][kH];     // gradient at the layer-2 pre-activation
-  __shared__ unsigned short d1[kWaves][16][kH];     // gradient at the layer-1 pre-activation
-  __shared__ unsigned short w2t[kH][kH];            // W2^T
-  __shared__ unsigned short w3t[kOutP][kH];         // W3^T (rows >= 2 zero)
+  __shared__ alignas(16) unsigned short dO[kWaves][16][kOS];  // output gradient (bf16), columns 0..1
+  __shared__ alignas(16) unsigned short d2[kWaves][16][kHS];  // gradient at the layer-2 pre-activation
+  __shared__ alignas(16) unsigned short d1[kWaves][16][kHS];  // gradient at the layer-1 pre-activation
+  // W2 and W3 untransposed ([in][out]): the B^T operands of the backward products
+  __shared__ alignas(16) unsigned short w2o[kH][kHS];
+  __shared__ alignas(16) unsigned short w3o[kH][kOS];
   __shared__ float gsum[kNParam + 1];
   __shared__ float bsum[kWaves][2 * kH + kOut];     // per-wave bias gradients
   stage_weights(W, params);
@@ -94,8 +95,8 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float *params, cons
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, g = lane >> 4;
   WaveBuf &B = buf[wave];
-  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) w2t[i % kH][i / kH] = W.w2[i / kH][i % kH];
-  for (int i = threadIdx.x; i < kOutP * kH; i += blockDim.x) w3t[i / kH][i % kH] = W.w3[i % kH][i / kH];
+  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) w2o[i / kH][i % kH] = W.w2t[i % kH][i / kH];
+  for (int i = threadIdx.x; i < kH * kOutP; i += blockDim.x) w3o[i / kOutP][i % kOutP] = W.w3t[i % kOutP][i / kOutP];
   for (int i = lane; i < 2 * kH + kOut; i += 64) bsum[wave][i] = 0.0f;
   __syncthreads();
   // per-lane accumulators of the dW tiles: dW2 (4 x 4 tiles), dW1 (2 x 4), dW3 (4 x 1)
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float *params, cons
     __syncthreads();
     // d2 = (dO W3^T) * relu'(h2)
     for (int nt = 0; nt < kH / 16; ++nt) {
-      const f32x4 acc = tile_gemm(&dO[wave][0][0], kOutP, &w3t[0][0], kH, 16 * nt, kOutP);
+      const f32x4 acc = tile_gemm(&dO[wave][0][0], kOS, &w3o[0][0], kOS, 16 * nt, kOutP);
       for (int j = 0; j < 4; ++j) {
         const int r = 4 * g + j, c = 16 * nt + col;
         d2[wave][r][c] = B.a.h2[r][c] ? f2bf(acc[j]) : 0;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float *params, cons
     __syncthreads();
     // d1 = (d2 W2^T) * relu'(h1)
     for (int nt = 0; nt < kH / 16; ++nt) {
-      const f32x4 acc = tile_gemm(&d2[wave][0][0], kH, &w2t[0][0], kH, 16 * nt, kH);
+      const f32x4 acc = tile_gemm(&d2[wave][0][0], kHS, &w2o[0][0], kHS, 16 * nt, kH);
       for (int j = 0; j < 4; ++j) {
         const int r = 4 * g + j, c = 16 * nt + col;
         d1[wave][r][c] = B.a.h1[r][c] ? f2bf(acc[j]) : 0;
@@ -213,6 +214,16 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float *params, cons
   for (int i = threadIdx.x; i < kNParam + 1; i += blockDim.x) part[(int64_t)blockIdx.x * (kNParam + 1) + i] = gsum[i];
 }
 
+// The LDS image of the weights (bf16, transposed, padded), made once per model.
+__global__ void k_mlp_pack(const float *params, Weights *out) {
+  __shared__ Weights W;
+  stage_weights(W, params);
+  __syncthreads();
+  const int4 *src = reinterpret_cast<const int4 *>(&W);
+  int4 *dst = reinterpret_cast<int4 *>(out);
+  for (int i = threadIdx.x; i < (int)(sizeof(Weights) / 16); i += blockDim.x) dst[i] = src[i];
+}
+
 __global__ void k_mlp_reduce(const float *part, int nblocks, float *grad, float *loss, int64_t n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNParam + 1; i += gridDim.x * blockDim.x) {
     float s = 0.0f;
@@ -235,6 +246,12 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t ste
 }  // namespace
 
 int mlp_nparam() { return kNParam; }
+
+size_t mlp_packed_bytes() { return sizeof(Weights); }
+
+void launch_mlp_pack(const float *params, void *packed, hipStream_t st) {
+  k_mlp_pack<<<1, 256, 0, st>>>(params, reinterpret_cast<Weights *>(packed));
+}
 
 void launch_mlp_forward(const float *params, const float *x, int64_t n, float *out, hipStream_t st) {
   int64_t tiles = (n + 15) / 16;

@@ -93,7 +93,7 @@ __device__ inline void bracket_features(const Quad &Q, float out[mlp::kIn]) {
 
 struct BracketLds {
   mlp::Weights W;
-  unsigned short x[256][mlp::kInP];
+  alignas(16) unsigned short x[256][mlp::kXS];
   mlp::Act act[4];
   float br[256][2];
 };
@@ -105,7 +105,7 @@ template <int N, bool LEARNED>
 __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *geo, int64_t hard_cap, double d,
                                                 double eps,
                                                 double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                                                int64_t ct_cap, const float *mlp_params, float kwidth,
+                                                int64_t ct_cap, const void *mlp_packed, float kwidth,
                                                 Counters *cnt) {
   int64_t nc = (int64_t)cnt->n_hard;
   nc = nc < hard_cap ? nc : hard_cap;
@@ -115,7 +115,8 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
   BracketLds &L = *reinterpret_cast<BracketLds *>(dyn_lds);
   if (LEARNED) {
     if ((int64_t)blockIdx.x * blockDim.x >= nc) return;  // whole workgroup idle: uniform exit
-    mlp::stage_weights(L.W, mlp_params);
+    mlp::load_packed(L.W, reinterpret_cast<const mlp::Weights *>(mlp_packed));
+    __syncthreads();  // the only workgroup barrier: after it each wavefront uses its own LDS rows
   }
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {
     const int64_t i = base + threadIdx.x;
@@ -139,18 +140,24 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
 #pragma unroll
           for (int k = 0; k < mlp::kIn; ++k) ft[k] = 0.0f;
         }
+        // the row as eight 8-byte stores (columns kIn .. kInP - 1 are zero)
 #pragma unroll
-        for (int k = 0; k < mlp::kInP; ++k) L.x[threadIdx.x][k] = k < mlp::kIn ? mlp::f2bf(ft[k]) : 0;
+        for (int q = 0; q < mlp::kInP / 4; ++q) {
+          mlp::bf16x4 v;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (short)(4 * q + j < mlp::kIn ? mlp::f2bf(ft[4 * q + j]) : 0);
+          *reinterpret_cast<mlp::bf16x4 *>(&L.x[threadIdx.x][4 * q]) = v;
+        }
       }
-      __syncthreads();
+      mlp::wave_lds_sync();
       const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
       for (int q = 0; q < 4; ++q) {
         const int row0 = 64 * wave + 16 * q;
-        const mlp::f32x4 o = mlp::forward16(L.W, &L.x[row0][0], L.act[wave]);
+        const mlp::f32x4 o = mlp::forward16<true>(L.W, &L.x[row0][0], L.act[wave]);
         const int col = lane & 15, gq = lane >> 4;
         if (col < 2)
           for (int j = 0; j < 4; ++j) L.br[row0 + 4 * gq + j][col] = o[j];
-        __syncthreads();
+        mlp::wave_lds_sync();
       }
       if (i < nc) {
         load_geo(geo, hard_cap, i, c.kind == 2, Q);
@@ -159,10 +166,10 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
         lo = lo < 0.0 ? 0.0 : lo;
         hi = hi > 1.0 ? 1.0 : hi;
         int certified = 0;
-        hit = earliest_bracket<N>(Q, d, lo, hi, &s, &within, &deg, &certified);
+        hit = earliest_bracket<N>(Q, d, lo, hi, (double)mu, &s, &within, &deg, &certified);
         cert += certified;
       }
-      __syncthreads();
+      mlp::wave_lds_sync();
     } else if (i < nc) {
       load_geo(geo, hard_cap, i, c.kind == 2, Q);
       hit = earliest<N>(Q, d, &s, &within, &deg);
@@ -205,18 +212,18 @@ static int grid_for(int64_t n, int max_blocks) {
 
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard,
                    const double *hard_geo, int64_t hard_cap, double d, double eps, double dt, Cand *ct, double *ct_s,
-                   double *ct_vol, double *ct_grad, int64_t ct_cap, const float *mlp_params, float kwidth,
+                   double *ct_vol, double *ct_grad, int64_t ct_cap, const void *mlp_packed, float kwidth,
                    Counters *cnt, hipStream_t st) {
   (void)S; (void)T; (void)pairs;
   const int g = grid_for(hard_cap, blocks);
   const size_t lds = sizeof(BracketLds);
-  if (mlp_params) {
+  if (mlp_packed) {
     if (d == 0.0)
       k_narrow<3, true><<<g, 256, lds, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
-                                            mlp_params, kwidth, cnt);
+                                            mlp_packed, kwidth, cnt);
     else
       k_narrow<6, true><<<g, 256, lds, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
-                                            mlp_params, kwidth, cnt);
+                                            mlp_packed, kwidth, cnt);
   } else {
     if (d == 0.0)
       k_narrow<3, false><<<g, 256, 0, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,

@@ -25,6 +25,9 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = 18, kInP = 32, kH = 64, kOut = 2, kOutP = 16;
+// LDS row strides of the bf16 tiles, padded by 8 elements (16 bytes) so that
+// the 16 rows an operand fragment reads start in different bank groups
+constexpr int kXS = kInP + 8, kHS = kH + 8, kOS = kOutP + 8;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kIn * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
               kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH * kOut, kNParam = kOffB3 + kOut;
 constexpr float kSdFloor = 1e-3f;
@@ -37,28 +40,33 @@ __device__ inline unsigned short f2bf(float f) {  // round to nearest even
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-struct Weights {
-  unsigned short w1[kInP][kH];  // [k][n]
-  unsigned short w2[kH][kH];
-  unsigned short w3[kH][kOutP];
+// Weights in LDS, bf16, transposed ([n][k]) so that the B operand of a tile
+// (four consecutive k of one column n) is one 8-byte read, like the A operand.
+struct alignas(16) Weights {
+  alignas(16) unsigned short w1t[kH][kXS];    // W1^T, k padded 18 -> 32 with zeros
+  alignas(16) unsigned short w2t[kH][kHS];    // W2^T
+  alignas(16) unsigned short w3t[kOutP][kHS]; // W3^T, n padded 2 -> 16 with zeros
   float b1[kH], b2[kH], b3[kOutP];
 };
 
 // Per-wave activations of one 16-sample tile.
 struct Act {
-  unsigned short h1[16][kH];
-  unsigned short h2[16][kH];
+  alignas(16) unsigned short h1[16][kHS];
+  alignas(16) unsigned short h2[16][kHS];
 };
 
 __device__ inline void stage_weights(Weights &W, const float *p) {
-  for (int i = threadIdx.x; i < kInP * kH; i += blockDim.x) {
-    const int k = i / kH, n = i % kH;
-    W.w1[k][n] = k < kIn ? f2bf(p[kOffW1 + k * kH + n]) : 0;
+  for (int i = threadIdx.x; i < kH * kXS; i += blockDim.x) {
+    const int n = i / kXS, k = i % kXS;
+    W.w1t[n][k] = k < kIn ? f2bf(p[kOffW1 + k * kH + n]) : 0;
   }
-  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) W.w2[i / kH][i % kH] = f2bf(p[kOffW2 + i]);
-  for (int i = threadIdx.x; i < kH * kOutP; i += blockDim.x) {
-    const int k = i / kOutP, n = i % kOutP;
-    W.w3[k][n] = n < kOut ? f2bf(p[kOffW3 + k * kOut + n]) : 0;
+  for (int i = threadIdx.x; i < kH * kHS; i += blockDim.x) {
+    const int n = i / kHS, k = i % kHS;
+    W.w2t[n][k] = k < kH ? f2bf(p[kOffW2 + k * kH + n]) : 0;
+  }
+  for (int i = threadIdx.x; i < kOutP * kHS; i += blockDim.x) {
+    const int n = i / kHS, k = i % kHS;
+    W.w3t[n][k] = (n < kOut && k < kH) ? f2bf(p[kOffW3 + k * kOut + n]) : 0;
   }
   for (int i = threadIdx.x; i < kH; i += blockDim.x) {
     W.b1[i] = p[kOffB1 + i];
@@ -67,47 +75,64 @@ __device__ inline void stage_weights(Weights &W, const float *p) {
   for (int i = threadIdx.x; i < kOutP; i += blockDim.x) W.b3[i] = i < kOut ? p[kOffB3 + i] : 0.0f;
 }
 
-// One 16x16 output tile D = A (16 x K) * B (K x 16); A and B row-major bf16
-// in LDS with leading dimensions lda, ldb; columns [n0, n0+16) of B.
-__device__ inline f32x4 tile_gemm(const unsigned short *A, int lda, const unsigned short *B, int ldb, int n0, int K) {
+// Copy of a packed Weights image (made once by k_mlp_pack) into LDS with
+// coalesced 16-byte loads.
+__device__ inline void load_packed(Weights &W, const Weights *g) {
+  static_assert(sizeof(Weights) % 16 == 0, "whole 16-byte words");
+  const int4 *src = reinterpret_cast<const int4 *>(g);
+  int4 *dst = reinterpret_cast<int4 *>(&W);
+  for (int i = threadIdx.x; i < (int)(sizeof(Weights) / 16); i += blockDim.x) dst[i] = src[i];
+}
+
+// One 16x16 output tile D = A (16 x K) * B (K x 16) with A row-major [16][lda]
+// and B given transposed, Bt row-major [n][ldb] (rows n0 .. n0 + 15), both
+// bf16 in LDS; K a multiple of 16, lda and ldb multiples of 4.
+__device__ inline f32x4 tile_gemm(const unsigned short *A, int lda, const unsigned short *Bt, int ldb, int n0, int K) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a, b;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      a[j] = (short)A[r * lda + k0 + 4 * g + j];
-      b[j] = (short)B[(k0 + 4 * g + j) * ldb + n0 + r];
-    }
+    const bf16x4 a = *reinterpret_cast<const bf16x4 *>(A + r * lda + k0 + 4 * g);
+    const bf16x4 b = *reinterpret_cast<const bf16x4 *>(Bt + (n0 + r) * ldb + k0 + 4 * g);
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
   return acc;
 }
 
-// Forward of the 16 samples in x (bf16, row stride kInP, columns >= kIn zero).
-// Fills A.h1, A.h2 (post-ReLU) and returns the two raw outputs of row
-// 4 (lane / 16) + j in out[j][0..1] for the lanes with lane % 16 < 2 (column
-// lane % 16).  Contains workgroup barriers: every wave of the workgroup must
-// call it the same number of times.
+// Makes this wavefront's LDS writes visible to its own later reads (no
+// workgroup barrier): for tiles that only one wavefront touches.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Forward of the 16 samples in x (bf16, row stride kXS, columns kIn .. kInP - 1 zero).
+// Fills A.h1, A.h2 (post-ReLU) and returns the raw outputs of rows
+// 4 (lane / 16) + j, column lane % 16 (columns 0 and 1 are the outputs).
+// kWaveOnly: x and A belong to this wavefront alone, so wavefront-level
+// ordering suffices; otherwise every wavefront of the workgroup must call it
+// the same number of times (workgroup barriers).
+template <bool kWaveOnly = false>
 __device__ inline f32x4 forward16(const Weights &W, const unsigned short *x, Act &A) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int nt = 0; nt < kH / 16; ++nt) {
-    const f32x4 acc = tile_gemm(x, kInP, &W.w1[0][0], kH, 16 * nt, kInP);
+    const f32x4 acc = tile_gemm(x, kXS, &W.w1t[0][0], kXS, 16 * nt, kInP);
 #pragma unroll
     for (int j = 0; j < 4; ++j) A.h1[4 * g + j][16 * nt + col] = f2bf(fmaxf(acc[j] + W.b1[16 * nt + col], 0.0f));
   }
-  __syncthreads();
+  if (kWaveOnly) wave_lds_sync();
+  else __syncthreads();
 #pragma unroll
   for (int nt = 0; nt < kH / 16; ++nt) {
-    const f32x4 acc = tile_gemm(&A.h1[0][0], kH, &W.w2[0][0], kH, 16 * nt, kH);
+    const f32x4 acc = tile_gemm(&A.h1[0][0], kHS, &W.w2t[0][0], kHS, 16 * nt, kH);
 #pragma unroll
     for (int j = 0; j < 4; ++j) A.h2[4 * g + j][16 * nt + col] = f2bf(fmaxf(acc[j] + W.b2[16 * nt + col], 0.0f));
   }
-  __syncthreads();
-  f32x4 acc = tile_gemm(&A.h2[0][0], kH, &W.w3[0][0], kOutP, 0, kH);
+  if (kWaveOnly) wave_lds_sync();
+  else __syncthreads();
+  f32x4 acc = tile_gemm(&A.h2[0][0], kHS, &W.w3t[0][0], kHS, 0, kH);
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] += W.b3[col];
   return acc;

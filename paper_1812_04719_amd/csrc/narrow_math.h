@@ -146,22 +146,29 @@ __host__ __device__ void bernstein_on(const double f[N + 1], double u, double wd
     for (int j = N; j >= r; --j) b[j] += b[j - 1];
 }
 
-// Root of f in [lo, hi] where f(lo) = flo != 0 and f changes sign, by the
-// Illinois variant of regula falsi: the secant point of the bracket, with the
-// value kept at an end that was not replaced twice in a row halved, which
-// restores superlinear convergence where plain regula falsi stalls.  Stops at
-// an exact zero or a bracket of width 2^-50.  Chosen over safeguarded Newton
-// for its short tail: the slowest of 64 lanes decides the cost on a wavefront.
+// Root of f in [lo, hi] where f(lo) = flo != 0 and f changes sign (one root
+// inside).  Newton steps from a start point (the given guess when it lies
+// inside, else the secant point of the bracket), the bracket kept around the
+// root; a step that would leave the bracket is replaced by the Illinois point
+// (regula falsi with the value at an end that was kept twice in a row
+// halved), which still converges superlinearly where Newton would not.
+// Stops at an exact zero, a bracket of width 2^-50 or a step below 2^-52 x.
+// Newton with this fallback has the shortest tail over a wavefront of the
+// variants measured (safeguarded Newton from the midpoint, plain Illinois).
 template <int N>
-__host__ __device__ double refine(const double f[N + 1], double lo, double hi, double flo) {
+__host__ __device__ double refine(const double f[N + 1], double lo, double hi, double flo, double guess = -1.0) {
   const double tol = 8.881784197001252e-16;
   double fhi = horner<N>(f, hi);
   int side = 0;
-  double x = 0.5 * (lo + hi);
+  double x = (guess > lo && guess < hi) ? guess : (lo * fhi - hi * flo) / (fhi - flo);
+  if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
   for (int it = 0; it < 100; ++it) {
-    x = (lo * fhi - hi * flo) / (fhi - flo);
-    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
-    const double fx = horner<N>(f, x);
+    double fx = f[N], dfx = 0.0;
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+      dfx = dfx * x + fx;
+      fx = fx * x + f[k];
+    }
     if (fx == 0.0) return x;
     if ((fx < 0.0) == (flo < 0.0)) {
       lo = x;
@@ -175,6 +182,14 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
       side = 1;
     }
     if (hi - lo <= tol) break;
+    double xn = (dfx != 0.0) ? x - fx / dfx : -1.0;
+    if (!(xn > lo && xn < hi)) xn = (lo * fhi - hi * flo) / (fhi - flo);
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    if (fabs(xn - x) <= 2.220446049250313e-16 * fmax(fabs(x), 1e-300)) {
+      x = xn;
+      break;
+    }
+    x = xn;
   }
   return x;
 }
@@ -183,7 +198,8 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
 // depth-first Bernstein subdivision of that interval into the pieces
 // lo + (hi - lo) [idx 2^-level, (idx + 1) 2^-level].  Returns 1 with *s_out on
 // contact.  *visits counts the intervals examined (shared budget across
-// calls); *deg counts degenerate skips.
+// calls); *deg counts degenerate skips.  guess (optional) is the start of
+// the refinement of a root isolated in an interval that contains it.
 //
 // The search alternates two phases: subdivide until the next interval that
 // isolates a root (or the end), then refine that root and test it.  On a
@@ -193,7 +209,7 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
 // roots computed are those of a plain depth-first traversal.
 template <int N>
 __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double lo, double hi, double *s_out,
-                                  int *visits, int *deg) {
+                                  int *visits, int *deg, double guess = -1.0) {
   const int kMaxLevel = 44;
   const int kMaxVisits = 4096;
   const double span = hi - lo;
@@ -253,7 +269,7 @@ __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double l
     }
     if (!iso) break;
     // phase 2: refine and test
-    if (root < 0.0) root = refine<N>(f, u, v, fu);
+    if (root < 0.0) root = refine<N>(f, u, v, fu, guess);
     const int in = inside_at(Q, root);
     if (in < 0) (*deg)++;
     if (in == 1) {
@@ -299,12 +315,13 @@ __host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *wi
 // [lo, hi] of [0,1]: when the Bernstein coefficients of F on [0, lo] all have
 // one strict sign, F has no root before lo, so the earliest valid root is
 // the first one found in [lo, hi], else in [hi, 1].  Without that
-// certificate the whole of [0,1] is searched.  The result is the root of
+// certificate the whole of [0,1] is searched.  The predicted root `guess`
+// starts the refinement of an isolated root when it lies in that interval.  The result is the root of
 // earliest() (up to the last bits of the final refinement, which starts
 // from a different enclosing interval).  *certified reports the path taken.
 template <int N>
-__host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, double hi, double *s_out, int *within,
-                                         int *deg, int *certified) {
+__host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, double hi, double guess, double *s_out,
+                                         int *within, int *deg, int *certified) {
   double f[N + 1];
   const int pre = prepare<N>(Q, d, f, s_out, within, deg);
   *certified = 0;
@@ -328,7 +345,7 @@ __host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, dou
   const int parts = (ok && hi < 1.0) ? 2 : 1;
   int visits = 0;
   for (int part = 0; part < parts; ++part) {
-    if (search_in<N>(Q, f, a0, a1, s_out, &visits, deg)) return 1;
+    if (search_in<N>(Q, f, a0, a1, s_out, &visits, deg, guess)) return 1;
     a0 = a1;
     a1 = 1.0;
   }

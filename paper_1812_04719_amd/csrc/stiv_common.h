@@ -181,7 +181,7 @@ void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T,
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard,
                    const double *hard_geo, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, const float *mlp_params, float kwidth, Counters *cnt, hipStream_t st);
+                   int64_t ct_cap, const void *mlp_packed, float kwidth, Counters *cnt, hipStream_t st);
 
 // LCP matrix assembly (Alg. 3)
 void launch_lcp_layout(const int *vtx_off, int n_ves, const int32_t *j_vtx, int64_t n_jrow, int32_t *flag,
@@ -203,6 +203,8 @@ void launch_lcp_reduce(const uint64_t *key, const uint32_t *idx, const double *c
 
 // Learned contact-time bracket (perceptron kernels)
 int mlp_nparam();
+size_t mlp_packed_bytes();
+void launch_mlp_pack(const float *params, void *packed, hipStream_t st);
 void launch_mlp_forward(const float *params, const float *x, int64_t n, float *out, hipStream_t st);
 int mlp_grad_blocks(int64_t n);
 void launch_mlp_grad(const float *params, const float *x, const float *target, int64_t n, float *part, float *grad,

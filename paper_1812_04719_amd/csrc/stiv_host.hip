@@ -70,7 +70,7 @@ struct stiv_ctx {
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
       row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
-  Buf toi_params, mlp_part;
+  Buf toi_params, toi_packed, mlp_part;
   // LCP matrix assembly scratch
   Buf lcp_flag, lcp_a, lcp_m9, lcp_vcnt, lcp_vcur, lcp_voff, lcp_vlist, lcp_c2, lcp_coff, lcp_ckey, lcp_cval,
       lcp_cidx, lcp_tk, lcp_tv, lcp_start, lcp_pos, lcp_ovf;
@@ -145,7 +145,7 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
                 &ctx->cand_list, &ctx->ct,
-                &ctx->toi_params, &ctx->mlp_part, &ctx->lcp_flag, &ctx->lcp_a, &ctx->lcp_m9, &ctx->lcp_vcnt,
+                &ctx->toi_params, &ctx->toi_packed, &ctx->mlp_part, &ctx->lcp_flag, &ctx->lcp_a, &ctx->lcp_m9, &ctx->lcp_vcnt,
                 &ctx->lcp_vcur, &ctx->lcp_voff, &ctx->lcp_vlist, &ctx->lcp_c2, &ctx->lcp_coff, &ctx->lcp_ckey,
                 &ctx->lcp_cval, &ctx->lcp_cidx, &ctx->lcp_tk, &ctx->lcp_tv, &ctx->lcp_start, &ctx->lcp_pos,
                 &ctx->lcp_ovf,
@@ -572,7 +572,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                 ctx->cap_cand, p->d, p->eps,
                 p->dt,
                 P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
-                (p->flags & STIV_LEARNED_BRACKET) ? P<float>(ctx->toi_params) : nullptr, ctx->toi_kwidth, cnt, st);
+                (p->flags & STIV_LEARNED_BRACKET) ? ctx->toi_packed.p : nullptr, ctx->toi_kwidth, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
   launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
@@ -948,6 +948,10 @@ stiv_status stiv_set_toi_model(stiv_ctx *ctx, const float *params, int n, float 
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(ensure(ctx->toi_params, sizeof(float) * (size_t)n));
   HIPCHK(hipMemcpy(ctx->toi_params.p, params, sizeof(float) * (size_t)n, hipMemcpyHostToDevice));
+  HIPCHK(ensure(ctx->toi_packed, mlp_packed_bytes()));
+  launch_mlp_pack(P<float>(ctx->toi_params), ctx->toi_packed.p, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipDeviceSynchronize());
   ctx->toi_kwidth = kwidth;
   ctx->have_model = true;
   return STIV_OK;

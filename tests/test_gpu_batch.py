@@ -81,3 +81,17 @@ def test_autotune(ctx, tmp_path):
     g, _ = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt)
     parity.compare(g, oracle.detect(sc), sc.dt, sc.eps)
     autotune.apply(ctx, dict(tile=64, prim_blocks=8192, narrow_blocks=8192))
+
+
+@pytest.mark.timeout(600)
+def test_batch_config_256_scenes(ctx):
+    """The full batching configuration: 256 independent scenes of 8-128
+    vesicles, orders 16/24/32, 10-60 % volume fraction, in one call; every
+    set exact against the oracle (candidate counts, contacts, volumes, J)."""
+    from paper_1812_04719_amd import stiv
+    b = S.make_config(4)
+    print("batch config: scenes=%d vesicles=%d vertices=%d" % (b.n_scenes, b.n_ves, b.n_vtx), flush=True)
+    g, _ = stiv.detect(ctx, stiv.DeviceScene(b), b.d, b.eps, b.dt)
+    o = oracle.detect(b)
+    assert b.n_scenes == 256
+    parity.compare(g, o, b.dt, b.eps)
