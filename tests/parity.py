@@ -19,6 +19,8 @@ def _rows(a):
 
 def same_rows(a, b):
     """Exact equality of two integer row sets (order-insensitive)."""
+    if len(a) == 0 or len(b) == 0:
+        return len(a) == len(b)
     a = np.asarray(a).reshape(len(a), -1)
     b = np.asarray(b).reshape(len(b), -1)
     if a.shape != b.shape:
