@@ -27,6 +27,9 @@ FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_VERTEX_BOXES = 48.0       # X0 and X1, 3 doubles each, read once by the box kernel
 BYTES_PER_BOX_OUT = 48.0            # 6 doubles per vesicle or patch box written
 FLOPS_PER_CANDIDATE = 152.0         # coefficients of F = g^2 - d^2 q (counted from the formulas)
+# per candidate in the primitive kernel: exact FP64 box test (66: min/max of 4 vertices at both
+# times, inflation and shift, 6 comparisons) + coefficients of F (152) + Bernstein screen (35)
+OPS_PER_CANDIDATE_SCREEN = 253.0
 FLOPS_PER_VT_CONTACT = 300.0        # volume and gradient of one vertex-triangle contact
 OPS_PER_BOX_TEST = 6.0              # 3 axes x 2 interval-end comparisons of two FP32 boxes
 LDS_BYTES_PER_BOX_TEST = 48.0       # two 6-float boxes read from LDS
@@ -142,7 +145,7 @@ def main():
     else:
         kern = {3: "k_prim_cand", 4: "k_narrow"}.get(dom, names[dom])
         if dom == 3:
-            ops = OPS_PER_BOX_TEST * work["box_tests"] + FLOPS_PER_CANDIDATE * n_cand
+            ops = OPS_PER_BOX_TEST * work["box_tests"] + OPS_PER_CANDIDATE_SCREEN * n_cand
         else:
             ops = FLOPS_PER_CANDIDATE * n_cand + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
         achieved = ops / (stages[dom] * 1e-3) / 1e12

@@ -370,7 +370,7 @@ void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_sce
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
                        const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
                        int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st) {
-  k_cell_pairs<<<grid1d(n_cp_cap, 256), 256, 0, st>>>(S, ves_box, ves_scene, keys, vals, n_cp, n_cp_cap, hash,
+  k_cell_pairs<<<grid1d(n_cp_cap, 64), 64, 0, st>>>(S, ves_box, ves_scene, keys, vals, n_cp, n_cp_cap, hash,
                                                        hash_cap, uniq, uniq_cap, cnt);
 }
 void launch_self_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, uint64_t *hash,

@@ -11,20 +11,31 @@ namespace {
 
 constexpr int kScanThreads = 1024;
 
-// Block-wide inclusive scan of one value per thread (1024 threads).
+// Block-wide inclusive scan of one value per thread (1024 threads): a
+// shuffle scan inside each wavefront, the 16 wavefront totals scanned by
+// the first wavefront, two workgroup barriers in all.  sh needs 16 entries.
 template <typename T>
 __device__ T block_inclusive_scan(T v, T *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    T add = (t >= off) ? sh[t - off] : T(0);
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  T r = sh[t];
+  if (lane == 63) sh[wave] = v;
   __syncthreads();
+  if (wave == 0) {
+    T w = lane < kScanThreads / 64 ? sh[lane] : T(0);
+#pragma unroll
+    for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+      const T u = __shfl_up(w, off, 64);
+      if (lane >= off) w += u;
+    }
+    if (lane < kScanThreads / 64) sh[lane] = w;
+  }
+  __syncthreads();
+  const T r = v + (wave ? sh[wave - 1] : T(0));
+  __syncthreads();  // sh may be reused by the caller's next scan
   return r;
 }
 
