@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--plain-only", action="store_true", help="skip the learned-bracket timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-scene batch measurement")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 256-scene batch measurement (for profiling it); prints its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -80,6 +82,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "copy_probe_bytes_written": y.numel() * 8,
                           "launches": 3}), flush=True)
+        return
+
+    if args.batch_only:
+        ctx = stiv.Context(0)
+        print(json.dumps(measure_batch(ctx, scenes, stiv, torch, np, args)), flush=True)
+        ctx.close()
         return
 
     t0 = time.time()

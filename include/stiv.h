@@ -78,7 +78,9 @@ typedef struct {
  * vertices [vtx_off[v], vtx_off[v+1]) and uses topology topo_id[v]; scene s
  * owns vesicles [scene_off[s], scene_off[s+1]); pairs never cross scenes.
  * box_len[s][c] > 0 makes axis c of scene s periodic with that period;
- * 0 means free space on that axis. */
+ * 0 means free space on that axis.  Image shifts are limited to |sigma_c| <=
+ * 7 (a vesicle box may span at most about 7 periods): beyond that stiv_detect
+ * returns STIV_E_ARG.  At most 2^24 - 1 vesicles per call. */
 typedef struct {
   int32_t n_ves, n_vtx, n_scenes;
   const int32_t *vtx_off;   /* [n_ves+1] */

@@ -62,71 +62,100 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const TIn *in, int64
   if (t == kScanThreads - 1) out[n] = inc;
 }
 
-// Single-workgroup LSD radix sort, 4-bit digits, stable.  Each thread owns a
-// contiguous chunk, so the scatter order within a digit follows input order.
-__global__ __launch_bounds__(kScanThreads) void k_radix_1wg(uint64_t *keys, uint32_t *vals, uint64_t *tk,
-                                                            uint32_t *tv, const unsigned long long *n_dev,
-                                                            int64_t n_host, int key_bits) {
-  __shared__ int32_t cnt[16 * kScanThreads];
-  __shared__ int64_t sh[kScanThreads];
-  int64_t n = n_host;
-  if (n_dev) n = (int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host;
-  const int t = threadIdx.x;
-  const int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
-  const int64_t lo = (int64_t)t * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  // only the bits below the largest key need passes
+// --------------------------------------------------------------------------
+// Multi-workgroup stable LSD radix sort, 8-bit digits.  A workgroup of 256
+// threads owns a tile of 2048 consecutive keys, laid out [wavefront][round]
+// [lane]: per pass, (1) a digit histogram per tile, written digit-major;
+// (2) an exclusive scan of it, which is the first output position of each
+// (digit, tile); (3) every key's rank among the equal digits before it in
+// its tile -- matched across the wavefront by ballots on the 8 digit bits,
+// carried across rounds and wavefronts in LDS -- gives its output position.
+// Equal keys keep their input order (stable), as Alg. 1 requires.
+// --------------------------------------------------------------------------
+constexpr int kRsThreads = 256, kRsItems = 8, kRsTile = kRsThreads * kRsItems, kRsWaves = kRsThreads / 64;
+static_assert(kRsThreads == 256, "one thread per digit in the histogram and offset steps");
+
+__device__ inline int64_t rs_count(const unsigned long long *n_dev, int64_t n_host) {
+  return n_dev ? ((int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host) : n_host;
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, const unsigned long long *n_dev,
+                                                        int64_t n_host, int shift, int32_t *hist, int nblk) {
+  __shared__ int h[256];
+  const int64_t n = rs_count(n_dev, n_host);
+  const int t = threadIdx.x, b = blockIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)b * kRsTile;
+  for (int k = t; k < kRsTile; k += kRsThreads) {
+    const int64_t e = e0 + k;
+    if (e < n) atomicAdd(&h[(int)((keys[e] >> shift) & 255u)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)t * nblk + b] = h[t];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *sk, const uint32_t *sv, uint64_t *dk,
+                                                           uint32_t *dv, const unsigned long long *n_dev,
+                                                           int64_t n_host, int shift, const int64_t *hoff, int nblk) {
+  __shared__ int wcnt[kRsWaves][256];
+  __shared__ int woff[kRsWaves][256];
+  const int64_t n = rs_count(n_dev, n_host);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, b = blockIdx.x;
+  for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&wcnt[0][0])[k] = 0;
+  __syncthreads();
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t base = (int64_t)b * kRsTile + (int64_t)w * (kRsItems * 64);
+  uint64_t key[kRsItems];
+  uint32_t val[kRsItems];
+  int dg[kRsItems], rank[kRsItems];
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    const int64_t e = base + j * 64 + lane;
+    const bool valid = e < n;
+    key[j] = valid ? sk[e] : 0ull;
+    val[j] = valid ? sv[e] : 0u;
+    const int d = valid ? (int)((key[j] >> shift) & 255u) : 0;
+    dg[j] = valid ? d : -1;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const unsigned long long m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    int pre = 0;
+    if (valid) pre = wcnt[w][d];
+    rank[j] = pre + __popcll(peers & lt);
+    // the last lane of each group of equal digits advances the wavefront's count
+    if (valid && (peers >> lane) == 1ull) wcnt[w][d] = pre + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
   {
-    __shared__ unsigned long long kmax;
-    if (t == 0) kmax = 0;
-    __syncthreads();
-    uint64_t m = 0;
-    for (int64_t i = lo; i < hi; ++i) m = keys[i] > m ? keys[i] : m;
-    if (m) atomicMax(&kmax, (unsigned long long)m);
-    __syncthreads();
-    const int used = kmax ? 64 - __clzll((long long)kmax) : 0;
-    key_bits = used < key_bits ? used : key_bits;
-    __syncthreads();
+    int run = 0;
+#pragma unroll
+    for (int ww = 0; ww < kRsWaves; ++ww) {
+      woff[ww][t] = run;
+      run += wcnt[ww][t];
+    }
   }
-  uint64_t *sk = keys, *dk = tk;
-  uint32_t *sv = vals, *dv = tv;
-  int passes = 0;
-  for (int shift = 0; shift < key_bits; shift += 4, ++passes) {
-    for (int dgt = 0; dgt < 16; ++dgt) cnt[dgt * kScanThreads + t] = 0;
-    for (int64_t i = lo; i < hi; ++i) cnt[(int)((sk[i] >> shift) & 15u) * kScanThreads + t]++;
-    __syncthreads();
-    // exclusive scan in flat (digit, thread) order; thread t covers 16 entries
-    int32_t loc[16];
-    int64_t s = 0;
-    for (int k = 0; k < 16; ++k) {
-      loc[k] = cnt[t * 16 + k];
-      s += loc[k];
-    }
-    int64_t inc = block_inclusive_scan<int64_t>(s, sh);
-    int64_t base = inc - s;
-    for (int k = 0; k < 16; ++k) {
-      int32_t v = loc[k];
-      cnt[t * 16 + k] = (int32_t)base;
-      base += v;
-    }
-    __syncthreads();
-    for (int64_t i = lo; i < hi; ++i) {
-      uint64_t k = sk[i];
-      int dgt = (int)((k >> shift) & 15u);
-      int32_t pos = cnt[dgt * kScanThreads + t]++;
-      dk[pos] = k;
-      dv[pos] = sv[i];
-    }
-    __threadfence_block();
-    __syncthreads();
-    uint64_t *xk = sk; sk = dk; dk = xk;
-    uint32_t *xv = sv; sv = dv; dv = xv;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    if (dg[j] < 0) continue;
+    const int64_t dst = hoff[(int64_t)dg[j] * nblk + b] + woff[w][dg[j]] + rank[j];
+    dk[dst] = key[j];
+    dv[dst] = val[j];
   }
-  if (passes & 1) {
-    for (int64_t i = t; i < n; i += kScanThreads) {
-      keys[i] = sk[i];
-      vals[i] = sv[i];
-    }
+}
+
+__global__ void k_rs_copy(const uint64_t *sk, const uint32_t *sv, uint64_t *dk, uint32_t *dv,
+                          const unsigned long long *n_dev, int64_t n_host) {
+  const int64_t n = rs_count(n_dev, n_host);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    dk[i] = sk[i];
+    dv[i] = sv[i];
   }
 }
 
@@ -161,9 +190,24 @@ void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long
                             hipStream_t st) {
   k_scan_excl<int32_t><<<1, kScanThreads, 0, st>>>(in, out, n_dev, n_host);
 }
+int64_t radix_scratch_blocks(int64_t n_host) { return (n_host + kRsTile - 1) / kRsTile; }
+
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
-                           const unsigned long long *n_dev, int64_t n_host, int key_bits, hipStream_t st) {
-  k_radix_1wg<<<1, kScanThreads, 0, st>>>(keys, vals, tk, tv, n_dev, n_host, key_bits);
+                           const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
+                           int64_t *hoff, hipStream_t st) {
+  if (n_host <= 0) return;
+  const int nblk = (int)radix_scratch_blocks(n_host);
+  uint64_t *sk = keys, *dk = tk;
+  uint32_t *sv = vals, *dv = tv;
+  int passes = 0;
+  for (int shift = 0; shift < key_bits; shift += 8, ++passes) {
+    k_rs_hist<<<nblk, kRsThreads, 0, st>>>(sk, n_dev, n_host, shift, hist, nblk);
+    k_scan_excl<int32_t><<<1, kScanThreads, 0, st>>>(hist, hoff, nullptr, (int64_t)256 * nblk);
+    k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hoff, nblk);
+    uint64_t *xk = sk; sk = dk; dk = xk;
+    uint32_t *xv = sv; sv = dv; dv = xv;
+  }
+  if (passes & 1) k_rs_copy<<<grid_for(n_host, 256), 256, 0, st>>>(sk, sv, keys, vals, n_dev, n_host);
 }
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u64<<<grid_for(n, 256), 256, 0, st>>>(p, v, n);

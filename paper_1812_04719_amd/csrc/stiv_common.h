@@ -136,8 +136,13 @@ void launch_scan_i64(const int64_t *in, int64_t *out, const unsigned long long *
                      hipStream_t st);
 void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
                             hipStream_t st);
+// Stable sort of n keys (device count n_dev clamped to n_host, or n_host)
+// by their low key_bits bits, values moved along; tk, tv: n_host scratch;
+// hist: 256 * radix_scratch_blocks(n_host) ints, hoff: one more int64.
+int64_t radix_scratch_blocks(int64_t n_host);
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
-                           const unsigned long long *n_dev, int64_t n_host, int key_bits, hipStream_t st);
+                           const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
+                           int64_t *hoff, hipStream_t st);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);

@@ -68,7 +68,7 @@ struct stiv_ctx {
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
-      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo;
+      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo, rs_hist, rs_off;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
   Buf toi_params, toi_packed, mlp_part;
   // LCP matrix assembly scratch
@@ -87,6 +87,14 @@ struct stiv_ctx {
 };
 
 namespace {
+
+// Histogram and offset scratch of the radix sort for up to n keys.
+hipError_t ensure_sort_scratch(stiv_ctx *ctx, int64_t n) {
+  const int64_t nb = radix_scratch_blocks(n > 0 ? n : 1);
+  hipError_t e = ensure(ctx->rs_hist, 4 * (size_t)(256 * nb));
+  if (e != hipSuccess) return e;
+  return ensure(ctx->rs_off, 8 * (size_t)(256 * nb + 1));
+}
 
 stiv_status fail(stiv_ctx *c, stiv_status s, const std::string &m) {
   if (c) c->err = m;
@@ -140,7 +148,7 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
                 &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->t_blob,
-                &ctx->hard_geo, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
@@ -415,6 +423,7 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->cp_keys, 8 * ctx->cap_cp));
   HIPCHK(ensure(ctx->cp_vals, 4 * ctx->cap_cp));
   HIPCHK(ensure(ctx->cp_tk, 8 * ctx->cap_cp));
+  HIPCHK(ensure_sort_scratch(ctx, ctx->cap_cp));
   HIPCHK(ensure(ctx->cp_tv, 4 * ctx->cap_cp));
   HIPCHK(ensure(ctx->hash, 8 * hash_cap));
   HIPCHK(ensure(ctx->uniq, 8 * ctx->cap_pairs));
@@ -541,7 +550,8 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   int scene_bits = 0;
   while ((1ll << scene_bits) < S.n_scenes) ++scene_bits;
   launch_radix_sort_u64(P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), P<uint64_t>(ctx->cp_tk),
-                        P<uint32_t>(ctx->cp_tv), n_cp, ctx->cap_cp, 30 + scene_bits, st);
+                        P<uint32_t>(ctx->cp_tv), n_cp, ctx->cap_cp, 30 + scene_bits, P<int32_t>(ctx->rs_hist),
+                        P<int64_t>(ctx->rs_off), st);
   launch_fill_u64(P<uint64_t>(ctx->hash), ~0ull, hash_cap, st);
   launch_cell_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->cp_keys),
                     P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap,
@@ -820,7 +830,9 @@ stiv_status stiv_sort_pairs_u64(stiv_ctx *ctx, uint64_t *keys, uint32_t *vals, i
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(ensure(ctx->sort_tk, 8 * (size_t)(n + 1)));
   HIPCHK(ensure(ctx->sort_tv, 4 * (size_t)(n + 1)));
-  launch_radix_sort_u64(keys, vals, P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), nullptr, n, 64, st);
+  HIPCHK(ensure_sort_scratch(ctx, n));
+  launch_radix_sort_u64(keys, vals, P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), nullptr, n, 64,
+                        P<int32_t>(ctx->rs_hist), P<int64_t>(ctx->rs_off), st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return STIV_OK;
@@ -915,8 +927,10 @@ stiv_status stiv_form_lcp(stiv_ctx *ctx, const stiv_scene *s, const stiv_result 
                    res->j_vol, res->j_vtx, res->j_g, res->n_jrow, P<int64_t>(ctx->lcp_coff),
                    P<uint64_t>(ctx->lcp_ckey), P<double>(ctx->lcp_cval), P<unsigned long long>(ctx->lcp_ovf), st);
   launch_iota_u32(P<uint32_t>(ctx->lcp_cidx), nc, st);
+  HIPCHK(ensure_sort_scratch(ctx, nc));
   launch_radix_sort_u64(P<uint64_t>(ctx->lcp_ckey), P<uint32_t>(ctx->lcp_cidx), P<uint64_t>(ctx->lcp_tk),
-                        P<uint32_t>(ctx->lcp_tv), nullptr, nc, 64, st);
+                        P<uint32_t>(ctx->lcp_tv), nullptr, nc, 64, P<int32_t>(ctx->rs_hist), P<int64_t>(ctx->rs_off),
+                        st);
   launch_lcp_runs(P<uint64_t>(ctx->lcp_ckey), nc, P<int32_t>(ctx->lcp_start), st);
   launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_start), P<int64_t>(ctx->lcp_pos), nullptr, nc, st);
   launch_lcp_reduce(P<uint64_t>(ctx->lcp_ckey), P<uint32_t>(ctx->lcp_cidx), P<double>(ctx->lcp_cval), nc,
