@@ -159,6 +159,53 @@ __global__ void k_rs_copy(const uint64_t *sk, const uint32_t *sv, uint64_t *dk, 
   }
 }
 
+// --------------------------------------------------------------------------
+// Multi-workgroup exclusive scan (reduce, scan the workgroup sums, scan each
+// chunk with its offset) for long inputs; the single-workgroup kernel above
+// serves short ones.
+// --------------------------------------------------------------------------
+constexpr int kScanItems = 8, kScanChunk = kScanThreads * kScanItems;
+
+template <typename TIn>
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const TIn *in, const unsigned long long *n_dev,
+                                                            int64_t n_host, int64_t *sums) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  const int64_t n = n_dev ? ((int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host) : n_host;
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+  int64_t s = 0;
+  for (int k = threadIdx.x; k < kScanChunk; k += kScanThreads) {
+    const int64_t i = c0 + k;
+    if (i < n) s += (int64_t)in[i];
+  }
+  const int64_t inc = block_inclusive_scan<int64_t>(s, sh);
+  if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = inc;
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const TIn *in, int64_t *out,
+                                                              const unsigned long long *n_dev, int64_t n_host,
+                                                              const int64_t *soff, int nblk) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  const int64_t n = n_dev ? ((int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host) : n_host;
+  // each thread owns kScanItems consecutive elements of the chunk
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (i0 + j < n) ? (int64_t)in[i0 + j] : 0;
+    s += v[j];
+  }
+  const int64_t inc = block_inclusive_scan<int64_t>(s, sh);
+  int64_t base = soff[blockIdx.x] + inc - s;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (i0 + j < n) out[i0 + j] = base;
+    base += v[j];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = soff[nblk];
+}
+
 __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -182,15 +229,35 @@ int grid_for(int64_t n, int threads) {
 
 }  // namespace
 
-void launch_scan_i64(const int64_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
+int64_t scan_scratch_elems(int64_t n_host) { return 2 * ((n_host + kScanChunk - 1) / kScanChunk) + 2; }
+
+template <typename TIn>
+static void scan_any(const TIn *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host, int64_t *tmp,
                      hipStream_t st) {
-  k_scan_excl<int64_t><<<1, kScanThreads, 0, st>>>(in, out, n_dev, n_host);
+  if (!tmp || n_host <= 2 * kScanChunk) {
+    k_scan_excl<TIn><<<1, kScanThreads, 0, st>>>(in, out, n_dev, n_host);
+    return;
+  }
+  const int nblk = (int)((n_host + kScanChunk - 1) / kScanChunk);
+  int64_t *sums = tmp, *soff = tmp + nblk + 1;
+  k_scan_sums<TIn><<<nblk, kScanThreads, 0, st>>>(in, n_dev, n_host, sums);
+  k_scan_excl<int64_t><<<1, kScanThreads, 0, st>>>(sums, soff, nullptr, nblk);
+  k_scan_chunks<TIn><<<nblk, kScanThreads, 0, st>>>(in, out, n_dev, n_host, soff, nblk);
+}
+
+void launch_scan_i64(const int64_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
+                     int64_t *tmp, hipStream_t st) {
+  scan_any<int64_t>(in, out, n_dev, n_host, tmp, st);
 }
 void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
-                            hipStream_t st) {
-  k_scan_excl<int32_t><<<1, kScanThreads, 0, st>>>(in, out, n_dev, n_host);
+                            int64_t *tmp, hipStream_t st) {
+  scan_any<int32_t>(in, out, n_dev, n_host, tmp, st);
 }
 int64_t radix_scratch_blocks(int64_t n_host) { return (n_host + kRsTile - 1) / kRsTile; }
+int64_t radix_offset_elems(int64_t n_host) {
+  const int64_t h = 256 * radix_scratch_blocks(n_host);
+  return h + 1 + scan_scratch_elems(h);
+}
 
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
@@ -202,7 +269,7 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
   int passes = 0;
   for (int shift = 0; shift < key_bits; shift += 8, ++passes) {
     k_rs_hist<<<nblk, kRsThreads, 0, st>>>(sk, n_dev, n_host, shift, hist, nblk);
-    k_scan_excl<int32_t><<<1, kScanThreads, 0, st>>>(hist, hoff, nullptr, (int64_t)256 * nblk);
+    scan_any<int32_t>(hist, hoff, nullptr, (int64_t)256 * nblk, hoff + (int64_t)256 * nblk + 1, st);
     k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hoff, nblk);
     uint64_t *xk = sk; sk = dk; dk = xk;
     uint32_t *xv = sv; sv = dv; dv = xv;

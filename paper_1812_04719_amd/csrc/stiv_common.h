@@ -132,14 +132,19 @@ struct Cand {
 // capacity, so the host never waits for an intermediate count.
 // ---------------------------------------------------------------------------
 // scan / sort / fill.  With n_dev != nullptr the length is min(*n_dev, n_host).
+// Exclusive scans: out[0 .. n] with out[n] the total; n = min(*n_dev, n_host)
+// when a device count is given.  tmp: scan_scratch_elems(n_host) int64
+// (NULL: one workgroup, for short inputs).
+int64_t scan_scratch_elems(int64_t n_host);
 void launch_scan_i64(const int64_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
-                     hipStream_t st);
+                     int64_t *tmp, hipStream_t st);
 void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host,
-                            hipStream_t st);
+                            int64_t *tmp, hipStream_t st);
 // Stable sort of n keys (device count n_dev clamped to n_host, or n_host)
 // by their low key_bits bits, values moved along; tk, tv: n_host scratch;
-// hist: 256 * radix_scratch_blocks(n_host) ints, hoff: one more int64.
+// hist: 256 * radix_scratch_blocks(n_host) ints, hoff: radix_offset_elems(n_host) int64.
 int64_t radix_scratch_blocks(int64_t n_host);
+int64_t radix_offset_elems(int64_t n_host);
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
                            int64_t *hoff, hipStream_t st);

@@ -68,7 +68,8 @@ struct stiv_ctx {
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
-      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo, rs_hist, rs_off;
+      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo, rs_hist, rs_off,
+      scan_tmp;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
   Buf toi_params, toi_packed, mlp_part;
   // LCP matrix assembly scratch
@@ -93,7 +94,7 @@ hipError_t ensure_sort_scratch(stiv_ctx *ctx, int64_t n) {
   const int64_t nb = radix_scratch_blocks(n > 0 ? n : 1);
   hipError_t e = ensure(ctx->rs_hist, 4 * (size_t)(256 * nb));
   if (e != hipSuccess) return e;
-  return ensure(ctx->rs_off, 8 * (size_t)(256 * nb + 1));
+  return ensure(ctx->rs_off, 8 * (size_t)radix_offset_elems(n > 0 ? n : 1));
 }
 
 stiv_status fail(stiv_ctx *c, stiv_status s, const std::string &m) {
@@ -148,7 +149,7 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
                 &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->t_blob,
-                &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->scan_tmp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
@@ -424,6 +425,7 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->cp_vals, 4 * ctx->cap_cp));
   HIPCHK(ensure(ctx->cp_tk, 8 * ctx->cap_cp));
   HIPCHK(ensure_sort_scratch(ctx, ctx->cap_cp));
+  HIPCHK(ensure(ctx->scan_tmp, 8 * (size_t)scan_scratch_elems(std::max<int64_t>(N, ctx->cap_pairs))));
   HIPCHK(ensure(ctx->cp_tv, 4 * ctx->cap_cp));
   HIPCHK(ensure(ctx->hash, 8 * hash_cap));
   HIPCHK(ensure(ctx->uniq, 8 * ctx->cap_pairs));
@@ -533,7 +535,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   if (timed) (void)hipEventRecord(ctx->ev[8], st);
   launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 0ull, sizeof(Counters) / 8, st);
   launch_ves_patch_count(S, T, P<int64_t>(ctx->ves_patch_cnt), st);
-  launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, st);
+  launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   // ---- K0 boxes
   if (timed) (void)hipEventRecord(ctx->ev[0], st);
   launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box), cnt, st);
@@ -543,7 +545,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), st);
   launch_cp_count(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
                   P<int64_t>(ctx->cp_cnt), st);
-  launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, st);
+  launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_cp_emit(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
                  P<int64_t>(ctx->cp_off), P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), ctx->cap_cp, st);
   const unsigned long long *n_cp = reinterpret_cast<const unsigned long long *>(P<int64_t>(ctx->cp_off) + N);
@@ -561,7 +563,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_fill_i32(P<int32_t>(ctx->cnt_a), 0, N + 1, st);
   launch_fill_i32(P<int32_t>(ctx->cursor_a), 0, N + 1, st);
   launch_pair_bucket_count(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a), cnt, st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->cnt_a), P<int64_t>(ctx->off_a), nullptr, N, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->cnt_a), P<int64_t>(ctx->off_a), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_pair_bucket_scatter(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int64_t>(ctx->off_a),
                              P<int32_t>(ctx->cursor_a), P<uint64_t>(ctx->sorted), cnt, st);
   launch_pair_bucket_sort_emit(S, P<int>(ctx->ves_scene), P<int64_t>(ctx->off_a), P<uint64_t>(ctx->sorted), (int)N,
@@ -589,7 +591,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_fill_i32(P<int32_t>(ctx->pair_cursor), 0, ctx->cap_pairs + 1, st);
   launch_ct_pair_count(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int32_t>(ctx->pair_cnt), st);
   const unsigned long long *n_pairs_dev = &cnt->n_pairs;
-  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_cnt), P<int64_t>(ctx->pair_off), n_pairs_dev, ctx->cap_pairs, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_cnt), P<int64_t>(ctx->pair_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
   launch_ct_scatter(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int64_t>(ctx->pair_off), P<int32_t>(ctx->pair_cursor),
                     P<int32_t>(ctx->perm), st);
   launch_ct_sort_aggregate(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, cnt, P<int64_t>(ctx->pair_off),
@@ -598,8 +600,8 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                            out->ct_key, out->ct_tau, out->ct_vol, out->ct_grad, out->cap_ct, P<double>(ctx->pair_V),
                            P<int32_t>(ctx->pair_hasvt), P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx),
                            P<double>(ctx->row_g), st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_hasvt), P<int64_t>(ctx->vol_off), n_pairs_dev, ctx->cap_pairs, st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_rows), P<int64_t>(ctx->row_off), n_pairs_dev, ctx->cap_pairs, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_hasvt), P<int64_t>(ctx->vol_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_rows), P<int64_t>(ctx->row_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
   launch_write_volumes(cnt, ctx->cap_pairs, P<int64_t>(ctx->pair_off), P<int64_t>(ctx->vol_off),
                        P<int64_t>(ctx->row_off), P<int32_t>(ctx->pair_hasvt), P<double>(ctx->pair_V),
                        P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx), P<double>(ctx->row_g), out->vol_pair,
@@ -868,8 +870,8 @@ stiv_status stiv_lcp_layout(stiv_ctx *ctx, const stiv_scene *s, const stiv_resul
   launch_fill_i32(P<int32_t>(ctx->lcp_flag), 0, s->n_vtx + 1, st);
   launch_lcp_layout(s->vtx_off, nv, res->j_vtx, res->n_jrow, P<int32_t>(ctx->lcp_flag), P<int32_t>(ctx->lcp_a),
                     P<int64_t>(ctx->lcp_m9), st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_a), act_off, nullptr, nv, st);
-  launch_scan_i64(P<int64_t>(ctx->lcp_m9), m_off, nullptr, nv, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_a), act_off, nullptr, nv, nullptr, st);
+  launch_scan_i64(P<int64_t>(ctx->lcp_m9), m_off, nullptr, nv, nullptr, st);
   HIPCHK(hipGetLastError());
   int64_t tot[2];
   HIPCHK(hipMemcpyAsync(&tot[0], act_off + nv, 8, hipMemcpyDeviceToHost, st));
@@ -907,10 +909,10 @@ stiv_status stiv_form_lcp(stiv_ctx *ctx, const stiv_scene *s, const stiv_result 
   launch_fill_i32(P<int32_t>(ctx->lcp_vcur), 0, nv + 1, st);
   launch_fill_u64(P<uint64_t>(ctx->lcp_ovf), 0ull, 1, st);
   launch_lcp_vcount(res->vol_pair, res->pair_ab, n_vol, P<int32_t>(ctx->lcp_vcnt), st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_vcnt), P<int64_t>(ctx->lcp_voff), nullptr, nv, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_vcnt), P<int64_t>(ctx->lcp_voff), nullptr, nv, nullptr, st);
   launch_lcp_vscatter(res->vol_pair, res->pair_ab, n_vol, P<int64_t>(ctx->lcp_voff), P<int32_t>(ctx->lcp_vcur),
                       P<int32_t>(ctx->lcp_vlist), nv, P<int64_t>(ctx->lcp_c2), st);
-  launch_scan_i64(P<int64_t>(ctx->lcp_c2), P<int64_t>(ctx->lcp_coff), nullptr, nv, st);
+  launch_scan_i64(P<int64_t>(ctx->lcp_c2), P<int64_t>(ctx->lcp_coff), nullptr, nv, nullptr, st);
   HIPCHK(hipGetLastError());
   int64_t nc = 0;
   HIPCHK(hipMemcpyAsync(&nc, P<int64_t>(ctx->lcp_coff) + nv, 8, hipMemcpyDeviceToHost, st));
@@ -932,7 +934,7 @@ stiv_status stiv_form_lcp(stiv_ctx *ctx, const stiv_scene *s, const stiv_result 
                         P<uint32_t>(ctx->lcp_tv), nullptr, nc, 64, P<int32_t>(ctx->rs_hist), P<int64_t>(ctx->rs_off),
                         st);
   launch_lcp_runs(P<uint64_t>(ctx->lcp_ckey), nc, P<int32_t>(ctx->lcp_start), st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_start), P<int64_t>(ctx->lcp_pos), nullptr, nc, st);
+  launch_scan_i32_to_i64(P<int32_t>(ctx->lcp_start), P<int64_t>(ctx->lcp_pos), nullptr, nc, nullptr, st);
   launch_lcp_reduce(P<uint64_t>(ctx->lcp_ckey), P<uint32_t>(ctx->lcp_cidx), P<double>(ctx->lcp_cval), nc,
                     P<int32_t>(ctx->lcp_start), P<int64_t>(ctx->lcp_pos), b_row, b_col, b_val, cap_b, st);
   HIPCHK(hipGetLastError());
