@@ -23,7 +23,7 @@ METRIC = "candidate pairs/s & contacts/s, 1440 vesicles 58% vf; learned-TOI vs p
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# Algorithmic work per unit (derivations in the design doc):
+# Algorithmic work per unit, counted from the formulas of the method:
 BYTES_PER_VERTEX_BOXES = 48.0       # X0 and X1, 3 doubles each, read once by the box kernel
 BYTES_PER_BOX_OUT = 48.0            # 6 doubles per vesicle or patch box written
 FLOPS_PER_CANDIDATE = 152.0         # coefficients of F = g^2 - d^2 q (counted from the formulas)

@@ -134,14 +134,16 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 
 // --------------------------------------------------------------------------
 // Per work item: one wavefront, both patches staged in LDS.
-// 1. Both patch blobs (ids and slots, see BlobLayout) arrive with one round
-//    of coalesced loads; then X0 and X1 of every referenced vertex.  A work
-//    item thus waits for three dependent rounds of global loads: the work
-//    record, the blobs, the positions.
-// 2. Per kind, build the left list (owned vertices, or owned edges) and the
-//    right list (triangles, or owned edges) of primitives whose boxes meet
-//    the other patch's box; boxes are FP32 rounded outward from the FP64
-//    boxes, so the filter keeps a superset.
+// 1. The header and slot bytes of both patch blobs (BlobLayout) and the
+//    referenced vertex ids arrive with one round of loads; then X0 and X1 of
+//    every referenced vertex, kept in LDS in FP64, with each vertex's
+//    space-time box rounded outward to FP32.  A work item thus waits for
+//    three dependent rounds of global loads: the work record, the blobs, the
+//    positions.
+// 2. Per kind, build the left list (owned vertices, or owned edges; 64 at a
+//    time) and the right list (triangles, or owned edges) of primitives whose
+//    FP32 boxes meet the other patch's box; the FP32 boxes enclose the FP64
+//    ones, so the filter keeps a superset.
 // 3. All left x right pairs of the lists, 64 per round, FP32 box test; hits
 //    are buffered in LDS.
 // 4. Buffered hits are processed 64 at a time with all lanes busy: the exact
