@@ -134,12 +134,15 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 
 // --------------------------------------------------------------------------
 // Per work item: one wavefront, both patches staged in LDS.
-// 1. The header and slot bytes of both patch blobs (BlobLayout) and the
-//    referenced vertex ids arrive with one round of loads; then X0 and X1 of
+// 1. Staging.  The header and slot bytes of both patch blobs (BlobLayout),
+//    the referenced vertex ids and the pair's image shift; then X0 and X1 of
 //    every referenced vertex, kept in LDS in FP64, with each vertex's
-//    space-time box rounded outward to FP32.  A work item thus waits for
-//    three dependent rounds of global loads: the work record, the blobs, the
-//    positions.
+//    space-time box rounded outward to FP32.  These are three dependent
+//    rounds of global loads (work record; blobs; positions), so they are
+//    software-pipelined across the work items of a wavefront: the record of
+//    the item after next, the blobs of the next item and then its positions
+//    are loaded into registers while the current item is swept, and only
+//    written to LDS once the current item is finished.
 // 2. Per kind, build the left list (owned vertices, or owned edges; 64 at a
 //    time) and the right list (triangles, or owned edges) of primitives whose
 //    FP32 boxes meet the other patch's box; the FP32 boxes enclose the FP64
@@ -149,20 +152,11 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 // 4. Buffered hits are processed 64 at a time with all lanes busy: the exact
 //    FP64 box test (the candidate definition), then the screens: candidates
 //    whose polynomial can have a root on [0,1] and whose closest-point test
-//    can pass somewhere on [0,1] are queued for the
-//    root-search kernel together with their FP64 geometry (structure of
-//    arrays), so the root search reads them coalesced; the rest are
-//    finished here.
+//    can pass somewhere on [0,1] are queued for the root-search kernel
+//    together with their FP64 geometry (structure of arrays), so the root
+//    search reads them coalesced; the rest are finished here.
 // --------------------------------------------------------------------------
 constexpr int kHitBuf = 256;
-
-// Up to kSlots work items can keep their FP64 positions and slot tables in
-// LDS until their hits are processed, so that one round of the exact test
-// and screens serves the hits of several work items (a work item has about
-// 20 hits on average).  Measured at 1440 vesicles, 2 or 3 slots cost more
-// (lower occupancy from the larger LDS footprint) than the fuller rounds
-// save, so one slot is used.
-constexpr int kSlots = 1;
 
 template <int TILE>
 struct WaveLds {
@@ -170,16 +164,15 @@ struct WaveLds {
   static constexpr int kRef = TileCaps<TILE>::ref;
   static constexpr int kL = 64;  // the left-hand list is built 64 primitives at a time
   static constexpr int kR = TileCaps<TILE>::owne > TILE ? TileCaps<TILE>::owne : TILE;
-  double pos[kSlots][2][kRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
-  double sh[kSlots][3];            // image shift of each slot's pair
-  int P[kSlots][2], pair[kSlots];  // patch-table indices and pair of each slot
-  float vbox[2][kRef][6];          // FP32 space-time box of each referenced vertex (current work item)
-  float lbox[kL][6];               // left-hand list (current chunk) of the current kind: FP32 boxes
-  float rbox[kR][6];               // right-hand list
-  uint8_t lk[kL];                  // patch-local indices of the left-hand list
-  uint8_t rk[kR];                  // and of the right-hand list
-  uint32_t hits[kHitBuf];          // slot << 18 | kind << 16 | left << 8 | right (patch-local indices)
-  alignas(16) int blob[kSlots][2][Lay::lds];  // header and slot arrays of the two patch blobs
+  double pos[2][kRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
+  double sh[3];            // image shift of the pair
+  float vbox[2][kRef][6];  // FP32 space-time box of each referenced vertex
+  float lbox[kL][6];       // left-hand list (current chunk) of the current kind: FP32 boxes
+  float rbox[kR][6];       // right-hand list
+  uint8_t lk[kL];          // patch-local indices of the left-hand list
+  uint8_t rk[kR];          // and of the right-hand list
+  uint32_t hits[kHitBuf];  // kind << 16 | left << 8 | right (patch-local indices)
+  alignas(16) int blob[2][Lay::lds];  // header and slot arrays of the two patch blobs
 };
 
 __device__ inline bool ov6f(const float *A, const float *B) {
@@ -212,16 +205,17 @@ __device__ inline float wave_maxf(float v) {
 }
 
 template <int TILE>
-__device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int slot, int side, int off) {
-  return reinterpret_cast<const uint8_t *>(&W.blob[slot][side][off]);
+__device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, int off) {
+  return reinterpret_cast<const uint8_t *>(&W.blob[side][off]);
 }
 
 // Exact FP64 box test of a buffered hit and the polynomial screen; queue the
-// candidates that need a root search.  All 64 lanes take part.
+// candidates that need a root search.  All 64 lanes take part.  P[2] are the
+// patch-table indices of the current work item and p its pair.
 template <int N, int TILE>
-__device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand *hard, double *geo,
-                             int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, unsigned long long &nvt,
-                             unsigned long long &nee, int nh) {
+__device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2], int p, double d, Cand *hard,
+                             double *geo, int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt,
+                             unsigned long long &nvt, unsigned long long &nee, int nh) {
   using Lay = BlobLayout<TILE>;
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
@@ -229,25 +223,23 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand 
   for (int r0 = 0; r0 < nh; r0 += 64) {
     const int k = r0 + lane;
     bool is_cand = false, need = false;
-    Cand c;
-    c.pair = 0; c.kind = 0; c.i = 0; c.j = 0;
-    int slots[4] = {0, 0, 0, 0}, sl = 0, sr = 1, ws = 0;
+    int kind = 0, kl = 0, kr = 0, sl = 0, sr = 1;
+    int slots[4] = {0, 0, 0, 0};
     if (k < nh) {
       nm::Quad Q;
       const uint32_t hv = W.hits[k];
-      ws = (int)(hv >> 18);
-      const int kind = (int)((hv >> 16) & 3u), kl = (int)((hv >> 8) & 0xffu), kr = (int)(hv & 0xffu);
-      const double *sh = W.sh[ws];
-      c.pair = W.pair[ws];
+      kind = (int)((hv >> 16) & 3u);
+      kl = (int)((hv >> 8) & 0xffu);
+      kr = (int)(hv & 0xffu);
       sl = (kind == 1) ? 1 : 0;
       sr = 1 - sl;
       const bool ee = kind == 2;
       if (ee) {
-        const uint8_t *el = blob_bytes(W, ws, sl, Lay::eslot), *er = blob_bytes(W, ws, sr, Lay::eslot);
+        const uint8_t *el = blob_bytes(W, sl, Lay::eslot), *er = blob_bytes(W, sr, Lay::eslot);
         slots[0] = el[2 * kl]; slots[1] = el[2 * kl + 1];
         slots[2] = er[2 * kr]; slots[3] = er[2 * kr + 1];
       } else {
-        const uint8_t *vl = blob_bytes(W, ws, sl, Lay::vslot), *tr = blob_bytes(W, ws, sr, Lay::tslot);
+        const uint8_t *vl = blob_bytes(W, sl, Lay::vslot), *tr = blob_bytes(W, sr, Lay::tslot);
         slots[0] = vl[kl];
         slots[1] = tr[3 * kr]; slots[2] = tr[3 * kr + 1]; slots[3] = tr[3 * kr + 2];
       }
@@ -263,8 +255,8 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand 
       for (int v = 0; v < 4; ++v) {
         const bool second = v >= nfirst;
         const int side = second ? sr : sl;
-        const double *pp = W.pos[ws][side][slots[v]];
-        const double shx = side ? sh[0] : 0.0, shy = side ? sh[1] : 0.0, shz = side ? sh[2] : 0.0;
+        const double *pp = W.pos[side][slots[v]];
+        const double shx = side ? W.sh[0] : 0.0, shy = side ? W.sh[1] : 0.0, shz = side ? W.sh[2] : 0.0;
         Q.X0[v] = nm::mk(pp[0] + shx, pp[1] + shy, pp[2] + shz);
         Q.D[v] = nm::mk(pp[3] - pp[0], pp[4] - pp[1], pp[5] - pp[2]);
 #pragma unroll
@@ -277,7 +269,7 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand 
       bool ov = true;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const double s0 = sl ? sh[q] : 0.0, s1 = sr ? sh[q] : 0.0;
+        const double s0 = sl ? W.sh[q] : 0.0, s1 = sr ? W.sh[q] : 0.0;
         const double l0 = (lo[0][q] - h) + s0, u0 = (hi[0][q] + h) + s0;
         const double l1 = (lo[1][q] - h) + s1, u1 = (hi[1][q] + h) + s1;
         ov = ov && l0 <= u1 && l1 <= u0;
@@ -285,11 +277,17 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand 
       if (ov) {
         is_cand = true;
         if (ee) ++nee; else ++nvt;
-        c.kind = kind;
-        c.i = gblob[(int64_t)W.P[ws][sl] * Lay::stride + (ee ? Lay::pedge : Lay::pvtx) + kl];
-        c.j = gblob[(int64_t)W.P[ws][sr] * Lay::stride + (ee ? Lay::pedge : Lay::ptri) + kr];
         need = nm::needs_root_search<N>(Q, d) && nm::may_be_inside(Q);
       }
+    }
+    // global primitive ids, only where a record is written; the loads are
+    // issued before the queue's atomic so that both latencies overlap
+    Cand c;
+    c.pair = p; c.kind = kind; c.i = 0; c.j = 0;
+    if (need || (list && is_cand)) {
+      const bool ee = kind == 2;
+      c.i = gblob[(int64_t)P[sl] * Lay::stride + (ee ? Lay::pedge : Lay::pvtx) + kl];
+      c.j = gblob[(int64_t)P[sr] * Lay::stride + (ee ? Lay::pedge : Lay::ptri) + kr];
     }
     const unsigned long long mh = __ballot(need);
     if (mh) {
@@ -307,10 +305,10 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand 
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int side = v >= nfirst ? sr : sl;
-            const double *pp = W.pos[ws][side][slots[v]];
+            const double *pp = W.pos[side][slots[v]];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-              geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? W.sh[ws][q] : 0.0);
+              geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? W.sh[q] : 0.0);
               geo[(12 + 3 * v + q) * hard_cap + slot] = pp[3 + q] - pp[q];
             }
           }
@@ -331,8 +329,60 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, double d, Cand 
       }
     }
   }
-  if (lane == 0 && nh) atomicAdd(&cnt->n_pre, (unsigned long long)nh);
   __syncthreads();
+}
+
+// Registers of a work item in flight: its record (lanes 0-7 hold the eight
+// ints of WorkRec), the pair's image shift (lanes 0-2), the header and slot
+// ints of both blobs (one int4 per lane), the referenced vertex ids and, once
+// those have arrived, the positions of the referenced vertices.
+template <int TILE>
+struct Prefetch {
+  using Lay = BlobLayout<TILE>;
+  static_assert(Lay::lds / 4 <= 64 && Lay::ref <= 64, "one int4 of each blob and one vertex per lane");
+  int4 blob[2];
+  int ref[2];
+  double sh;
+  double pos[2][6];
+};
+
+__device__ inline int load_workrec(const WorkRec *work, int64_t w, int64_t nw, int lane) {
+  return (w < nw && lane < 8) ? reinterpret_cast<const int *>(work + w)[lane] : 0;
+}
+
+// Blobs, referenced ids and shift of a work item whose record is in wr.
+template <int TILE>
+__device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const PairRec *pairs, int wr, int lane) {
+  using Lay = BlobLayout<TILE>;
+  const int p = __builtin_amdgcn_readlane(wr, 0);
+  const int P[2] = {__builtin_amdgcn_readlane(wr, 1), __builtin_amdgcn_readlane(wr, 2)};
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int *gb = T.blob + (int64_t)P[side] * Lay::stride;
+    F.blob[side] = lane < Lay::lds / 4 ? reinterpret_cast<const int4 *>(gb)[lane] : int4{0, 0, 0, 0};
+    // unused entries of the referenced list are 0: a valid vertex of the vesicle
+    F.ref[side] = lane < Lay::ref ? gb[Lay::pref + lane] : 0;
+  }
+  F.sh = lane < 3 ? pairs[p].sh[lane] : 0.0;
+}
+
+// Positions of the referenced vertices (every lane below the list capacity
+// loads one vertex; lanes past the patch's count load vertex 0 of the vesicle).
+template <int TILE>
+__device__ inline void load_positions(Prefetch<TILE> &F, const DevScene &S, int wr, int lane) {
+  using Lay = BlobLayout<TILE>;
+  const int base[2] = {__builtin_amdgcn_readlane(wr, 3), __builtin_amdgcn_readlane(wr, 4)};
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    if (lane < Lay::ref) {
+      const int64_t g = base[side] + F.ref[side];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        F.pos[side][c] = S.x0[c * (int64_t)S.n_vtx + g];
+        F.pos[side][3 + c] = S.x1[c * (int64_t)S.n_vtx + g];
+      }
+    }
+  }
 }
 
 template <int N, int TILE>
@@ -345,57 +395,44 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   const double h = 0.5 * d;
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
-  unsigned long long nvt = 0, nee = 0, ntests = 0;
-  static_assert(kSlots <= 3, "slot id takes two bits of a hit record");
-  int nh = 0;   // buffered hits (wave-uniform)
-  int cur = 0;  // LDS slot of the current work item
-  for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
-    if (cur == kSlots) {  // all slots hold work items with pending hits: process them
-      if (nh) process_hits<N, TILE>(W, T.blob, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
-      nh = 0;
-      cur = 0;
-    }
-    const WorkRec wr = work[w];
-    const int P[2] = {wr.pa, wr.pb};
-    const int base[2] = {wr.base_a, wr.base_b};
-    double sh[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sh[c] = pairs[wr.p].sh[c];
-    // header and slots of both blobs (16-byte loads), and the referenced
-    // vertex ids of both patches: one round of independent loads
-    int ref[2] = {-1, -1};
+  unsigned long long nvt = 0, nee = 0, ntests = 0, npre = 0;
+  const int64_t G = gridDim.x;
+  int64_t w = blockIdx.x;
+  // pipeline prologue: the first item completely, the record of the second
+  Prefetch<TILE> F;
+  int wr_cur = load_workrec(work, w, nw, lane);
+  int wr_next = load_workrec(work, w + G, nw, lane);
+  if (w < nw) {
+    load_blobs<TILE>(F, T, pairs, wr_cur, lane);
+    load_positions<TILE>(F, S, wr_cur, lane);
+  }
+  for (; w < nw; w += G) {
+    // the current item: registers -> LDS
+    const int p = __builtin_amdgcn_readlane(wr_cur, 0);
+    const int P[2] = {__builtin_amdgcn_readlane(wr_cur, 1), __builtin_amdgcn_readlane(wr_cur, 2)};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int *gb = T.blob + (int64_t)P[side] * Lay::stride;
-      const int4 *src = reinterpret_cast<const int4 *>(gb);
-      int4 *dst = reinterpret_cast<int4 *>(&W.blob[cur][side][0]);
+      if (lane < Lay::lds / 4) reinterpret_cast<int4 *>(&W.blob[side][0])[lane] = F.blob[side];
+      if (lane < Lay::ref)
 #pragma unroll
-      for (int i = lane; i < Lay::lds / 4; i += 64) dst[i] = src[i];
-      if (lane < Lay::ref) ref[side] = gb[Lay::pref + lane];
+        for (int c = 0; c < 6; ++c) W.pos[side][lane][c] = F.pos[side][c];
     }
-    if (lane < 3) W.sh[cur][lane] = sh[lane];
-    if (lane < 2) W.P[cur][lane] = P[lane];
-    if (lane == 0) W.pair[cur] = wr.p;
+    if (lane < 3) W.sh[lane] = F.sh;
     __syncthreads();
     float pb[2][6];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int nref = W.blob[cur][side][Lay::hdr + 0];
+      const int nref = W.blob[side][Lay::hdr + 0];
       float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-      static_assert(Lay::ref <= 64, "one referenced vertex per lane");
       if (lane < nref) {
-        const int r = lane;
-        const int64_t g = base[side] + ref[side];
-        const double sc[3] = {side ? sh[0] : 0.0, side ? sh[1] : 0.0, side ? sh[2] : 0.0};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double a = S.x0[c * (int64_t)S.n_vtx + g], b = S.x1[c * (int64_t)S.n_vtx + g];
-          W.pos[cur][side][r][c] = a;
-          W.pos[cur][side][r][3 + c] = b;
-          lo[c] = __double2float_rd((fmin(a, b) - h) + sc[c]);
-          hi[c] = __double2float_ru((fmax(a, b) + h) + sc[c]);
-          W.vbox[side][r][c] = lo[c];
-          W.vbox[side][r][3 + c] = hi[c];
+          const double a = F.pos[side][c], b = F.pos[side][3 + c];
+          const double sc = side ? W.sh[c] : 0.0;
+          lo[c] = __double2float_rd((fmin(a, b) - h) + sc);
+          hi[c] = __double2float_ru((fmax(a, b) + h) + sc);
+          W.vbox[side][lane][c] = lo[c];
+          W.vbox[side][lane][3 + c] = hi[c];
         }
       }
 #pragma unroll
@@ -404,13 +441,20 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
         pb[side][3 + c] = wave_maxf(hi[c]);
       }
     }
+    // the next item's blobs and the record of the one after it (the loads
+    // complete while this item is swept)
+    const bool more = w + G < nw;
+    if (more) load_blobs<TILE>(F, T, pairs, wr_next, lane);
+    const int wr_after = load_workrec(work, w + 2 * G, nw, lane);
     __syncthreads();
+    int nh = 0;  // buffered hits (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
+      if (kind == 1 && more) load_positions<TILE>(F, S, wr_next, lane);
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
-      const int lcount = kind == 2 ? W.blob[cur][sl][Lay::hdr + 3] : W.blob[cur][sl][Lay::hdr + 1];
-      const int rcount = kind == 2 ? W.blob[cur][sr][Lay::hdr + 3] : W.blob[cur][sr][Lay::hdr + 2];
-      const uint8_t *lslot = blob_bytes(W, cur, sl, kind == 2 ? Lay::eslot : Lay::vslot);
-      const uint8_t *rslot = blob_bytes(W, cur, sr, kind == 2 ? Lay::eslot : Lay::tslot);
+      const int lcount = kind == 2 ? W.blob[sl][Lay::hdr + 3] : W.blob[sl][Lay::hdr + 1];
+      const int rcount = kind == 2 ? W.blob[sr][Lay::hdr + 3] : W.blob[sr][Lay::hdr + 2];
+      const uint8_t *lslot = blob_bytes(W, sl, kind == 2 ? Lay::eslot : Lay::vslot);
+      const uint8_t *rslot = blob_bytes(W, sr, kind == 2 ? Lay::eslot : Lay::tslot);
       const int lnv = kind == 2 ? 2 : 1;
       const int rnv = kind == 2 ? 2 : 3;
       // compact the primitives whose box meets the other patch's box (ballot +
@@ -467,20 +511,25 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           const unsigned long long mh = __ballot(hit);
           if (hit)
             W.hits[nh + __popcll(mh & lanemask_lt())] =
-                ((uint32_t)cur << 18) | ((uint32_t)kind << 16) | ((uint32_t)W.lk[x] << 8) | (uint32_t)W.rk[y];
+                ((uint32_t)kind << 16) | ((uint32_t)W.lk[x] << 8) | (uint32_t)W.rk[y];
           nh += __popcll(mh);
           if (nh > kHitBuf - 64) {
-            process_hits<N, TILE>(W, T.blob, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+            process_hits<N, TILE>(W, T.blob, P, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+            npre += (unsigned long long)nh;
             nh = 0;
           }
         }
         __syncthreads();
       }
     }
-    ++cur;
+    // the hits refer to this item's LDS data: finish them before the next item
+    if (nh) {
+      process_hits<N, TILE>(W, T.blob, P, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+      npre += (unsigned long long)nh;
+    }
+    wr_cur = wr_next;
+    wr_next = wr_after;
   }
-  // hits still buffered refer to LDS data of this wavefront's last work items
-  if (nh) process_hits<N, TILE>(W, T.blob, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
   for (int off = 32; off > 0; off >>= 1) {
     nvt += __shfl_xor(nvt, off, 64);
     nee += __shfl_xor(nee, off, 64);
@@ -489,6 +538,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     if (nvt) atomicAdd(&cnt->n_cand_vt, nvt);
     if (nee) atomicAdd(&cnt->n_cand_ee, nee);
     if (ntests) atomicAdd(&cnt->n_tests, ntests);
+    if (npre) atomicAdd(&cnt->n_pre, npre);
   }
 }
 
