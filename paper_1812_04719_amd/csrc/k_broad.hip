@@ -51,8 +51,10 @@ __device__ inline uint64_t mix64(uint64_t k) {
   return k;
 }
 
-__device__ void hash_insert(uint64_t key, uint64_t *hash, int64_t cap, uint64_t *uniq, int64_t uniq_cap,
-                            Counters *cnt) {
+// Insert a key into the open-addressing set (linear probing).  The set is
+// listed afterwards by k_hash_list, so an insertion touches only its own
+// slots (no shared counter).
+__device__ void hash_insert(uint64_t key, uint64_t *hash, int64_t cap, Counters *cnt) {
   uint64_t h = mix64(key) & (uint64_t)(cap - 1);
   for (int64_t probe = 0; probe < cap; ++probe) {
     // most insertions repeat a pair already present: look before the atomic
@@ -65,12 +67,7 @@ __device__ void hash_insert(uint64_t key, uint64_t *hash, int64_t cap, uint64_t 
     }
     uint64_t prev = atomicCAS((unsigned long long *)&hash[h], (unsigned long long)kEmpty,
                               (unsigned long long)key);
-    if (prev == kEmpty) {
-      unsigned long long idx = atomicAdd(&cnt->n_pairs, 1ull);
-      if ((int64_t)idx < uniq_cap) uniq[idx] = key;
-      return;
-    }
-    if (prev == key) return;
+    if (prev == kEmpty || prev == key) return;
     h = (h + 1) & (uint64_t)(cap - 1);
   }
   atomicAdd(&cnt->hash_overflow, 1ull);
@@ -86,8 +83,7 @@ __device__ inline bool box_overlap_shifted(const double *A, const double *B, con
 
 // Insert every image shift of (a, b) whose shifted boxes overlap.
 __device__ void test_pair_all_shifts(int a, int b, const double *A, const double *B, const double *L,
-                                     uint64_t *hash, int64_t cap, uint64_t *uniq, int64_t uniq_cap,
-                                     Counters *cnt) {
+                                     uint64_t *hash, int64_t cap, Counters *cnt) {
   // candidate shifts per axis: (A.lo - B.hi)/L <= sigma <= (A.hi - B.lo)/L, widened
   // by 1e-6 against rounding; each one is then tested exactly
   int lo[3], hi[3];
@@ -115,7 +111,7 @@ __device__ void test_pair_all_shifts(int a, int b, const double *A, const double
         }
         double sh[3];
         for (int c = 0; c < 3; ++c) sh[c] = (double)s[c] * L[c];
-        if (box_overlap_shifted(A, B, sh)) hash_insert(pack_pair(a, b, s), hash, cap, uniq, uniq_cap, cnt);
+        if (box_overlap_shifted(A, B, sh)) hash_insert(pack_pair(a, b, s), hash, cap, cnt);
       }
 }
 
@@ -257,34 +253,92 @@ __global__ void k_cp_emit(DevScene S, const double *box, const int *ves_scene, c
   }
 }
 
-__global__ void k_cell_pairs(DevScene S, const double *box, const int *ves_scene, const uint64_t *keys,
-                             const uint32_t *vals, const unsigned long long *n_cp, int64_t cap_cp, uint64_t *hash,
-                             int64_t cap,
-                             uint64_t *uniq, int64_t uniq_cap, Counters *cnt) {
+// One wavefront per check point i that starts its box's stretch in a cell
+// (a box's check points in one cell are consecutive in the stable order, so
+// each box is taken once per cell); lane l takes the l-th following check
+// point of the same cell, 64 at a time, and tests the box pair if that point
+// starts its own box's stretch.
+__global__ __launch_bounds__(256) void k_cell_pairs(DevScene S, const double *box, const int *ves_scene,
+                                                    const uint64_t *keys, const uint32_t *vals,
+                                                    const unsigned long long *n_cp, int64_t cap_cp, uint64_t *hash,
+                                                    int64_t cap, Counters *cnt) {
   int64_t n = (int64_t)*n_cp;
   n = n < cap_cp ? n : cap_cp;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n; i += nwaves) {
     const uint64_t k = keys[i];
     const int vi = (int)vals[i];
-    // a box's check points are consecutive in the stable order: test each box once per cell
     if (i > 0 && keys[i - 1] == k && (int)vals[i - 1] == vi) continue;
-    for (int64_t j = i + 1; j < n && keys[j] == k; ++j) {
-      const int vj = (int)vals[j];
-      if (vi == vj || (int)vals[j - 1] == vj) continue;
-      const int a = vi < vj ? vi : vj, b = vi < vj ? vj : vi;
-      const double *L = S.box_len + 3 * ves_scene[a];
-      test_pair_all_shifts(a, b, box + 6 * (int64_t)a, box + 6 * (int64_t)b, L, hash, cap, uniq, uniq_cap, cnt);
+    for (int64_t j0 = i + 1; j0 < n; j0 += 64) {
+      const int64_t j = j0 + lane;
+      // equal keys are contiguous: the lanes still in the cell are a prefix
+      const bool in = j < n && keys[j] == k;
+      if (in) {
+        const int vj = (int)vals[j];
+        if (vi != vj && (int)vals[j - 1] != vj) {
+          const int a = vi < vj ? vi : vj, b = vi < vj ? vj : vi;
+          const double *L = S.box_len + 3 * ves_scene[a];
+          test_pair_all_shifts(a, b, box + 6 * (int64_t)a, box + 6 * (int64_t)b, L, hash, cap, cnt);
+        }
+      }
+      if (!(__ballot(in) >> 63)) break;
     }
   }
 }
 
 __global__ void k_self_pairs(DevScene S, const double *box, const int *ves_scene, uint64_t *hash, int64_t cap,
-                             uint64_t *uniq, int64_t uniq_cap, Counters *cnt) {
+                             Counters *cnt) {
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
     const double *L = S.box_len + 3 * ves_scene[v];
     if (!(L[0] > 0.0 || L[1] > 0.0 || L[2] > 0.0)) continue;
     const double *A = box + 6 * (int64_t)v;
-    test_pair_all_shifts(v, v, A, A, L, hash, cap, uniq, uniq_cap, cnt);
+    test_pair_all_shifts(v, v, A, A, L, hash, cap, cnt);
+  }
+}
+
+// List the keys of the set: each workgroup compacts a contiguous range of
+// slots and reserves its output range with one atomic; n_pairs ends as the
+// number of keys (the list order is settled by the bucket sort that follows).
+constexpr int kListThreads = 256, kListItems = 16;
+__global__ __launch_bounds__(kListThreads) void k_hash_list(const uint64_t *hash, int64_t cap, uint64_t *uniq,
+                                                            int64_t uniq_cap, Counters *cnt) {
+  __shared__ int wsum[kListThreads / 64];
+  __shared__ unsigned long long base_sh;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int64_t r0 = (int64_t)blockIdx.x * kListThreads * kListItems; r0 < cap;
+       r0 += (int64_t)gridDim.x * kListThreads * kListItems) {
+    // slots r0 + (w * kListItems + j) * 64 + lane: each wavefront a contiguous stretch
+    uint64_t key[kListItems];
+    int cnt_w = 0;
+#pragma unroll
+    for (int j = 0; j < kListItems; ++j) {
+      const int64_t e = r0 + ((int64_t)(w * kListItems + j) << 6) + lane;
+      key[j] = e < cap ? hash[e] : kEmpty;
+      cnt_w += __popcll(__ballot(key[j] != kEmpty));
+    }
+    if (lane == 0) wsum[w] = cnt_w;
+    __syncthreads();
+    if (t == 0) {
+      int tot = 0;
+      for (int k = 0; k < kListThreads / 64; ++k) tot += wsum[k];
+      base_sh = tot ? atomicAdd(&cnt->n_pairs, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long o = base_sh;
+    for (int k = 0; k < w; ++k) o += (unsigned long long)wsum[k];
+#pragma unroll
+    for (int j = 0; j < kListItems; ++j) {
+      const bool keep = key[j] != kEmpty;
+      const unsigned long long m = __ballot(keep);
+      if (keep) {
+        const unsigned long long idx = o + __popcll(m & lt);
+        if ((int64_t)idx < uniq_cap) uniq[idx] = key[j];
+      }
+      o += __popcll(m);
+    }
+    __syncthreads();
   }
 }
 
@@ -369,13 +423,19 @@ void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_sce
 }
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
                        const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
-                       int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st) {
-  k_cell_pairs<<<grid1d(n_cp_cap, 64), 64, 0, st>>>(S, ves_box, ves_scene, keys, vals, n_cp, n_cp_cap, hash,
-                                                       hash_cap, uniq, uniq_cap, cnt);
+                       int64_t hash_cap, Counters *cnt, hipStream_t st) {
+  // one wavefront per check point (grid-stride beyond 4096 x 4 wavefronts)
+  k_cell_pairs<<<grid1d(n_cp_cap, 4, 4096), 256, 0, st>>>(S, ves_box, ves_scene, keys, vals, n_cp, n_cp_cap, hash,
+                                                          hash_cap, cnt);
 }
 void launch_self_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, uint64_t *hash,
-                       int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt, hipStream_t st) {
-  k_self_pairs<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_box, ves_scene, hash, hash_cap, uniq, uniq_cap, cnt);
+                       int64_t hash_cap, Counters *cnt, hipStream_t st) {
+  k_self_pairs<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_box, ves_scene, hash, hash_cap, cnt);
+}
+void launch_hash_list(const uint64_t *hash, int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt,
+                      hipStream_t st) {
+  k_hash_list<<<grid1d(hash_cap, kListThreads * kListItems, 1024), kListThreads, 0, st>>>(hash, hash_cap, uniq,
+                                                                                         uniq_cap, cnt);
 }
 void launch_pair_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, Counters *cnt,
                               hipStream_t st) {

@@ -556,10 +556,9 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                         P<int64_t>(ctx->rs_off), st);
   launch_fill_u64(P<uint64_t>(ctx->hash), ~0ull, hash_cap, st);
   launch_cell_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->cp_keys),
-                    P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap,
-                    P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
-  launch_self_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->hash), hash_cap,
-                    P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
+                    P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap, cnt, st);
+  launch_self_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->hash), hash_cap, cnt, st);
+  launch_hash_list(P<uint64_t>(ctx->hash), hash_cap, P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
   launch_fill_i32(P<int32_t>(ctx->cnt_a), 0, N + 1, st);
   launch_fill_i32(P<int32_t>(ctx->cursor_a), 0, N + 1, st);
   launch_pair_bucket_count(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a), cnt, st);
