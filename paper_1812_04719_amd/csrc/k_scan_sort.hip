@@ -11,11 +11,13 @@ namespace {
 
 constexpr int kScanThreads = 1024;
 
-// Block-wide inclusive scan of one value per thread (1024 threads): a
-// shuffle scan inside each wavefront, the 16 wavefront totals scanned by
-// the first wavefront, two workgroup barriers in all.  sh needs 16 entries.
-template <typename T>
+// Block-wide inclusive scan of one value per thread (NT threads, at most
+// 4096): a shuffle scan inside each wavefront, the wavefront totals scanned
+// by the first wavefront, two workgroup barriers in all.  sh needs NT / 64
+// entries.
+template <typename T, int NT = kScanThreads>
 __device__ T block_inclusive_scan(T v, T *sh) {
+  static_assert(NT % 64 == 0 && NT / 64 <= 64, "whole wavefronts, totals in one wavefront");
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -25,13 +27,13 @@ __device__ T block_inclusive_scan(T v, T *sh) {
   if (lane == 63) sh[wave] = v;
   __syncthreads();
   if (wave == 0) {
-    T w = lane < kScanThreads / 64 ? sh[lane] : T(0);
+    T w = lane < NT / 64 ? sh[lane] : T(0);
 #pragma unroll
-    for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+    for (int off = 1; off < NT / 64; off <<= 1) {
       const T u = __shfl_up(w, off, 64);
       if (lane >= off) w += u;
     }
-    if (lane < kScanThreads / 64) sh[lane] = w;
+    if (lane < NT / 64) sh[lane] = w;
   }
   __syncthreads();
   const T r = v + (wave ? sh[wave - 1] : T(0));
@@ -70,6 +72,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const TIn *in, int64
 // (digit, tile); (3) every key's rank among the equal digits before it in
 // its tile -- matched across the wavefront by ballots on the 8 digit bits,
 // carried across rounds and wavefronts in LDS -- gives its output position.
+// Up to kRsFusedMaxBlocks tiles, (2) and (3) are one launch (k_rs_pass: each
+// workgroup sums the histogram itself), so a pass costs two launches.
 // Equal keys keep their input order (stable), as Alg. 1 requires.
 // --------------------------------------------------------------------------
 constexpr int kRsThreads = 256, kRsItems = 8, kRsTile = kRsThreads * kRsItems, kRsWaves = kRsThreads / 64;
@@ -145,6 +149,81 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *sk, c
   for (int j = 0; j < kRsItems; ++j) {
     if (dg[j] < 0) continue;
     const int64_t dst = hoff[(int64_t)dg[j] * nblk + b] + woff[w][dg[j]] + rank[j];
+    dk[dst] = key[j];
+    dv[dst] = val[j];
+  }
+}
+
+// Offsets and scatter of one pass in one launch, for inputs of at most
+// kRsFusedMaxBlocks tiles: each workgroup finds the output position of its
+// tile's first key of every digit from the whole histogram of the pass
+// (counts of all smaller digits in every tile, plus this digit in the tiles
+// before), then ranks and scatters its keys as k_rs_scatter does.  This
+// replaces the scan launches between the histogram and the scatter.
+constexpr int kRsFusedMaxBlocks = 256;
+__global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint64_t *sk, const uint32_t *sv, uint64_t *dk,
+                                                        uint32_t *dv, const unsigned long long *n_dev,
+                                                        int64_t n_host, int shift, const int32_t *hin, int nblk) {
+  __shared__ int wcnt[kRsWaves][256];
+  __shared__ int woff[kRsWaves][256];
+  __shared__ int64_t dbase[256];
+  __shared__ int64_t sh[kRsWaves];
+  const int64_t n = rs_count(n_dev, n_host);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, b = blockIdx.x;
+  {
+    // thread t: digit t
+    int64_t tot = 0, before = 0;
+    const int32_t *row = hin + (int64_t)t * nblk;
+    for (int bb = 0; bb < nblk; ++bb) {
+      const int c = row[bb];
+      tot += c;
+      before += bb < b ? c : 0;
+    }
+    const int64_t inc = block_inclusive_scan<int64_t, kRsThreads>(tot, sh);
+    dbase[t] = inc - tot + before;
+  }
+  for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&wcnt[0][0])[k] = 0;
+  __syncthreads();
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t base = (int64_t)b * kRsTile + (int64_t)w * (kRsItems * 64);
+  uint64_t key[kRsItems];
+  uint32_t val[kRsItems];
+  int dg[kRsItems], rank[kRsItems];
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    const int64_t e = base + j * 64 + lane;
+    const bool valid = e < n;
+    key[j] = valid ? sk[e] : 0ull;
+    val[j] = valid ? sv[e] : 0u;
+    const int d = valid ? (int)((key[j] >> shift) & 255u) : 0;
+    dg[j] = valid ? d : -1;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const unsigned long long m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    int pre = 0;
+    if (valid) pre = wcnt[w][d];
+    rank[j] = pre + __popcll(peers & lt);
+    if (valid && (peers >> lane) == 1ull) wcnt[w][d] = pre + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  {
+    int run = 0;
+#pragma unroll
+    for (int ww = 0; ww < kRsWaves; ++ww) {
+      woff[ww][t] = run;
+      run += wcnt[ww][t];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    if (dg[j] < 0) continue;
+    const int64_t dst = dbase[dg[j]] + woff[w][dg[j]] + rank[j];
     dk[dst] = key[j];
     dv[dst] = val[j];
   }
@@ -269,8 +348,12 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
   int passes = 0;
   for (int shift = 0; shift < key_bits; shift += 8, ++passes) {
     k_rs_hist<<<nblk, kRsThreads, 0, st>>>(sk, n_dev, n_host, shift, hist, nblk);
-    scan_any<int32_t>(hist, hoff, nullptr, (int64_t)256 * nblk, hoff + (int64_t)256 * nblk + 1, st);
-    k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hoff, nblk);
+    if (nblk <= kRsFusedMaxBlocks) {
+      k_rs_pass<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hist, nblk);
+    } else {
+      scan_any<int32_t>(hist, hoff, nullptr, (int64_t)256 * nblk, hoff + (int64_t)256 * nblk + 1, st);
+      k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hoff, nblk);
+    }
     uint64_t *xk = sk; sk = dk; dk = xk;
     uint32_t *xv = sv; sv = dv; dv = xv;
   }

@@ -66,6 +66,22 @@ def test_sort_stability_large(ctx):
     assert np.array_equal(vals.cpu().numpy(), order)
 
 
+@pytest.mark.parametrize("n", [1, 2047, 2049, 50000, 600000])
+def test_sort_random_u64(ctx, n):
+    """Stable sort of full 64-bit keys with repeats: one launch per pass up to
+    256 tiles of 2048 keys, histogram / scan / scatter launches above."""
+    import torch
+    rng = np.random.default_rng(n)
+    k = rng.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
+    k[rng.integers(0, n, n // 4)] = k[0]
+    keys = torch.tensor(k.view(np.int64), device="cuda:0")
+    vals = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    ctx.sort_pairs_u64(keys, vals)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(vals.cpu().numpy(), order)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), k[order])
+
+
 def test_parity_two_spheres(ctx):
     g, o = check(ctx, S.make_config(1))
     assert o["n_ct_vt"] > 0 and o["n_vol"] == 1
