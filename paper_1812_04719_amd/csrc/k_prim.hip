@@ -32,8 +32,17 @@ __device__ inline unsigned long long lanemask_lt() {
 constexpr int kPPThreads = 256;
 constexpr int kPPBuf = 512;
 
-__device__ inline bool ov6f_(const float *A, const float *B) {
-  return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
+// Closed-interval overlap of two FP32 boxes (lo x, y, z, hi x, y, z) held in
+// LDS at 8-byte aligned addresses: both boxes are read with three 8-byte
+// loads each and the six compares are combined without branches (a
+// short-circuit chain would wait for one pair of loads after another).
+__device__ inline bool ov6f_lds(const float *A, const float *B) {
+  const float2 a0 = *reinterpret_cast<const float2 *>(A), a1 = *reinterpret_cast<const float2 *>(A + 2),
+               a2 = *reinterpret_cast<const float2 *>(A + 4);
+  const float2 b0 = *reinterpret_cast<const float2 *>(B), b1 = *reinterpret_cast<const float2 *>(B + 2),
+               b2 = *reinterpret_cast<const float2 *>(B + 4);
+  // a0 = (lo x, lo y), a1 = (lo z, hi x), a2 = (hi y, hi z)
+  return (a0.x <= b1.y) & (b0.x <= a1.y) & (a0.y <= b2.x) & (b0.y <= a2.x) & (a1.x <= b2.y) & (b1.x <= a2.y);
 }
 
 // One workgroup per vesicle pair.  Each side's patch boxes that meet the
@@ -45,7 +54,8 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
                                                             const double *ves_box, const int64_t *ves_patch_off,
                                                             const double *patch_box, WorkRec *work,
                                                             int64_t work_cap, Counters *cnt, int64_t pairs_cap) {
-  __shared__ float bA[kMaxPatchesPerVes][6], bB[kMaxPatchesPerVes][6];
+  __shared__ alignas(8) float bA[kMaxPatchesPerVes][6];
+  __shared__ alignas(8) float bB[kMaxPatchesPerVes][6];
   __shared__ short iA[kMaxPatchesPerVes], iB[kMaxPatchesPerVes];
   __shared__ WorkRec buf[kPPBuf];
   __shared__ int nA, nB, nbuf;
@@ -98,7 +108,7 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
       const int t = t0 + threadIdx.x;
       if (t < tot) {
         const int x = t / mb, y = t - x * mb;
-        if (ov6f_(bA[x], bB[y])) {
+        if (ov6f_lds(bA[x], bB[y])) {
           const int q = atomicAdd(&nbuf, 1);
           WorkRec w;
           w.p = (int)p;
@@ -166,17 +176,18 @@ struct WaveLds {
   static constexpr int kR = TileCaps<TILE>::owne > TILE ? TileCaps<TILE>::owne : TILE;
   double pos[2][kRef][6];  // raw X0 (x, y, z), X1 (x, y, z) of the referenced vertices
   double sh[3];            // image shift of the pair
-  float vbox[2][kRef][6];  // FP32 space-time box of each referenced vertex
-  float lbox[kL][6];       // left-hand list (current chunk) of the current kind: FP32 boxes
-  float rbox[kR][6];       // right-hand list
+  float vbox[2][kRef][6];             // FP32 space-time box of each referenced vertex
+  alignas(8) float lbox[kL][6];       // left-hand list (current chunk) of the current kind: FP32 boxes
+  alignas(8) float rbox[kR][6];       // right-hand list
   uint8_t lk[kL];          // patch-local indices of the left-hand list
   uint8_t rk[kR];          // and of the right-hand list
   uint32_t hits[kHitBuf];  // kind << 16 | left << 8 | right (patch-local indices)
   alignas(16) int blob[2][Lay::lds];  // header and slot arrays of the two patch blobs
 };
 
+// Overlap of two FP32 boxes in registers (branch-free).
 __device__ inline bool ov6f(const float *A, const float *B) {
-  return A[0] <= B[3] && B[0] <= A[3] && A[1] <= B[4] && B[1] <= A[4] && A[2] <= B[5] && B[2] <= A[5];
+  return (A[0] <= B[3]) & (B[0] <= A[3]) & (A[1] <= B[4]) & (B[1] <= A[4]) & (A[2] <= B[5]) & (B[2] <= A[5]);
 }
 
 // FP64 box of a primitive (min - h + sh, max + h + sh), rounded outward to
@@ -506,7 +517,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           if ((int)t < tot) {
             x = (int)(((unsigned long long)t * magic) >> 32);
             y = (int)t - x * nr;
-            hit = ov6f(W.lbox[x], W.rbox[y]);
+            hit = ov6f_lds(W.lbox[x], W.rbox[y]);
           }
           const unsigned long long mh = __ballot(hit);
           if (hit)
