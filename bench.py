@@ -38,6 +38,13 @@ LDS_BYTES_PER_BOX_TEST = 48.0       # two 6-float boxes read from LDS
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # LDS: 128 bytes per clock per CU
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+# Algorithmic bytes and flops of the whole path (what the method must move and compute):
+# X0 and X1 read once, 16 B per vesicle pair, 128 B per vertex-triangle contact (key, tau, V,
+# 12-gradient), 32 B per edge-edge contact, 8 B per volume, 32 B per Jacobian row; F's
+# coefficients per candidate (170 flops) and V with its gradient per vertex-triangle contact.
+ALG_BYTES = {"vertex": 48.0, "pair": 16.0, "vt": 128.0, "ee": 32.0, "vol": 8.0, "jrow": 32.0}
+ALG_FLOPS_PER_CANDIDATE = 170.0
+FLUSH_BYTES = 1 << 30               # written before each cold-cache step (larger than the 256 MB MALL)
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE + WRITE_SIZE on this workload,
 # each scaled by the counter's reading for a plain 1 GiB copy (factors 2.0 and 1.0), for the
 # kernel as it was built when the counters were taken (profiles/, HBM traffic summary);
@@ -59,6 +66,7 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--plain-only", action="store_true", help="skip the learned-bracket timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-scene batch measurement")
+    ap.add_argument("--no-single-thread", action="store_true", help="skip the single-thread oracle run")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 256-scene batch measurement (for profiling it); prints its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
@@ -170,6 +178,47 @@ def main():
             roof["lds_tbs"] = round(lds, 3)
             roof["lds_frac"] = round(lds / LDS_PEAK_TBS, 4)
 
+    # measured copy bandwidth (1 GiB device-to-device) beside the datasheet peak
+    src = torch.empty(FLUSH_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * FLUSH_BYTES * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    if roof.get("hbm_gbs"):
+        roof["hbm_frac_of_copy"] = round(roof["hbm_gbs"] / copy_gbs, 4)
+    # cold cache: before every step a 1 GiB write evicts the input from the 256 MB MALL;
+    # each step is timed alone with events (the write is outside the timed window)
+    cold = []
+    for k in range(max(5, args.steps // 2)):
+        dst.fill_(float(k))
+        torch.cuda.synchronize()
+        e0.record()
+        stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False, learned_bracket=(mode == "learned"))
+        e1.record()
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    del src, dst
+    cold_ms = float(np.median(cold))
+    cold_cache = {"ms_per_step": round(cold_ms, 4), "candidate_pairs_per_s": round(n_cand / (cold_ms * 1e-3), 1),
+                  "contacts_per_s": round(n_ct / (cold_ms * 1e-3), 1), "steps": len(cold),
+                  "flush_bytes": FLUSH_BYTES, "statistic": "median"}
+    log("cold cache: %s" % cold_cache)
+    # algorithmic fractions of the whole path
+    b_alg = (ALG_BYTES["vertex"] * sc.n_vtx + ALG_BYTES["pair"] * res["n_pairs"] + ALG_BYTES["vt"] * res["n_ct_vt"]
+             + ALG_BYTES["ee"] * res["n_ct_ee"] + ALG_BYTES["vol"] * res["n_vol"] + ALG_BYTES["jrow"] * res["n_jrow"])
+    f_alg = ALG_FLOPS_PER_CANDIDATE * n_cand + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
+    t_fp = float(stages[3] + stages[4] + stages[5]) * 1e-3  # screens, root search, volumes, aggregation
+    algorithmic = {"bytes": int(b_alg), "hbm_frac": round(b_alg / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),
+                   "flops": int(f_alg), "fp64_frac": round(f_alg / t_fp / (FP64_PEAK_TFLOPS * 1e12), 5),
+                   "fp64_time": "primitive_candidates + narrow_volume_gradient + aggregation"}
+
     out = {
         "metric": METRIC,
         "value": round(pairs_per_s, 1),
@@ -193,6 +242,8 @@ def main():
         "stages_ms": stage_ms,
         "work": work,
         "roofline": roof,
+        "cold_cache": cold_cache,
+        "algorithmic": algorithmic,
         "toi_search": mode,
         "learned_vs_plain": learned,
     }
@@ -208,12 +259,25 @@ def main():
             ts.append(time.perf_counter() - t1)
         tmed = float(np.median(ts))
         oc = r["n_cand_vt"] + r["n_cand_ee"]
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": round(oc / tmed, 1), "unit": "candidate pairs/s",
                                "contacts_per_s": round(r["n_ct"] / tmed, 1), "cores": int(r["threads_used"]),
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model, "nproc": os.cpu_count(),
                                "sample": "whole 1440-vesicle scene, median of %d runs (%.2f s each)"
                                          % (args.cpu_reps, tmed)}
         log("oracle: %.2f s per run on %d threads" % (tmed, r["threads_used"]))
+        if not args.no_single_thread:
+            t1 = time.perf_counter()
+            r1 = oracle.detect(sc, threads=1)
+            t_one = time.perf_counter() - t1
+            out["cpu_baseline"]["single_thread"] = {"value": round((r1["n_cand_vt"] + r1["n_cand_ee"]) / t_one, 1),
+                                                    "seconds": round(t_one, 2), "cores": int(r1["threads_used"])}
+            log("oracle: %.2f s on 1 thread" % t_one)
     ctx.close()
     print(json.dumps(out), flush=True)
 
