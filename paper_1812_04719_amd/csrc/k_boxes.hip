@@ -37,9 +37,12 @@ __device__ inline double okey_inv(unsigned long long k) {
 // loads of X0 and X1), folds them into the vesicle box and, through the
 // vertex -> patch incidence lists, into the LDS boxes of the patches that
 // reference the vertex.
+// MAXP bounds the patches of any vesicle's topology (LDS is sized for it, so
+// small meshes keep more workgroups resident).
+template <int MAXP>
 __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, const int64_t *ves_patch_off,
                                                double *ves_box, double *patch_box, Counters *cnt) {
-  __shared__ unsigned long long pk[kMaxPatchesPerVes][6];  // lo as key, hi as key
+  __shared__ unsigned long long pk[MAXP][6];  // lo as key, hi as key
   __shared__ double red[4][6];
   __shared__ int bad_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -113,10 +116,15 @@ __global__ void k_ves_patch_count(DevScene S, DevTopo T, int64_t *out) {
 }  // namespace
 
 void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
-                  double *patch_box, Counters *cnt, hipStream_t st) {
+                  double *patch_box, int max_patches, Counters *cnt, hipStream_t st) {
   int g = S.n_ves < 8192 ? S.n_ves : 8192;
   if (g < 1) return;
-  k_boxes<<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
+  if (max_patches <= 128)
+    k_boxes<128><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
+  else if (max_patches <= 512)
+    k_boxes<512><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
+  else
+    k_boxes<kMaxPatchesPerVes><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
 }
 
 void launch_ves_patch_count(const DevScene &S, const DevTopo &T, int64_t *out, hipStream_t st) {

@@ -50,13 +50,15 @@ __device__ inline bool ov6f_lds(const float *A, const float *B) {
 // conservative filter: the primitive kernel applies the exact test later),
 // the surviving patch pairs are tested, and the work items are buffered in
 // LDS and written with one atomic per flush.
+// MAXP bounds the patches of any vesicle's topology (LDS is sized for it).
+template <int MAXP>
 __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo T, const PairRec *pairs,
                                                             const double *ves_box, const int64_t *ves_patch_off,
                                                             const double *patch_box, WorkRec *work,
                                                             int64_t work_cap, Counters *cnt, int64_t pairs_cap) {
-  __shared__ alignas(8) float bA[kMaxPatchesPerVes][6];
-  __shared__ alignas(8) float bB[kMaxPatchesPerVes][6];
-  __shared__ short iA[kMaxPatchesPerVes], iB[kMaxPatchesPerVes];
+  __shared__ alignas(8) float bA[MAXP][6];
+  __shared__ alignas(8) float bB[MAXP][6];
+  __shared__ short iA[MAXP], iB[MAXP];
   __shared__ WorkRec buf[kPPBuf];
   __shared__ int nA, nB, nbuf;
   __shared__ unsigned long long base_sh;
@@ -557,9 +559,16 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
 
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
-                        WorkRec *work, int64_t work_cap, Counters *cnt, hipStream_t st) {
-  k_patch_pairs<<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap, cnt,
-                                             pairs_cap);
+                        WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt, hipStream_t st) {
+  if (max_patches <= 128)
+    k_patch_pairs<128><<<4096, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
+                                                    cnt, pairs_cap);
+  else if (max_patches <= 512)
+    k_patch_pairs<512><<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
+                                                    cnt, pairs_cap);
+  else
+    k_patch_pairs<kMaxPatchesPerVes><<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box,
+                                                                  work, work_cap, cnt, pairs_cap);
 }
 
 template <int TILE>

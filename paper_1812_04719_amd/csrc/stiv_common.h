@@ -154,8 +154,8 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // K0
 void launch_ves_patch_count(const DevScene &S, const DevTopo &T, int64_t *cnt_out, hipStream_t st);
-void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off,
-                  double *ves_box, double *patch_box, Counters *cnt, hipStream_t st);
+void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
+                  double *patch_box, int max_patches, Counters *cnt, hipStream_t st);
 
 // K1
 void launch_ves_scene(const DevScene &S, int *ves_scene, hipStream_t st);
@@ -182,7 +182,7 @@ void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const
 // K2
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
-                        WorkRec *work, int64_t work_cap, Counters *cnt, hipStream_t st);
+                        WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt, hipStream_t st);
 // hard_geo: geometry of the queued candidates for the root search, SoA
 // [24][hard_cap]: X0 (shifted) x, y, z of vertices 0..3, then D = X1 - X0.
 void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,

@@ -538,7 +538,8 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   // ---- K0 boxes
   if (timed) (void)hipEventRecord(ctx->ev[0], st);
-  launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box), cnt, st);
+  launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box),
+               ctx->max_patches, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[1], st);
   // ---- K1 vesicle broad phase
   launch_ves_scene(S, P<int>(ctx->ves_scene), st);
@@ -571,7 +572,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   // ---- K2 primitive broad phase
   launch_patch_pairs(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, P<double>(ctx->ves_box),
                      P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<WorkRec>(ctx->work),
-                     ctx->cap_work, cnt, st);
+                     ctx->cap_work, ctx->max_patches, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[3], st);
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
   launch_prim_cand(ctx->tile, ctx->prim_blocks, S, T, P<PairRec>(ctx->pairs), P<WorkRec>(ctx->work),

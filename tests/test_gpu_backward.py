@@ -58,6 +58,22 @@ def test_backward_vs_oracle_rsa(ctx):
         assert np.abs(got - want).max() <= 1e-10 * scale
 
 
+def test_backward_vs_oracle_1440(ctx):
+    """The full 1440-vesicle scene: every vertex-triangle contact's adjoint
+    (random cotangents on all volumes and J rows) against the oracle's
+    complex-step backward, 1e-10 of the largest component."""
+    sc = S.make_config(3)
+    gV, gG, dX0, dX1, res = _gpu_backward(ctx, sc, 7)
+    ora = oracle.detect(sc)
+    assert np.array_equal(res["ct_key"].cpu().numpy(), ora["ct_key"])
+    assert int(res["n_ct_vt"]) > 10000
+    o0, o1 = parity.oracle_backward(sc, ora, gV, gG)
+    for got, want in ((dX0, o0), (dX1, o1)):
+        scale = np.abs(want).max()
+        assert scale > 0
+        assert np.abs(got - want).max() <= 1e-10 * scale, np.abs(got - want).max() / scale
+
+
 def test_autograd_function_vs_finite_differences(ctx):
     """torch.autograd through the library backward vs central FD (h = 1e-6) of
     L = sum(a V) + sum(b G) on a sample of coordinates of X0 and X1."""
