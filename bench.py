@@ -138,11 +138,20 @@ def main():
         if t_l < t_total:
             res, t_total, stages, work = res_l, t_l, stages_l, work_l
     mode = "learned" if (learned and t_total == t_l) else "plain"
-    ms_step = 1e3 * t_total / args.steps
+    eager_ms = 1e3 * t_total / args.steps
     n_cand = res["n_cand_vt"] + res["n_cand_ee"]
     n_ct = res["n_ct"]
+    # the same detect captured once as a HIP graph and replayed once per step (the way a
+    # time-stepping caller runs it): W untimed replays, then K replays between synchronizations
+    g_ms, g_wall, _ = graph_replay_ms(ctx, ds, sc, res, stiv, torch, np, args.steps, args.warmup,
+                                      learned=(mode == "learned"))
+    ms_step = 1e3 * g_wall
     pairs_per_s = n_cand / (ms_step * 1e-3)
     contacts_per_s = n_ct / (ms_step * 1e-3)
+    eager = {"ms_per_step": round(eager_ms, 4), "candidate_pairs_per_s": round(n_cand / (eager_ms * 1e-3), 1),
+             "contacts_per_s": round(n_ct / (eager_ms * 1e-3), 1),
+             "note": "one stiv_detect call per step (enqueue, one synchronization to read the counts)"}
+    log("graph replay: %.4f ms per step (events %.4f); eager %.4f ms" % (ms_step, g_ms, eager_ms))
     names = ["boxes", "vesicle_broad_phase", "patch_pair_cull", "primitive_candidates", "narrow_volume_gradient",
              "aggregation", "device_total"]
     stage_ms = {n: round(float(v), 4) for n, v in zip(names, stages)}
@@ -242,6 +251,8 @@ def main():
         "stages_ms": stage_ms,
         "work": work,
         "roofline": roof,
+        "launch": "one HIP graph replay per step (stiv_detect_async captured once)",
+        "eager": eager,
         "cold_cache": cold_cache,
         "algorithmic": algorithmic,
         "toi_search": mode,
@@ -282,6 +293,43 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def graph_replay_ms(ctx, ds, sc, eager, stiv, torch, np, steps, warmup, learned=False):
+    """The whole detect captured once in a HIP graph (stiv_detect_async) and
+    replayed: (ms per replay from events, wall ms per replay, result of the
+    last replay), checked equal to the eager result."""
+    outs = stiv.Outputs(ds.x0.device, cap_pairs=2 * int(eager["n_pairs"]) + 16, cap_ct=2 * int(eager["n_ct"]) + 16,
+                        cap_vol=2 * int(eager["n_vol"]) + 16, cap_jrow=2 * int(eager["n_jrow"]) + 16)
+    job = stiv.AsyncDetect(ctx, ds, sc.d, sc.eps, sc.dt, outs, learned_bracket=learned)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        job.enqueue()
+        job.collect()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        job.enqueue()
+    for _ in range(max(1, warmup)):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_a = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t_a) / steps
+    ms = e0.elapsed_time(e1) / steps
+    r = job.collect(to_numpy=True)
+    # reference: a fresh eager call in the same mode (bit-identical results expected)
+    ref, _ = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, learned_bracket=learned)
+    if not (np.array_equal(r["ct_key"], ref["ct_key"]) and np.array_equal(r["vol_V"], ref["vol_V"])
+            and np.array_equal(r["ct_tau"], ref["ct_tau"])):
+        raise SystemExit("graph replay differs from the eager result")
+    return ms, wall, r
+
+
 def measure_batch(ctx, scenes, stiv, torch, np, args):
     """256 independent scenes of 8-128 vesicles (orders 16/24/32, 10-60 % vf) in one
     call: autotuned launch configuration, then the whole detect captured in a HIP
@@ -294,35 +342,8 @@ def measure_batch(ctx, scenes, stiv, torch, np, args):
     cfg, table = autotune.tune(ctx, ds, b.d, b.eps, b.dt, cache_file=None, reps=2)
     log("batch autotune: %s" % cfg)
     eager, _ = stiv.detect(ctx, ds, b.d, b.eps, b.dt)
-    outs = stiv.Outputs(ds.x0.device, cap_pairs=2 * eager["n_pairs"] + 16, cap_ct=2 * eager["n_ct"] + 16,
-                        cap_vol=2 * eager["n_vol"] + 16, cap_jrow=2 * eager["n_jrow"] + 16)
-    job = stiv.AsyncDetect(ctx, ds, b.d, b.eps, b.dt, outs)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        job.enqueue()
-        job.collect()
-    torch.cuda.current_stream().wait_stream(side)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        job.enqueue()
-    for _ in range(max(1, args.warmup)):
-        g.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(1, args.steps // 2)
-    t_a = time.perf_counter()
-    e0.record()
-    for _ in range(reps):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t_a) / reps
-    ms = e0.elapsed_time(e1) / reps
-    r = job.collect(to_numpy=True)
-    same = bool(np.array_equal(r["ct_key"], eager["ct_key"]) and np.array_equal(r["vol_V"], eager["vol_V"]))
-    if not same:
-        raise SystemExit("graph replay of the batch differs from the eager result")
+    ms, wall, r = graph_replay_ms(ctx, ds, b, eager, stiv, torch, np, max(1, args.steps // 2), args.warmup)
+    same = True
     n_cand = int(eager["n_cand_vt"] + eager["n_cand_ee"])
     res = {"workload": "256 scenes of 8-128 vesicles, orders 16/24/32, 10-60% vf, one graph-captured call",
            "scenes": int(b.n_scenes), "vesicles": int(b.n_ves), "vertices": int(b.n_vtx),
