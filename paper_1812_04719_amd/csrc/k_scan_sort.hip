@@ -41,27 +41,42 @@ __device__ T block_inclusive_scan(T v, T *sh) {
   return r;
 }
 
+constexpr int kScanItems = 8, kScanChunk = kScanThreads * kScanItems;
+
+// Exclusive scan in one workgroup: tiles of kScanChunk elements (each thread
+// owns kScanItems consecutive ones), a block scan per tile and a running
+// carry between tiles; out[n] gets the total.
 template <typename TIn>
 __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const TIn *in, int64_t *out,
                                                             const unsigned long long *n_dev, int64_t n_host) {
-  __shared__ int64_t sh[kScanThreads];
+  __shared__ int64_t sh[kScanThreads / 64];
+  __shared__ int64_t tile_total;
   // n = n_host, or min(*n_dev, n_host) when a device count is given
   int64_t n = n_host;
   if (n_dev) n = (int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host;
-  const int t = threadIdx.x;
-  const int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
-  const int64_t lo = (int64_t)t * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  int64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += (int64_t)in[i];
-  int64_t inc = block_inclusive_scan<int64_t>(s, sh);
-  int64_t base = inc - s;
-  for (int64_t i = lo; i < hi; ++i) {
-    int64_t v = (int64_t)in[i];
-    out[i] = base;
-    base += v;
+  int64_t carry = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += kScanChunk) {
+    const int64_t i0 = t0 + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = (i0 + j < n) ? (int64_t)in[i0 + j] : 0;
+      s += v[j];
+    }
+    const int64_t inc = block_inclusive_scan<int64_t>(s, sh);
+    int64_t base = carry + inc - s;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      if (i0 + j < n) out[i0 + j] = base;
+      base += v[j];
+    }
+    if (threadIdx.x == kScanThreads - 1) tile_total = inc;
+    __syncthreads();
+    carry += tile_total;
+    __syncthreads();
   }
-  if (t == kScanThreads - 1) out[n] = inc;
+  if (threadIdx.x == 0) out[n] = carry;
 }
 
 // --------------------------------------------------------------------------
@@ -243,8 +258,6 @@ __global__ void k_rs_copy(const uint64_t *sk, const uint32_t *sv, uint64_t *dk, 
 // chunk with its offset) for long inputs; the single-workgroup kernel above
 // serves short ones.
 // --------------------------------------------------------------------------
-constexpr int kScanItems = 8, kScanChunk = kScanThreads * kScanItems;
-
 template <typename TIn>
 __global__ __launch_bounds__(kScanThreads) void k_scan_sums(const TIn *in, const unsigned long long *n_dev,
                                                             int64_t n_host, int64_t *sums) {
@@ -308,12 +321,16 @@ int grid_for(int64_t n, int threads) {
 
 }  // namespace
 
+// Longest input scanned by one workgroup (8 tiles); longer ones use the
+// three multi-workgroup kernels.
+constexpr int64_t kScanSingleMax = 8 * (int64_t)kScanChunk;
+
 int64_t scan_scratch_elems(int64_t n_host) { return 2 * ((n_host + kScanChunk - 1) / kScanChunk) + 2; }
 
 template <typename TIn>
 static void scan_any(const TIn *in, int64_t *out, const unsigned long long *n_dev, int64_t n_host, int64_t *tmp,
                      hipStream_t st) {
-  if (!tmp || n_host <= 2 * kScanChunk) {
+  if (!tmp || n_host <= kScanSingleMax) {
     k_scan_excl<TIn><<<1, kScanThreads, 0, st>>>(in, out, n_dev, n_host);
     return;
   }
