@@ -221,13 +221,20 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
   }
 }
 
-__global__ void k_write_volumes(const Counters *cnt, const int64_t *pair_off, const int64_t *vol_off,
+// Volumes and J rows to the caller's arrays; workgroup 0 also stores the
+// final counts (check points, volumes, J rows) for the host.
+__global__ void k_write_volumes(Counters *cnt, const int64_t *pair_off, const int64_t *vol_off,
                                 const int64_t *row_off, const int32_t *pair_hasvt, const double *pair_V,
                                 const int32_t *pair_rows, const int32_t *row_vtx_tmp, const double *row_g_tmp,
                                 int32_t *vol_pair, double *vol_V, int64_t cap_vol, int32_t *j_vol, int32_t *j_vtx,
-                                double *j_g, int64_t cap_jrow, int64_t pairs_cap) {
+                                double *j_g, int64_t cap_jrow, int64_t pairs_cap, const int64_t *cp_total) {
   int64_t np = (int64_t)cnt->n_pairs;
   np = np < pairs_cap ? np : pairs_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cnt->n_cp = (unsigned long long)*cp_total;
+    cnt->n_vol = (unsigned long long)vol_off[np];
+    cnt->n_jrow = (unsigned long long)row_off[np];
+  }
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     if (!pair_hasvt[p]) continue;
     const int64_t v = vol_off[p];
@@ -246,15 +253,6 @@ __global__ void k_write_volumes(const Counters *cnt, const int64_t *pair_off, co
       }
     }
   }
-}
-
-__global__ void k_finalize(Counters *cnt, const int64_t *vol_off, const int64_t *row_off, int64_t pairs_cap,
-                           const int64_t *cp_total) {
-  cnt->n_cp = (unsigned long long)*cp_total;
-  int64_t np = (int64_t)cnt->n_pairs;
-  np = np < pairs_cap ? np : pairs_cap;
-  cnt->n_vol = (unsigned long long)vol_off[np];
-  cnt->n_jrow = (unsigned long long)row_off[np];
 }
 
 int g1(int64_t n, int t) {
@@ -283,18 +281,13 @@ void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec
       S, T, pairs, cnt, pair_off, perm, ct, ct_s, ct_vol, ct_grad, dt, gkeys, gidx, out_key, out_tau, out_vol,
       out_grad, cap_ct, pair_V, pair_hasvt, pair_rows, row_vtx_tmp, row_g_tmp, pairs_cap);
 }
-void launch_write_volumes(const Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,
+void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,
                           const int64_t *row_off, const int32_t *pair_hasvt, const double *pair_V,
                           const int32_t *pair_rows, const int32_t *row_vtx_tmp, const double *row_g_tmp,
                           int32_t *vol_pair, double *vol_V, int64_t cap_vol, int32_t *j_vol, int32_t *j_vtx,
-                          double *j_g, int64_t cap_jrow, hipStream_t st) {
+                          double *j_g, int64_t cap_jrow, const int64_t *cp_total, hipStream_t st) {
   k_write_volumes<<<g1(pairs_cap, 1), 64, 0, st>>>(cnt, pair_off, vol_off, row_off, pair_hasvt, pair_V, pair_rows,
                                                    row_vtx_tmp, row_g_tmp, vol_pair, vol_V, cap_vol, j_vol, j_vtx,
-                                                   j_g, cap_jrow, pairs_cap);
+                                                   j_g, cap_jrow, pairs_cap, cp_total);
 }
-void launch_finalize(Counters *cnt, const int64_t *vol_off, const int64_t *row_off, int64_t pairs_cap,
-                     const int64_t *cp_total, hipStream_t st) {
-  k_finalize<<<1, 1, 0, st>>>(cnt, vol_off, row_off, pairs_cap, cp_total);
-}
-
 }  // namespace stiv

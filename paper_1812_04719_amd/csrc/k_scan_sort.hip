@@ -298,6 +298,53 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const TIn *in, int
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = soff[nblk];
 }
 
+// Several fills in one launch: workgroup row y fills job y.
+__global__ void k_fill_multi(FillJobs J) {
+  const FillJob f = J.job[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < f.n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (f.bytes == 8)
+      reinterpret_cast<uint64_t *>(f.p)[i] = f.v;
+    else
+      reinterpret_cast<uint32_t *>(f.p)[i] = (uint32_t)f.v;
+  }
+}
+
+// Two single-workgroup scans in one launch (workgroup 0: the first array).
+template <typename TIn>
+__global__ __launch_bounds__(kScanThreads) void k_scan_excl2(const TIn *in0, int64_t *out0, const TIn *in1,
+                                                             int64_t *out1, const unsigned long long *n_dev,
+                                                             int64_t n_host) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  __shared__ int64_t tile_total;
+  const TIn *in = blockIdx.x ? in1 : in0;
+  int64_t *out = blockIdx.x ? out1 : out0;
+  int64_t n = n_host;
+  if (n_dev) n = (int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host;
+  int64_t carry = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += kScanChunk) {
+    const int64_t i0 = t0 + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = (i0 + j < n) ? (int64_t)in[i0 + j] : 0;
+      s += v[j];
+    }
+    const int64_t inc = block_inclusive_scan<int64_t>(s, sh);
+    int64_t base = carry + inc - s;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      if (i0 + j < n) out[i0 + j] = base;
+      base += v[j];
+    }
+    if (threadIdx.x == kScanThreads - 1) tile_total = inc;
+    __syncthreads();
+    carry += tile_total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
 __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -375,6 +422,21 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
     uint32_t *xv = sv; sv = dv; dv = xv;
   }
   if (passes & 1) k_rs_copy<<<grid_for(n_host, 256), 256, 0, st>>>(sk, sv, keys, vals, n_dev, n_host);
+}
+void launch_fill_multi(const FillJobs &J, hipStream_t st) {
+  int64_t nmax = 0;
+  for (int k = 0; k < J.count; ++k) nmax = J.job[k].n > nmax ? J.job[k].n : nmax;
+  if (J.count <= 0 || nmax <= 0) return;
+  k_fill_multi<<<dim3(grid_for(nmax, 256), J.count), 256, 0, st>>>(J);
+}
+void launch_scan2_i32_to_i64(const int32_t *in0, int64_t *out0, const int32_t *in1, int64_t *out1,
+                             const unsigned long long *n_dev, int64_t n_host, int64_t *tmp, hipStream_t st) {
+  if (n_host <= kScanSingleMax) {
+    k_scan_excl2<int32_t><<<2, kScanThreads, 0, st>>>(in0, out0, in1, out1, n_dev, n_host);
+    return;
+  }
+  scan_any<int32_t>(in0, out0, n_dev, n_host, tmp, st);
+  scan_any<int32_t>(in1, out1, n_dev, n_host, tmp, st);
 }
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u64<<<grid_for(n, 256), 256, 0, st>>>(p, v, n);

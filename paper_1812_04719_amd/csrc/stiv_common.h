@@ -149,6 +149,24 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
                            int64_t *hoff, hipStream_t st);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+// Up to 8 fills (4- or 8-byte elements) in one launch.
+struct FillJob {
+  void *p;
+  uint64_t v;
+  int64_t n;
+  int bytes;
+};
+struct FillJobs {
+  FillJob job[8];
+  int count = 0;
+  void add(void *p, uint64_t v, int64_t n, int bytes) {
+    if (n > 0) job[count++] = FillJob{p, v, n, bytes};
+  }
+};
+void launch_fill_multi(const FillJobs &J, hipStream_t st);
+// Two exclusive scans of the same length (one launch when short enough).
+void launch_scan2_i32_to_i64(const int32_t *in0, int64_t *out0, const int32_t *in1, int64_t *out1,
+                             const unsigned long long *n_dev, int64_t n_host, int64_t *tmp, hipStream_t st);
 void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
@@ -234,14 +252,11 @@ void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec
                               uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_vol,
                               double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
                               int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp, hipStream_t st);
-void launch_write_volumes(const Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,
+void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,
                           const int64_t *row_off, const int32_t *pair_hasvt, const double *pair_V,
                           const int32_t *pair_rows, const int32_t *row_vtx_tmp, const double *row_g_tmp,
                           int32_t *vol_pair, double *vol_V, int64_t cap_vol, int32_t *j_vol, int32_t *j_vtx,
-                          double *j_g, int64_t cap_jrow, hipStream_t st);
-void launch_finalize(Counters *cnt, const int64_t *vol_off, const int64_t *row_off, int64_t pairs_cap,
-                     const int64_t *cp_total, hipStream_t st);
-
+                          double *j_g, int64_t cap_jrow, const int64_t *cp_total, hipStream_t st);
 // Backward pass
 void launch_backward(const DevScene &S, const DevTopo &T, double d, double eps, double dt, int64_t n_ct,
                      const int32_t *ct_key, const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift,

@@ -533,7 +533,17 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   const DevTopo &T = ctx->topo;
   const int64_t hash_cap = pow2_at_least(4 * ctx->cap_pairs);
   if (timed) (void)hipEventRecord(ctx->ev[8], st);
-  launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 0ull, sizeof(Counters) / 8, st);
+  {
+    // every buffer this call clears, in one launch
+    FillJobs J;
+    J.add(cnt, 0ull, (int64_t)(sizeof(Counters) / 8), 8);
+    J.add(P<uint64_t>(ctx->hash), ~0ull, hash_cap, 8);
+    J.add(P<int32_t>(ctx->cnt_a), 0ull, N + 1, 4);
+    J.add(P<int32_t>(ctx->cursor_a), 0ull, N + 1, 4);
+    J.add(P<int32_t>(ctx->pair_cnt), 0ull, ctx->cap_pairs + 1, 4);
+    J.add(P<int32_t>(ctx->pair_cursor), 0ull, ctx->cap_pairs + 1, 4);
+    launch_fill_multi(J, st);
+  }
   launch_ves_patch_count(S, T, P<int64_t>(ctx->ves_patch_cnt), st);
   launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   // ---- K0 boxes
@@ -555,13 +565,10 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_radix_sort_u64(P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), P<uint64_t>(ctx->cp_tk),
                         P<uint32_t>(ctx->cp_tv), n_cp, ctx->cap_cp, 30 + scene_bits, P<int32_t>(ctx->rs_hist),
                         P<int64_t>(ctx->rs_off), st);
-  launch_fill_u64(P<uint64_t>(ctx->hash), ~0ull, hash_cap, st);
   launch_cell_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->cp_keys),
                     P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap, cnt, st);
   launch_self_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->hash), hash_cap, cnt, st);
   launch_hash_list(P<uint64_t>(ctx->hash), hash_cap, P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
-  launch_fill_i32(P<int32_t>(ctx->cnt_a), 0, N + 1, st);
-  launch_fill_i32(P<int32_t>(ctx->cursor_a), 0, N + 1, st);
   launch_pair_bucket_count(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a), cnt, st);
   launch_scan_i32_to_i64(P<int32_t>(ctx->cnt_a), P<int64_t>(ctx->off_a), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_pair_bucket_scatter(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int64_t>(ctx->off_a),
@@ -587,8 +594,6 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                 (p->flags & STIV_LEARNED_BRACKET) ? ctx->toi_packed.p : nullptr, ctx->toi_kwidth, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
-  launch_fill_i32(P<int32_t>(ctx->pair_cnt), 0, ctx->cap_pairs + 1, st);
-  launch_fill_i32(P<int32_t>(ctx->pair_cursor), 0, ctx->cap_pairs + 1, st);
   launch_ct_pair_count(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int32_t>(ctx->pair_cnt), st);
   const unsigned long long *n_pairs_dev = &cnt->n_pairs;
   launch_scan_i32_to_i64(P<int32_t>(ctx->pair_cnt), P<int64_t>(ctx->pair_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
@@ -600,14 +605,13 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                            out->ct_key, out->ct_tau, out->ct_vol, out->ct_grad, out->cap_ct, P<double>(ctx->pair_V),
                            P<int32_t>(ctx->pair_hasvt), P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx),
                            P<double>(ctx->row_g), st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_hasvt), P<int64_t>(ctx->vol_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
-  launch_scan_i32_to_i64(P<int32_t>(ctx->pair_rows), P<int64_t>(ctx->row_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
+  launch_scan2_i32_to_i64(P<int32_t>(ctx->pair_hasvt), P<int64_t>(ctx->vol_off), P<int32_t>(ctx->pair_rows),
+                          P<int64_t>(ctx->row_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
   launch_write_volumes(cnt, ctx->cap_pairs, P<int64_t>(ctx->pair_off), P<int64_t>(ctx->vol_off),
                        P<int64_t>(ctx->row_off), P<int32_t>(ctx->pair_hasvt), P<double>(ctx->pair_V),
                        P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx), P<double>(ctx->row_g), out->vol_pair,
-                       out->vol_V, out->cap_vol, out->j_vol, out->j_vtx, out->j_g, out->cap_jrow, st);
-  launch_finalize(cnt, P<int64_t>(ctx->vol_off), P<int64_t>(ctx->row_off), ctx->cap_pairs, P<int64_t>(ctx->cp_off) + N,
-                  st);
+                       out->vol_V, out->cap_vol, out->j_vol, out->j_vtx, out->j_g, out->cap_jrow,
+                       P<int64_t>(ctx->cp_off) + N, st);
   if (timed) (void)hipEventRecord(ctx->ev[6], st);
 }
 
