@@ -106,10 +106,17 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
   }
 }
 
-__global__ void k_ves_patch_count(DevScene S, DevTopo T, int64_t *out) {
+// Per vesicle: the number of patches of its topology and its scene index.
+__global__ void k_ves_tables(DevScene S, DevTopo T, int64_t *patch_cnt, int *ves_scene) {
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
     const int t = S.topo_id[v];
-    out[v] = T.patch_off[t + 1] - T.patch_off[t];
+    patch_cnt[v] = T.patch_off[t + 1] - T.patch_off[t];
+    int lo = 0, hi = S.n_scenes;  // invariant: scene_off[lo] <= v < scene_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (S.scene_off[mid] <= v) lo = mid; else hi = mid;
+    }
+    ves_scene[v] = lo;
   }
 }
 
@@ -127,11 +134,11 @@ void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *
     k_boxes<kMaxPatchesPerVes><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
 }
 
-void launch_ves_patch_count(const DevScene &S, const DevTopo &T, int64_t *out, hipStream_t st) {
+void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st) {
   int g = (S.n_ves + 255) / 256;
   if (g < 1) return;
   if (g > 1024) g = 1024;
-  k_ves_patch_count<<<g, 256, 0, st>>>(S, T, out);
+  k_ves_tables<<<g, 256, 0, st>>>(S, T, patch_cnt, ves_scene);
 }
 
 }  // namespace stiv

@@ -116,19 +116,43 @@ __device__ void test_pair_all_shifts(int a, int b, const double *A, const double
 }
 
 // Scene of each vesicle: binary search of scene_off (one thread per vesicle).
-__global__ void k_ves_scene(DevScene S, int *ves_scene) {
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
-    int lo = 0, hi = S.n_scenes;  // invariant: scene_off[lo] <= v < scene_off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (S.scene_off[mid] <= v) lo = mid; else hi = mid;
-    }
-    ves_scene[v] = lo;
+// Number of check points of a box on one axis; full = every cell of a
+// periodic axis (box at least one period long).
+__device__ inline int axis_points(const SceneGrid &g, int c, double lo, double hi, bool *full) {
+  const double e = (hi - lo) + 2.0 * g.tiny;
+  const int ncell = 1 << g.depth;
+  *full = false;
+  if (g.periodic[c] && e >= g.w[c] * ncell) {
+    *full = true;
+    return ncell;
   }
+  int n = (int)ceil(e / g.w[c]) + 1;
+  if (n < 2) n = 2;
+  if (n > ncell + 2) n = ncell + 2;
+  return n;
 }
 
-__global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *box, SceneGrid *grid) {
+__device__ inline uint32_t axis_cell(const SceneGrid &g, int c, double lo, double hi, int k, int n, bool full) {
+  const int ncell = 1 << g.depth;
+  if (full) return (uint32_t)k;
+  const double a = lo - g.tiny, e = (hi - lo) + 2.0 * g.tiny;
+  const double x = (k == n - 1) ? (hi + g.tiny) : a + e * ((double)k / (double)(n - 1));
+  long long ci = (long long)floor((x - g.org[c]) / g.w[c]);
+  if (g.periodic[c]) {
+    ci %= ncell;
+    if (ci < 0) ci += ncell;
+  } else {
+    ci = ci < 0 ? 0 : (ci >= ncell ? ncell - 1 : ci);
+  }
+  return (uint32_t)ci;
+}
+
+// One workgroup per scene: the scene's grid (Alg. 1, first steps), then the
+// number of check points of each of its vesicles' boxes.
+__global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *box, SceneGrid *grid,
+                                                    int64_t *cp_cnt) {
   __shared__ double sh_sum[256], sh_lo[3][256], sh_hi[3][256];
+  __shared__ SceneGrid sg;
   for (int sc = blockIdx.x; sc < S.n_scenes; sc += gridDim.x) {
     const int v0 = S.scene_off[sc], v1 = S.scene_off[sc + 1];
     double sum = 0.0, lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -176,53 +200,19 @@ __global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *bo
       for (int c = 0; c < 3; ++c) g.w[c] = fmax(ext[c], g.tiny) / (double)(1 << depth);
       g.pad = 0;
       grid[sc] = g;
+      sg = g;
     }
     __syncthreads();
-  }
-}
-
-// Number of check points of a box on one axis; full = every cell of a
-// periodic axis (box at least one period long).
-__device__ inline int axis_points(const SceneGrid &g, int c, double lo, double hi, bool *full) {
-  const double e = (hi - lo) + 2.0 * g.tiny;
-  const int ncell = 1 << g.depth;
-  *full = false;
-  if (g.periodic[c] && e >= g.w[c] * ncell) {
-    *full = true;
-    return ncell;
-  }
-  int n = (int)ceil(e / g.w[c]) + 1;
-  if (n < 2) n = 2;
-  if (n > ncell + 2) n = ncell + 2;
-  return n;
-}
-
-__device__ inline uint32_t axis_cell(const SceneGrid &g, int c, double lo, double hi, int k, int n, bool full) {
-  const int ncell = 1 << g.depth;
-  if (full) return (uint32_t)k;
-  const double a = lo - g.tiny, e = (hi - lo) + 2.0 * g.tiny;
-  const double x = (k == n - 1) ? (hi + g.tiny) : a + e * ((double)k / (double)(n - 1));
-  long long ci = (long long)floor((x - g.org[c]) / g.w[c]);
-  if (g.periodic[c]) {
-    ci %= ncell;
-    if (ci < 0) ci += ncell;
-  } else {
-    ci = ci < 0 ? 0 : (ci >= ncell ? ncell - 1 : ci);
-  }
-  return (uint32_t)ci;
-}
-
-__global__ void k_cp_count(DevScene S, const double *box, const int *ves_scene, const SceneGrid *grid,
-                           int64_t *cnt_out) {
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
-    const SceneGrid g = grid[ves_scene[v]];
-    const double *B = box + 6 * (int64_t)v;
-    int64_t tot = 1;
-    for (int c = 0; c < 3; ++c) {
-      bool full;
-      tot *= axis_points(g, c, B[c], B[3 + c], &full);
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+      const double *B = box + 6 * (int64_t)v;
+      int64_t tot = 1;
+      for (int c = 0; c < 3; ++c) {
+        bool full;
+        tot *= axis_points(sg, c, B[c], B[3 + c], &full);
+      }
+      cp_cnt[v] = tot;
     }
-    cnt_out[v] = tot;
+    __syncthreads();
   }
 }
 
@@ -405,17 +395,10 @@ int grid1d(int64_t n, int threads, int maxg = 2048) {
 
 }  // namespace
 
-void launch_ves_scene(const DevScene &S, int *ves_scene, hipStream_t st) {
-  k_ves_scene<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_scene);
-}
-void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, hipStream_t st) {
+void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st) {
   int g = S.n_scenes < 1024 ? S.n_scenes : 1024;
   if (g < 1) return;
-  k_scene_grid<<<g, 256, 0, st>>>(S, ves_box, grid);
-}
-void launch_cp_count(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
-                     int64_t *cp_cnt, hipStream_t st) {
-  k_cp_count<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_box, ves_scene, grid, cp_cnt);
+  k_scene_grid<<<g, 256, 0, st>>>(S, ves_box, grid, cp_cnt);
 }
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
                     const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st) {

@@ -171,15 +171,12 @@ void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // K0
-void launch_ves_patch_count(const DevScene &S, const DevTopo &T, int64_t *cnt_out, hipStream_t st);
+void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st);
 void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
                   double *patch_box, int max_patches, Counters *cnt, hipStream_t st);
 
 // K1
-void launch_ves_scene(const DevScene &S, int *ves_scene, hipStream_t st);
-void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, hipStream_t st);
-void launch_cp_count(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
-                     int64_t *cp_cnt, hipStream_t st);
+void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st);
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
                     const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st);
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,

@@ -544,7 +544,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
     J.add(P<int32_t>(ctx->pair_cursor), 0ull, ctx->cap_pairs + 1, 4);
     launch_fill_multi(J, st);
   }
-  launch_ves_patch_count(S, T, P<int64_t>(ctx->ves_patch_cnt), st);
+  launch_ves_tables(S, T, P<int64_t>(ctx->ves_patch_cnt), P<int>(ctx->ves_scene), st);
   launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   // ---- K0 boxes
   if (timed) (void)hipEventRecord(ctx->ev[0], st);
@@ -552,10 +552,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                ctx->max_patches, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[1], st);
   // ---- K1 vesicle broad phase
-  launch_ves_scene(S, P<int>(ctx->ves_scene), st);
-  launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), st);
-  launch_cp_count(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
-                  P<int64_t>(ctx->cp_cnt), st);
+  launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), P<int64_t>(ctx->cp_cnt), st);
   launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_cp_emit(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
                  P<int64_t>(ctx->cp_off), P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), ctx->cap_cp, st);
