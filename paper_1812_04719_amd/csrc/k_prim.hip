@@ -359,6 +359,33 @@ struct Prefetch {
   double pos[2][6];
 };
 
+// Work items are handed out in chunks of kChunk consecutive items: wavefront b
+// starts with chunk b, and claims each further chunk from a device counter as
+// it enters a chunk, kChunk items before it needs it (so the atomic's latency
+// is hidden and there is one atomic per kChunk items).  Items differ widely in
+// cost; fixed strides left the last 30 % of the kernel with few wavefronts.
+constexpr int kChunk = 8;
+
+struct ItemSeq {
+  int end;      // end of the chunk of the last item handed out
+  int pending;  // lane 0: first item of the chunk claimed next (read when needed)
+};
+
+__device__ inline int claim_chunk(Counters *cnt, int64_t first_dynamic, int lane) {
+  unsigned long long t = 0;
+  if (lane == 0) t = first_dynamic + (unsigned long long)kChunk * atomicAdd(&cnt->work_claimed, 1ull);
+  return (int)(t < 0x7fffffffull ? t : 0x7fffffffull);
+}
+
+// The item after `last` in this wavefront's sequence.
+__device__ inline int next_item(int last, ItemSeq &Q, Counters *cnt, int64_t first_dynamic, int lane) {
+  if (last + 1 < Q.end) return last + 1;
+  const int start = __builtin_amdgcn_readfirstlane(Q.pending);
+  Q.pending = claim_chunk(cnt, first_dynamic, lane);
+  Q.end = start + kChunk;
+  return start;
+}
+
 __device__ inline int load_workrec(const WorkRec *work, int64_t w, int64_t nw, int lane) {
   return (w < nw && lane < 8) ? reinterpret_cast<const int *>(work + w)[lane] : 0;
 }
@@ -409,17 +436,22 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   int64_t nw = (int64_t)cnt->n_work;
   nw = nw < work_cap ? nw : work_cap;
   unsigned long long nvt = 0, nee = 0, ntests = 0, npre = 0;
-  const int64_t G = gridDim.x;
-  int64_t w = blockIdx.x;
+  // this wavefront's items: its own first chunk, then chunks claimed in turn
+  const int64_t first_dynamic = (int64_t)gridDim.x * kChunk;
+  ItemSeq Q;
+  Q.end = (int)(blockIdx.x * kChunk + kChunk);
+  Q.pending = claim_chunk(cnt, first_dynamic, lane);
+  int w = (int)(blockIdx.x * kChunk);
+  int w_next = next_item(w, Q, cnt, first_dynamic, lane);
   // pipeline prologue: the first item completely, the record of the second
   Prefetch<TILE> F;
   int wr_cur = load_workrec(work, w, nw, lane);
-  int wr_next = load_workrec(work, w + G, nw, lane);
+  int wr_next = load_workrec(work, w_next, nw, lane);
   if (w < nw) {
     load_blobs<TILE>(F, T, pairs, wr_cur, lane);
     load_positions<TILE>(F, S, wr_cur, lane);
   }
-  for (; w < nw; w += G) {
+  while (w < nw) {
     // the current item: registers -> LDS
     const int p = __builtin_amdgcn_readlane(wr_cur, 0);
     const int P[2] = {__builtin_amdgcn_readlane(wr_cur, 1), __builtin_amdgcn_readlane(wr_cur, 2)};
@@ -456,9 +488,10 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     }
     // the next item's blobs and the record of the one after it (the loads
     // complete while this item is swept)
-    const bool more = w + G < nw;
+    const bool more = w_next < nw;
     if (more) load_blobs<TILE>(F, T, pairs, wr_next, lane);
-    const int wr_after = load_workrec(work, w + 2 * G, nw, lane);
+    const int w_after = next_item(w_next, Q, cnt, first_dynamic, lane);
+    const int wr_after = load_workrec(work, w_after, nw, lane);
     __syncthreads();
     int nh = 0;  // buffered hits (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
@@ -540,6 +573,8 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
       process_hits<N, TILE>(W, T.blob, P, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
       npre += (unsigned long long)nh;
     }
+    w = w_next;
+    w_next = w_after;
     wr_cur = wr_next;
     wr_next = wr_after;
   }

@@ -118,7 +118,8 @@ struct Counters {
   unsigned long long hash_overflow, shift_overflow, nonfinite, lds_fallback;
   unsigned long long n_tests;      // primitive box-pair tests of the candidate sweep
   unsigned long long n_bracket_ok;  // root searches whose predicted bracket was certified
-  unsigned long long pad[2];
+  unsigned long long work_claimed;  // work-item chunks handed out by the primitive kernel
+  unsigned long long pad;
 };
 
 // Narrow-phase candidate record.
