@@ -118,7 +118,9 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
           w.pb = ptB + iB[y];
           w.base_a = vbA;
           w.base_b = vbB;
-          w.pad[0] = w.pad[1] = w.pad[2] = 0;
+          w.box_a = (int)(pa0 + iA[x]);
+          w.box_b = (int)(pb0 + iB[y]);
+          w.pad = 0;
           buf[q] = w;
         }
       }
@@ -206,15 +208,6 @@ __device__ inline void prim_box32(const float (*vbox)[6], const uint8_t *slot, i
       out[c] = fminf(out[c], vbox[slot[k]][c]);
       out[3 + c] = fmaxf(out[3 + c], vbox[slot[k]][3 + c]);
     }
-}
-
-__device__ inline float wave_minf(float v) {
-  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ inline float wave_maxf(float v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
 }
 
 template <int TILE>
@@ -346,9 +339,10 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2],
 }
 
 // Registers of a work item in flight: its record (lanes 0-7 hold the eight
-// ints of WorkRec), the pair's image shift (lanes 0-2), the header and slot
-// ints of both blobs (one int4 per lane), the referenced vertex ids and, once
-// those have arrived, the positions of the referenced vertices.
+// ints of WorkRec), the pair's image shift (lanes 0-2), the FP64 boxes of both
+// patches (lanes 0-11), the header and slot ints of both blobs (one int4 per
+// lane), the referenced vertex ids and, once those have arrived, the positions
+// of the referenced vertices.
 template <int TILE>
 struct Prefetch {
   using Lay = BlobLayout<TILE>;
@@ -356,6 +350,7 @@ struct Prefetch {
   int4 blob[2];
   int ref[2];
   double sh;
+  double pbox;  // lanes 0-11: the FP64 box of patch lane / 6, component lane % 6
   double pos[2][6];
 };
 
@@ -390,9 +385,10 @@ __device__ inline int load_workrec(const WorkRec *work, int64_t w, int64_t nw, i
   return (w < nw && lane < 8) ? reinterpret_cast<const int *>(work + w)[lane] : 0;
 }
 
-// Blobs, referenced ids and shift of a work item whose record is in wr.
+// Blobs, referenced ids, patch boxes and shift of a work item whose record is in wr.
 template <int TILE>
-__device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const PairRec *pairs, int wr, int lane) {
+__device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const PairRec *pairs, const double *patch_box,
+                                  int wr, int lane) {
   using Lay = BlobLayout<TILE>;
   const int p = __builtin_amdgcn_readlane(wr, 0);
   const int P[2] = {__builtin_amdgcn_readlane(wr, 1), __builtin_amdgcn_readlane(wr, 2)};
@@ -404,6 +400,8 @@ __device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const Pai
     F.ref[side] = lane < Lay::ref ? gb[Lay::pref + lane] : 0;
   }
   F.sh = lane < 3 ? pairs[p].sh[lane] : 0.0;
+  const int box[2] = {__builtin_amdgcn_readlane(wr, 5), __builtin_amdgcn_readlane(wr, 6)};
+  F.pbox = lane < 12 ? patch_box[6 * (int64_t)box[lane >= 6] + lane % 6] : 0.0;
 }
 
 // Positions of the referenced vertices (every lane below the list capacity
@@ -427,7 +425,7 @@ __device__ inline void load_positions(Prefetch<TILE> &F, const DevScene &S, int 
 
 template <int N, int TILE>
 __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const PairRec *pairs, const WorkRec *work,
-                                                  int64_t work_cap, double d, Cand *hard, double *geo,
+                                                  int64_t work_cap, const double *patch_box, double d, Cand *hard, double *geo,
                                                   int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt) {
   using Lay = BlobLayout<TILE>;
   __shared__ WaveLds<TILE> W;
@@ -448,7 +446,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   int wr_cur = load_workrec(work, w, nw, lane);
   int wr_next = load_workrec(work, w_next, nw, lane);
   if (w < nw) {
-    load_blobs<TILE>(F, T, pairs, wr_cur, lane);
+    load_blobs<TILE>(F, T, pairs, patch_box, wr_cur, lane);
     load_positions<TILE>(F, S, wr_cur, lane);
   }
   while (w < nw) {
@@ -464,32 +462,42 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     }
     if (lane < 3) W.sh[lane] = F.sh;
     __syncthreads();
-    float pb[2][6];
+    // FP32 boxes of the referenced vertices, rounded outward, into LDS
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int nref = W.blob[side][Lay::hdr + 0];
-      float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
       if (lane < nref) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const double a = F.pos[side][c], b = F.pos[side][3 + c];
           const double sc = side ? W.sh[c] : 0.0;
-          lo[c] = __double2float_rd((fmin(a, b) - h) + sc);
-          hi[c] = __double2float_ru((fmax(a, b) + h) + sc);
-          W.vbox[side][lane][c] = lo[c];
-          W.vbox[side][lane][3 + c] = hi[c];
+          W.vbox[side][lane][c] = __double2float_rd((fmin(a, b) - h) + sc);
+          W.vbox[side][lane][3 + c] = __double2float_ru((fmax(a, b) + h) + sc);
         }
       }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        pb[side][c] = wave_minf(lo[c]);
-        pb[side][3 + c] = wave_maxf(hi[c]);
+    }
+    // the two patch boxes in FP32 (wave-uniform).  The FP64 patch box is
+    // fl(m - h) with m the exact minimum (maximum) over the patch's vertices,
+    // and x -> round_down(fl(fl(x - h) + s)) is monotone, so this equals the
+    // union of the vertex boxes above.
+    float pb[2][6];
+    {
+      float v = 0.0f;
+      if (lane < 12) {
+        const int c = lane % 6;
+        const double x = F.pbox + (lane >= 6 ? W.sh[c % 3] : 0.0);
+        v = c < 3 ? __double2float_rd(x) : __double2float_ru(x);
       }
+#pragma unroll
+      for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+          pb[side][c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 6 * side + c));
     }
     // the next item's blobs and the record of the one after it (the loads
     // complete while this item is swept)
     const bool more = w_next < nw;
-    if (more) load_blobs<TILE>(F, T, pairs, wr_next, lane);
+    if (more) load_blobs<TILE>(F, T, pairs, patch_box, wr_next, lane);
     const int w_after = next_item(w_next, Q, cnt, first_dynamic, lane);
     const int wr_after = load_workrec(work, w_after, nw, lane);
     __syncthreads();
@@ -545,21 +553,24 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
         // as (t * ceil(2^32 / nr)) >> 32, exact for t < 2^16 (t <= 64 * 128 here)
         const int tot = nl * nr;
         ntests += (unsigned long long)tot;
-        for (int t0 = 0; t0 < tot; t0 += 64) {
-          const unsigned int t = (unsigned int)(t0 + lane);
-          bool hit = false;
-          int x = 0, y = 0;
-          if ((int)t < tot) {
-            x = (int)(((unsigned long long)t * magic) >> 32);
-            y = (int)t - x * nr;
-            hit = ov6f_lds(W.lbox[x], W.rbox[y]);
-          }
-          const unsigned long long mh = __ballot(hit);
-          if (hit)
-            W.hits[nh + __popcll(mh & lanemask_lt())] =
-                ((uint32_t)kind << 16) | ((uint32_t)W.lk[x] << 8) | (uint32_t)W.rk[y];
-          nh += __popcll(mh);
-          if (nh > kHitBuf - 64) {
+        // two rounds per iteration, every load of both issued before either
+        // ballot (lanes past the end test pair 0 and discard it)
+        for (int t0 = 0; t0 < tot; t0 += 128) {
+          const int ta = t0 + lane, tb = t0 + 64 + lane;
+          const bool va = ta < tot, vb = tb < tot;
+          const unsigned int ua = va ? (unsigned int)ta : 0u, ub = vb ? (unsigned int)tb : 0u;
+          const int xa = (int)(((unsigned long long)ua * magic) >> 32), ya = (int)ua - xa * nr;
+          const int xb = (int)(((unsigned long long)ub * magic) >> 32), yb = (int)ub - xb * nr;
+          const bool ha = va & ov6f_lds(W.lbox[xa], W.rbox[ya]);
+          const bool hb = vb & ov6f_lds(W.lbox[xb], W.rbox[yb]);
+          const uint32_t ra = ((uint32_t)kind << 16) | ((uint32_t)W.lk[xa] << 8) | (uint32_t)W.rk[ya];
+          const uint32_t rb = ((uint32_t)kind << 16) | ((uint32_t)W.lk[xb] << 8) | (uint32_t)W.rk[yb];
+          const unsigned long long ma = __ballot(ha), mb = __ballot(hb);
+          if (ha) W.hits[nh + __popcll(ma & lanemask_lt())] = ra;
+          nh += __popcll(ma);
+          if (hb) W.hits[nh + __popcll(mb & lanemask_lt())] = rb;
+          nh += __popcll(mb);
+          if (nh > kHitBuf - 128) {
             process_hits<N, TILE>(W, T.blob, P, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
             npre += (unsigned long long)nh;
             nh = 0;
@@ -608,25 +619,26 @@ void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pair
 
 template <int TILE>
 static void launch_tile(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const WorkRec *work,
-                        int64_t work_cap, double d, Cand *hard, double *geo, int64_t hard_cap, Cand *list,
+                        int64_t work_cap, const double *patch_box, double d, Cand *hard, double *geo, int64_t hard_cap, Cand *list,
                         int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (d == 0.0)
-    k_prim_cand<3, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, work, work_cap, d, hard, geo, hard_cap, list, list_cap,
+    k_prim_cand<3, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, work, work_cap, patch_box, d, hard, geo, hard_cap, list, list_cap,
                                               cnt);
   else
-    k_prim_cand<6, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, work, work_cap, d, hard, geo, hard_cap, list, list_cap,
+    k_prim_cand<6, TILE><<<blocks, 64, 0, st>>>(S, T, pairs, work, work_cap, patch_box, d, hard, geo, hard_cap, list, list_cap,
                                               cnt);
 }
 
 void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,
-                      const WorkRec *work, int64_t work_cap, double d, Cand *hard, double *hard_geo,
+                      const WorkRec *work, int64_t work_cap, const double *patch_box, double d, Cand *hard,
+                      double *hard_geo,
                       int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st) {
   if (tile <= 16)
-    launch_tile<16>(blocks, S, T, pairs, work, work_cap, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
+    launch_tile<16>(blocks, S, T, pairs, work, work_cap, patch_box, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
   else if (tile <= 32)
-    launch_tile<32>(blocks, S, T, pairs, work, work_cap, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
+    launch_tile<32>(blocks, S, T, pairs, work, work_cap, patch_box, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
   else
-    launch_tile<64>(blocks, S, T, pairs, work, work_cap, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
+    launch_tile<64>(blocks, S, T, pairs, work, work_cap, patch_box, d, hard, hard_geo, hard_cap, list, list_cap, cnt, st);
 }
 
 }  // namespace stiv

@@ -48,10 +48,11 @@ struct BlobLayout {
 };
 
 // Patch-pair work item: pair index, global patch-table indices of the two
-// patches and the first global vertex of each vesicle.
+// patches, the first global vertex of each vesicle and the slots of the two
+// patches in the per-call patch-box array.
 struct __align__(16) WorkRec {
   int p, pa, pb, base_a;
-  int base_b, pad[3];
+  int base_b, box_a, box_b, pad;
 };
 
 constexpr int kMaxPatchTri = 64;   // largest supported patch
@@ -202,7 +203,8 @@ void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pair
 // hard_geo: geometry of the queued candidates for the root search, SoA
 // [24][hard_cap]: X0 (shifted) x, y, z of vertices 0..3, then D = X1 - X0.
 void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,
-                      const WorkRec *work, int64_t work_cap, double d, Cand *hard, double *hard_geo,
+                      const WorkRec *work, int64_t work_cap, const double *patch_box, double d, Cand *hard,
+                      double *hard_geo,
                       int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt, hipStream_t st);
 
 // K3 + K4: root search on the queued candidates, volumes and gradients

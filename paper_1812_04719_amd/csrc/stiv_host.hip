@@ -414,6 +414,7 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   if (ctx->cap_cand == 0) ctx->cap_cand = std::max<int64_t>(4 * ctx->cap_work, 1 << 20);
   if (ctx->cap_ct == 0) ctx->cap_ct = std::max<int64_t>(ctx->cap_cand / 8, 1 << 18);
   ctx->cap_patch = N * std::max(ctx->max_patches, 1);
+  if (ctx->cap_patch >= INT32_MAX) return fail(ctx, STIV_E_ARG, "detect: too many patches for 32-bit work records");
   const int64_t hash_cap = pow2_at_least(4 * ctx->cap_pairs);
   HIPCHK(ensure(ctx->counters, sizeof(Counters)));
   HIPCHK(ensure(ctx->ves_box, 6 * 8 * (N + 1)));
@@ -580,7 +581,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   if (timed) (void)hipEventRecord(ctx->ev[3], st);
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
   launch_prim_cand(ctx->tile, ctx->prim_blocks, S, T, P<PairRec>(ctx->pairs), P<WorkRec>(ctx->work),
-                   ctx->cap_work, p->d, P<Cand>(ctx->cand), P<double>(ctx->hard_geo), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
+                   ctx->cap_work, P<double>(ctx->patch_box), p->d, P<Cand>(ctx->cand), P<double>(ctx->hard_geo), ctx->cap_cand, emit ? P<Cand>(ctx->cand_list) : nullptr,
                    emit ? ctx->cap_list : 0, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[4], st);
   // ---- K3 + K4 root search, volumes and gradients
