@@ -351,19 +351,41 @@ __global__ void k_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const i
   }
 }
 
+constexpr int kBucketRegs = 16;
+
 __global__ void k_bucket_sort_emit(DevScene S, const int *ves_scene, const int64_t *off_a, uint64_t *sorted,
                                    int n_ves, PairRec *pairs, int32_t *pair_ab, int32_t *pair_shift,
                                    int64_t cap_pairs) {
   for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_ves; a += gridDim.x * blockDim.x) {
     const int64_t p0 = off_a[a], p1 = off_a[a + 1];
-    for (int64_t i = p0 + 1; i < p1; ++i) {  // insertion sort (buckets hold a handful of pairs)
-      uint64_t k = sorted[i];
-      int64_t j = i - 1;
-      while (j >= p0 && sorted[j] > k) {
-        sorted[j + 1] = sorted[j];
-        --j;
+    if (p1 - p0 <= kBucketRegs) {
+      // the usual case (a handful of pairs): all loads at once, an odd-even
+      // transposition network in registers, one store per pair (keys are
+      // distinct and below the ~0 padding)
+      uint64_t v[kBucketRegs];
+#pragma unroll
+      for (int k = 0; k < kBucketRegs; ++k) v[k] = p0 + k < p1 ? sorted[p0 + k] : ~0ull;
+#pragma unroll
+      for (int r = 0; r < kBucketRegs; ++r)
+#pragma unroll
+        for (int k = r & 1; k + 1 < kBucketRegs; k += 2) {
+          const uint64_t x = v[k], y = v[k + 1];
+          v[k] = x < y ? x : y;
+          v[k + 1] = x < y ? y : x;
+        }
+#pragma unroll
+      for (int k = 0; k < kBucketRegs; ++k)
+        if (p0 + k < p1) sorted[p0 + k] = v[k];
+    } else {
+      for (int64_t i = p0 + 1; i < p1; ++i) {  // insertion sort in place
+        uint64_t k = sorted[i];
+        int64_t j = i - 1;
+        while (j >= p0 && sorted[j] > k) {
+          sorted[j + 1] = sorted[j];
+          --j;
+        }
+        sorted[j + 1] = k;
       }
-      sorted[j + 1] = k;
     }
     const double *L = S.box_len + 3 * ves_scene[a];
     for (int64_t i = p0; i < p1; ++i) {

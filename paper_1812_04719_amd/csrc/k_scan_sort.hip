@@ -99,10 +99,14 @@ __device__ inline int64_t rs_count(const unsigned long long *n_dev, int64_t n_ho
 }
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, const unsigned long long *n_dev,
-                                                        int64_t n_host, int shift, int32_t *hist, int nblk) {
+                                                        int64_t n_host, int shift, int32_t *hist, int nblk,
+                                                        bool full_only) {
   __shared__ int h[256];
   const int64_t n = rs_count(n_dev, n_host);
   const int t = threadIdx.x, b = blockIdx.x;
+  // with full_only, tiles past the count are never read (k_rs_pass stops at the
+  // last tile that holds keys); the multi-launch scan reads every tile
+  if (full_only && (int64_t)b * kRsTile >= n) return;
   h[t] = 0;
   __syncthreads();
   const int64_t e0 = (int64_t)b * kRsTile;
@@ -185,11 +189,15 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint64_t *sk, cons
   __shared__ int64_t sh[kRsWaves];
   const int64_t n = rs_count(n_dev, n_host);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, b = blockIdx.x;
+  // tiles that hold keys (the grid is sized for the capacity, the count is
+  // read on the device); the others have nothing to place
+  const int nfull = (int)((n + kRsTile - 1) / kRsTile);
+  if (b >= nfull) return;
   {
     // thread t: digit t
     int64_t tot = 0, before = 0;
     const int32_t *row = hin + (int64_t)t * nblk;
-    for (int bb = 0; bb < nblk; ++bb) {
+    for (int bb = 0; bb < nfull; ++bb) {
       const int c = row[bb];
       tot += c;
       before += bb < b ? c : 0;
@@ -411,7 +419,7 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
   uint32_t *sv = vals, *dv = tv;
   int passes = 0;
   for (int shift = 0; shift < key_bits; shift += 8, ++passes) {
-    k_rs_hist<<<nblk, kRsThreads, 0, st>>>(sk, n_dev, n_host, shift, hist, nblk);
+    k_rs_hist<<<nblk, kRsThreads, 0, st>>>(sk, n_dev, n_host, shift, hist, nblk, nblk <= kRsFusedMaxBlocks);
     if (nblk <= kRsFusedMaxBlocks) {
       k_rs_pass<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hist, nblk);
     } else {
