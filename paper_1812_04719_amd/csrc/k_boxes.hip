@@ -35,10 +35,12 @@ __device__ inline double okey_inv(unsigned long long k) {
 
 // One workgroup per vesicle: each thread streams vertices (coalesced SoA
 // loads of X0 and X1), folds them into the vesicle box and, through the
-// vertex -> patch incidence lists, into the LDS boxes of the patches that
-// reference the vertex.
+// vertex -> patch incidence (packed four to a vertex), into the LDS boxes of
+// the patches that reference the vertex.
 // MAXP bounds the patches of any vesicle's topology (LDS is sized for it, so
 // small meshes keep more workgroups resident).
+constexpr int kBoxU = 4;
+
 template <int MAXP>
 __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, const int64_t *ves_patch_off,
                                                double *ves_box, double *patch_box, Counters *cnt) {
@@ -60,21 +62,56 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
     double lo[3], hi[3];
     for (int c = 0; c < 3; ++c) { lo[c] = INFINITY; hi[c] = -INFINITY; }
     int bad = 0;
-    for (int i = threadIdx.x; i < nvv; i += blockDim.x) {
-      double l[3], u[3];
-      for (int c = 0; c < 3; ++c) {
-        const double a = S.x0[c * nv_all + base + i], b = S.x1[c * nv_all + base + i];
-        bad |= !(isfinite(a) && isfinite(b));
-        l[c] = fmin(a, b);
-        u[c] = fmax(a, b);
-        lo[c] = fmin(lo[c], l[c]);
-        hi[c] = fmax(hi[c], u[c]);
-      }
-      for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) {
-        const int q = T.vp[e];
+    // kBoxU vertices per thread at a time: every load of the batch (positions
+    // and the packed patch list) is issued before any of them is used, so a
+    // workgroup waits for memory once per batch, not twice per vertex
+    for (int i0 = threadIdx.x; i0 < nvv; i0 += kBoxU * blockDim.x) {
+      double x0[kBoxU][3], x1[kBoxU][3];
+      int4 q4[kBoxU];
+#pragma unroll
+      for (int k = 0; k < kBoxU; ++k) {
+        const int i = i0 + k * blockDim.x;
+        const bool in = i < nvv;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          atomicMin(&pk[q][c], okey(l[c]));
-          atomicMax(&pk[q][3 + c], okey(u[c]));
+          x0[k][c] = in ? S.x0[c * nv_all + base + i] : 0.0;
+          x1[k][c] = in ? S.x1[c * nv_all + base + i] : 0.0;
+        }
+        q4[k] = in ? T.vp4[vb + i] : make_int4(-1, -1, -1, -1);
+      }
+#pragma unroll
+      for (int k = 0; k < kBoxU; ++k) {
+        const int i = i0 + k * blockDim.x;
+        if (i >= nvv) break;
+        double l[3], u[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double a = x0[k][c], b = x1[k][c];
+          bad |= !(isfinite(a) && isfinite(b));
+          l[c] = fmin(a, b);
+          u[c] = fmax(a, b);
+          lo[c] = fmin(lo[c], l[c]);
+          hi[c] = fmax(hi[c], u[c]);
+        }
+        const int qs[4] = {q4[k].x, q4[k].y, q4[k].z, q4[k].w};
+        if (qs[3] == -2) {  // more than four patches: the full list
+          for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) {
+            const int q = T.vp[e];
+            for (int c = 0; c < 3; ++c) {
+              atomicMin(&pk[q][c], okey(l[c]));
+              atomicMax(&pk[q][3 + c], okey(u[c]));
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int q = qs[j];
+            if (q < 0) break;
+            for (int c = 0; c < 3; ++c) {
+              atomicMin(&pk[q][c], okey(l[c]));
+              atomicMax(&pk[q][3 + c], okey(u[c]));
+            }
+          }
         }
       }
     }

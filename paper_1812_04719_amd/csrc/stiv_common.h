@@ -79,6 +79,8 @@ struct DevTopo {
   const int *pref_off, *pref;          // referenced vertices (local ids)
   const int *vbase;                    // [n_topo] first row of each topology in vp_off
   const int *vp_off, *vp;              // vertex -> patches (local patch index) referencing it
+  const int4 *vp4;                     // [rows] the same, up to 4 per vertex, -1 padded; .w == -2:
+                                       // more than 4, read vp_off / vp
   const int *blob;                     // [n_ptab][blob_stride] patch blobs (BlobLayout of the current tile)
   int blob_stride;
 };

@@ -56,7 +56,7 @@ struct stiv_ctx {
   // topology (device)
   Buf t_nv, t_nt, t_ne, t_tri_off, t_edge_off, t_tri, t_edge, t_patch_off, t_ptri_off, t_ptri, t_ptri_slot,
       t_pvtx_off, t_pvtx, t_pvtx_slot, t_pedge_off, t_pedge, t_pedge_slot, t_pref_off, t_pref, t_vbase, t_vp_off,
-      t_vp, t_blob;
+      t_vp, t_vp4, t_blob;
   DevTopo topo{};
   std::vector<int> h_npatch;  // patches per topology
   int max_patches = 0;
@@ -148,8 +148,8 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
   Buf *all[] = {&ctx->t_nv, &ctx->t_nt, &ctx->t_ne, &ctx->t_tri_off, &ctx->t_edge_off, &ctx->t_tri, &ctx->t_edge,
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
-                &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->t_blob,
-                &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->scan_tmp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->t_vp4,
+                &ctx->t_blob, &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->scan_tmp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
                 &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
@@ -189,7 +189,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   std::vector<int> patch_off(1, 0), ptri_off(1, 0), ptri, pvtx_off(1, 0), pvtx, pedge_off(1, 0), pedge,
       pref_off(1, 0), pref;
   std::vector<uint8_t> ptri_slot, pvtx_slot, pedge_slot;
-  std::vector<int> vbase, vp_off(1, 0), vp;
+  std::vector<int> vbase, vp_off(1, 0), vp, vp4;
   ctx->h_npatch.assign(nt_topo, 0);
   ctx->max_patches = 0;
   for (int t = 0; t < nt_topo; ++t) {
@@ -281,6 +281,8 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
         vpl[v].erase(std::unique(vpl[v].begin(), vpl[v].end()), vpl[v].end());
         for (int q : vpl[v]) vp.push_back(q);
         vp_off.push_back((int)vp.size());
+        const int nq = (int)vpl[v].size();
+        for (int k = 0; k < 4; ++k) vp4.push_back(nq > 4 ? (k < 3 ? vpl[v][k] : -2) : (k < nq ? vpl[v][k] : -1));
       }
     }
     std::vector<char> vown(NV, 0), eown(NE, 0);
@@ -384,6 +386,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   HIPCHK(upload(ctx->t_vbase, vbase));
   HIPCHK(upload(ctx->t_vp_off, vp_off));
   HIPCHK(upload(ctx->t_vp, vp));
+  HIPCHK(upload(ctx->t_vp4, vp4));
   DevTopo &D = ctx->topo;
   D.n_topo = nt_topo;
   D.nv = P<int>(ctx->t_nv); D.nt = P<int>(ctx->t_nt); D.ne = P<int>(ctx->t_ne);
@@ -396,6 +399,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   D.pedge_slot = P<uint8_t>(ctx->t_pedge_slot);
   D.pref_off = P<int>(ctx->t_pref_off); D.pref = P<int>(ctx->t_pref);
   D.vbase = P<int>(ctx->t_vbase); D.vp_off = P<int>(ctx->t_vp_off); D.vp = P<int>(ctx->t_vp);
+  D.vp4 = P<int4>(ctx->t_vp4);
   D.blob = P<int>(ctx->t_blob);
   D.blob_stride = bs;
   ctx->have_topo = true;
