@@ -38,12 +38,17 @@ __global__ void k_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt
 }
 
 // Ascending bitonic sort of (key, idx) pairs in place; n_pow2 >= n is a power of
-// two and entries [n, n_pow2) are padded by the caller with key = ~0.
-__device__ void bitonic(uint64_t *key, int32_t *idx, int n_pow2) {
+// two and entries [n, n_pow2) are padded by the caller with key = ~0.  Inlined
+// at each call, so that a call on the LDS arrays compiles to LDS accesses (a
+// pointer that may be either LDS or global memory makes every access a
+// generic one); GLOBAL adds the fence that the global-memory slices need.
+template <bool GLOBAL>
+__device__ __forceinline__ void bitonic(uint64_t *key, int32_t *idx, int n_pow2) {
   for (int size = 2; size <= n_pow2; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = threadIdx.x; t < (n_pow2 >> 1); t += blockDim.x) {
-        const int i = 2 * stride * (t / stride) + (t % stride);
+        // i = 2 * stride * (t / stride) + t % stride, stride a power of two
+        const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
         const int j = i + stride;
         const bool asc = (i & size) == 0;
         const uint64_t ki = key[i], kj = key[j];
@@ -55,7 +60,7 @@ __device__ void bitonic(uint64_t *key, int32_t *idx, int n_pow2) {
           idx[j] = x;
         }
       }
-      __threadfence_block();
+      if (GLOBAL) __threadfence_block();
       __syncthreads();
     }
   }
@@ -105,7 +110,10 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
     }
     __threadfence_block();
     __syncthreads();
-    bitonic(key, idx, n2);
+    if (n2 <= kLdsSort)
+      bitonic<false>(skey, sidx, n2);
+    else
+      bitonic<true>(key, idx, n2);
     if (threadIdx.x == 0) s_nvt = 0;
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -183,7 +191,10 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
     }
     __threadfence_block();
     __syncthreads();
-    bitonic(jkey, jidx, nj2);
+    if (jkey == skey)
+      bitonic<false>(skey, sidx, nj2);
+    else
+      bitonic<true>(jkey, jidx, nj2);
     // segments of equal vertex: each thread owns a contiguous chunk of entries,
     // counts the segment starts in it, and after a scan of those counts writes
     // the rows that start in its chunk (adding the segment in entry order)
