@@ -19,21 +19,48 @@ namespace {
 constexpr int kAggThreads = 256;
 constexpr int kLdsSort = 2048;
 
+// Adds each lane's 1 to ctr[key] with one atomic per distinct key of the
+// wavefront (contacts of a wavefront mostly share a pair, and one atomic per
+// contact on the same counter serialized); returns the lane's old value
+// (its position among the lanes of its key in lane order, after the value the
+// counter had).  Lanes with key < 0 take no part.
+__device__ inline int wave_grouped_add(int32_t *ctr, int key) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  unsigned long long todo = __ballot(key >= 0);
+  int mine = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int k0 = __shfl(key, leader, 64);
+    const unsigned long long grp = __ballot(key == k0) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[k0], __popcll(grp));
+    base = __shfl(base, leader, 64);
+    if ((grp >> lane) & 1ull) mine = base + __popcll(grp & lt);
+    todo &= ~grp;
+  }
+  return mine;
+}
+
 __global__ void k_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt) {
   int64_t n = (int64_t)cnt->n_ct;
   n = n < ct_cap ? n : ct_cap;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&pair_cnt[ct[i].pair], 1);
+  // whole wavefronts run every iteration (the grouped add is a wavefront operation)
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    (void)wave_grouped_add(pair_cnt, i < n ? ct[i].pair : -1);
+  }
 }
 
 __global__ void k_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
                              int32_t *cursor, int32_t *perm) {
   int64_t n = (int64_t)cnt->n_ct;
   n = n < ct_cap ? n : ct_cap;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int p = ct[i].pair;
-    const int pos = atomicAdd(&cursor[p], 1);
-    perm[pair_off[p] + pos] = (int32_t)i;
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const int p = i < n ? ct[i].pair : -1;
+    const int pos = wave_grouped_add(cursor, p);
+    if (p >= 0) perm[pair_off[p] + pos] = (int32_t)i;
   }
 }
 
