@@ -32,6 +32,18 @@ __device__ inline unsigned long long lanemask_lt() {
 constexpr int kPPThreads = 256;
 constexpr int kPPBuf = 512;
 
+// Slot for each lane with take set in an LDS list whose length is *n: one
+// atomic per wavefront, lanes in lane order.  Every lane of the wavefront
+// must call it.
+__device__ inline int wave_slot(int *n, bool take) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long m = __ballot(take);
+  int base = 0;
+  if (m && lane == __ffsll((long long)m) - 1) base = atomicAdd(n, __popcll(m));
+  base = __shfl(base, __ffsll((long long)(m ? m : 1ull)) - 1, 64);
+  return base + __popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
+}
+
 // Closed-interval overlap of two FP32 boxes (lo x, y, z, hi x, y, z) held in
 // LDS at 8-byte aligned addresses: both boxes are read with three 8-byte
 // loads each and the six compares are combined without branches (a
@@ -79,10 +91,17 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
     const int na = (int)(ves_patch_off[pr.a + 1] - pa0), nb = (int)(ves_patch_off[pr.b + 1] - pb0);
     if (threadIdx.x == 0) { nA = 0; nB = 0; }
     __syncthreads();
-    for (int k = threadIdx.x; k < na; k += blockDim.x) {
-      const double *P = patch_box + 6 * (pa0 + k);
-      if (ov6(P, boxB)) {
-        const int q = atomicAdd(&nA, 1);
+    // compaction: a ballot per wavefront and one LDS atomic for its survivors
+    for (int k0 = 0; k0 < na; k0 += blockDim.x) {
+      const int k = k0 + threadIdx.x;
+      double P[6];
+      bool keep = false;
+      if (k < na) {
+        for (int c = 0; c < 6; ++c) P[c] = patch_box[6 * (pa0 + k) + c];
+        keep = ov6(P, boxB);
+      }
+      const int q = wave_slot(&nA, keep);
+      if (keep) {
         for (int c = 0; c < 3; ++c) {
           bA[q][c] = __double2float_rd(P[c]);
           bA[q][3 + c] = __double2float_ru(P[3 + c]);
@@ -90,12 +109,19 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
         iA[q] = (short)k;
       }
     }
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-      const double *P = patch_box + 6 * (pb0 + k);
+    for (int k0 = 0; k0 < nb; k0 += blockDim.x) {
+      const int k = k0 + threadIdx.x;
       double Q[6];
-      for (int c = 0; c < 3; ++c) { Q[c] = P[c] + pr.sh[c]; Q[3 + c] = P[3 + c] + pr.sh[c]; }
-      if (ov6(Q, boxA)) {
-        const int q = atomicAdd(&nB, 1);
+      bool keep = false;
+      if (k < nb) {
+        for (int c = 0; c < 3; ++c) {
+          Q[c] = patch_box[6 * (pb0 + k) + c] + pr.sh[c];
+          Q[3 + c] = patch_box[6 * (pb0 + k) + 3 + c] + pr.sh[c];
+        }
+        keep = ov6(Q, boxA);
+      }
+      const int q = wave_slot(&nB, keep);
+      if (keep) {
         for (int c = 0; c < 3; ++c) {
           bB[q][c] = __double2float_rd(Q[c]);
           bB[q][3 + c] = __double2float_ru(Q[3 + c]);
@@ -108,10 +134,11 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
     const int tot = ma * mb;
     for (int t0 = 0; t0 < tot; t0 += blockDim.x) {
       const int t = t0 + threadIdx.x;
-      if (t < tot) {
-        const int x = t / mb, y = t - x * mb;
-        if (ov6f_lds(bA[x], bB[y])) {
-          const int q = atomicAdd(&nbuf, 1);
+      const int x = t < tot ? t / mb : 0, y = t < tot ? t - x * mb : 0;
+      const bool hit = t < tot && ov6f_lds(bA[x], bB[y]);
+      const int q = wave_slot(&nbuf, hit);
+      {
+        if (hit) {
           WorkRec w;
           w.p = (int)p;
           w.pa = ptA + iA[x];

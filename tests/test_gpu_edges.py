@@ -84,3 +84,49 @@ def test_periodic_box_too_small(ctx):
     with pytest.raises(stiv.StivError) as e:
         stiv.detect(ctx, stiv.DeviceScene(small), small.d, small.eps, small.dt)
     assert e.value.status == stiv.STIV_E_ARG
+
+
+def _hub_scene(n_sat=20, p=16, r_sat=0.3, gap=0.01, step=0.03, seed=5):
+    """Vesicle 0 (unit sphere) with n_sat small spheres around it, each moving
+    toward it: every pair (0, k) is a vesicle pair, so the pair list of
+    vesicle 0 is longer than the in-register sort of a pair bucket holds."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(seed)
+    unit = S.spheroid_body_points(p, 1.0, 1.0)
+    rots = Rotation.random(n_sat + 1, random_state=rng).as_matrix()
+    k = np.arange(n_sat) + 0.5
+    polar = np.arccos(1.0 - 2.0 * k / n_sat)
+    azim = np.pi * (1.0 + 5.0 ** 0.5) * k
+    dirs = np.stack([np.sin(polar) * np.cos(azim), np.sin(polar) * np.sin(azim), np.cos(polar)], axis=1)
+    s0 = [unit @ rots[0].T]
+    s1 = [s0[0].copy()]
+    for i in range(n_sat):
+        c = dirs[i] * (1.0 + r_sat + gap)
+        pts = r_sat * (unit @ rots[i + 1].T) + c
+        s0.append(pts)
+        s1.append(pts - step * dirs[i])
+    return S._assemble(s0, s1, [p] * (n_sat + 1), [0.0, 0.0, 0.0],
+                       meta={"config": "hub", "n_sat": n_sat, "seed": seed})
+
+
+def test_vesicle_with_many_pairs(ctx):
+    """More than 16 pairs share their first vesicle: the pair bucket is sorted
+    by the general path instead of in registers."""
+    sc = _hub_scene()
+    g, o = _check(ctx, sc)
+    first = np.asarray(g["pair_ab"])[: g["n_pairs"], 0]
+    assert np.count_nonzero(first == 0) > 16
+    assert g["n_ct_vt"] > 0 and g["n_vol"] >= 17
+
+
+def test_vertex_in_many_patches(ctx):
+    """Order-48 grids tiled into 16-triangle patches: each pole vertex lies in
+    all 96 triangles of its fan, so in at least 6 patches (more than the four
+    packed per vertex in the box kernel's incidence table)."""
+    ctx.set_patch_size(16)
+    try:
+        sc = S.make_two_spheres(seed=7, p=48)
+        g, o = _check(ctx, sc, emit=False)
+        assert g["n_ct"] > 0
+    finally:
+        ctx.set_patch_size(64)
