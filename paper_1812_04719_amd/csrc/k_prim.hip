@@ -412,15 +412,18 @@ __device__ inline int load_workrec(const WorkRec *work, int64_t w, int64_t nw, i
   return (w < nw && lane < 8) ? reinterpret_cast<const int *>(work + w)[lane] : 0;
 }
 
-// Blobs, referenced ids, patch boxes and shift of a work item whose record is in wr.
+// Blobs, referenced ids, patch boxes and shift of a work item whose record is
+// in wr.  With keep0 (wave-uniform: the item has the same pair and first patch
+// as the one before it) the first patch's registers are left as they are.
 template <int TILE>
 __device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const PairRec *pairs, const double *patch_box,
-                                  int wr, int lane) {
+                                  int wr, int lane, bool keep0) {
   using Lay = BlobLayout<TILE>;
   const int p = __builtin_amdgcn_readlane(wr, 0);
   const int P[2] = {__builtin_amdgcn_readlane(wr, 1), __builtin_amdgcn_readlane(wr, 2)};
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
+    if (side == 0 && keep0) continue;
     const int *gb = T.blob + (int64_t)P[side] * Lay::stride;
     F.blob[side] = lane < Lay::lds / 4 ? reinterpret_cast<const int4 *>(gb)[lane] : int4{0, 0, 0, 0};
     // unused entries of the referenced list are 0: a valid vertex of the vesicle
@@ -428,17 +431,18 @@ __device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const Pai
   }
   F.sh = lane < 3 ? pairs[p].sh[lane] : 0.0;
   const int box[2] = {__builtin_amdgcn_readlane(wr, 5), __builtin_amdgcn_readlane(wr, 6)};
-  F.pbox = lane < 12 ? patch_box[6 * (int64_t)box[lane >= 6] + lane % 6] : 0.0;
+  if (lane < 12 && !(keep0 && lane < 6)) F.pbox = patch_box[6 * (int64_t)box[lane >= 6] + lane % 6];
 }
 
 // Positions of the referenced vertices (every lane below the list capacity
 // loads one vertex; lanes past the patch's count load vertex 0 of the vesicle).
 template <int TILE>
-__device__ inline void load_positions(Prefetch<TILE> &F, const DevScene &S, int wr, int lane) {
+__device__ inline void load_positions(Prefetch<TILE> &F, const DevScene &S, int wr, int lane, bool keep0) {
   using Lay = BlobLayout<TILE>;
   const int base[2] = {__builtin_amdgcn_readlane(wr, 3), __builtin_amdgcn_readlane(wr, 4)};
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
+    if (side == 0 && keep0) continue;
     if (lane < Lay::ref) {
       const int64_t g = base[side] + F.ref[side];
 #pragma unroll
@@ -473,15 +477,20 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
   int wr_cur = load_workrec(work, w, nw, lane);
   int wr_next = load_workrec(work, w_next, nw, lane);
   if (w < nw) {
-    load_blobs<TILE>(F, T, pairs, patch_box, wr_cur, lane);
-    load_positions<TILE>(F, S, wr_cur, lane);
+    load_blobs<TILE>(F, T, pairs, patch_box, wr_cur, lane, false);
+    load_positions<TILE>(F, S, wr_cur, lane, false);
   }
+  // the current item has the pair and first patch of the previous one: that
+  // patch's blob, positions and vertex boxes are still in LDS (consecutive
+  // items of a pair come in the order of the first patch)
+  bool same0 = false;
   while (w < nw) {
     // the current item: registers -> LDS
     const int p = __builtin_amdgcn_readlane(wr_cur, 0);
     const int P[2] = {__builtin_amdgcn_readlane(wr_cur, 1), __builtin_amdgcn_readlane(wr_cur, 2)};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      if (side == 0 && same0) continue;
       if (lane < Lay::lds / 4) reinterpret_cast<int4 *>(&W.blob[side][0])[lane] = F.blob[side];
       if (lane < Lay::ref)
 #pragma unroll
@@ -492,6 +501,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     // FP32 boxes of the referenced vertices, rounded outward, into LDS
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      if (side == 0 && same0) continue;
       const int nref = W.blob[side][Lay::hdr + 0];
       if (lane < nref) {
 #pragma unroll
@@ -524,13 +534,15 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     // the next item's blobs and the record of the one after it (the loads
     // complete while this item is swept)
     const bool more = w_next < nw;
-    if (more) load_blobs<TILE>(F, T, pairs, patch_box, wr_next, lane);
+    const bool same0_next =
+        more && __builtin_amdgcn_readlane(wr_next, 0) == p && __builtin_amdgcn_readlane(wr_next, 1) == P[0];
+    if (more) load_blobs<TILE>(F, T, pairs, patch_box, wr_next, lane, same0_next);
     const int w_after = next_item(w_next, Q, cnt, first_dynamic, lane);
     const int wr_after = load_workrec(work, w_after, nw, lane);
     __syncthreads();
     int nh = 0;  // buffered hits (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
-      if (kind == 1 && more) load_positions<TILE>(F, S, wr_next, lane);
+      if (kind == 1 && more) load_positions<TILE>(F, S, wr_next, lane, same0_next);
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
       const int lcount = kind == 2 ? W.blob[sl][Lay::hdr + 3] : W.blob[sl][Lay::hdr + 1];
       const int rcount = kind == 2 ? W.blob[sr][Lay::hdr + 3] : W.blob[sr][Lay::hdr + 2];
@@ -615,6 +627,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     w_next = w_after;
     wr_cur = wr_next;
     wr_next = wr_after;
+    same0 = same0_next;
   }
   for (int off = 32; off > 0; off >>= 1) {
     nvt += __shfl_xor(nvt, off, 64);
