@@ -33,6 +33,21 @@ __device__ inline double okey_inv(unsigned long long k) {
   return __longlong_as_double((long long)b);
 }
 
+// Folds vertex bounds (keys) into a patch's LDS box.  The box only shrinks
+// toward its final value, so a vertex that does not beat the value read now
+// cannot beat the final one: its atomic is skipped (most vertices of a patch
+// are not extreme, and neighbouring lanes often hit the same patch).
+__device__ inline void fold_box(unsigned long long (*pk)[6], int q, const unsigned long long kl[3],
+                                const unsigned long long ku[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const unsigned long long lo = __hip_atomic_load(&pk[q][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const unsigned long long hi = __hip_atomic_load(&pk[q][3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (kl[c] < lo) atomicMin(&pk[q][c], kl[c]);
+    if (ku[c] > hi) atomicMax(&pk[q][3 + c], ku[c]);
+  }
+}
+
 // One workgroup per vesicle: each thread streams vertices (coalesced SoA
 // loads of X0 and X1), folds them into the vesicle box and, through the
 // vertex -> patch incidence (packed four to a vertex), into the LDS boxes of
@@ -93,24 +108,16 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
           lo[c] = fmin(lo[c], l[c]);
           hi[c] = fmax(hi[c], u[c]);
         }
+        const unsigned long long kl[3] = {okey(l[0]), okey(l[1]), okey(l[2])};
+        const unsigned long long ku[3] = {okey(u[0]), okey(u[1]), okey(u[2])};
         const int qs[4] = {q4[k].x, q4[k].y, q4[k].z, q4[k].w};
         if (qs[3] == -2) {  // more than four patches: the full list
-          for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) {
-            const int q = T.vp[e];
-            for (int c = 0; c < 3; ++c) {
-              atomicMin(&pk[q][c], okey(l[c]));
-              atomicMax(&pk[q][3 + c], okey(u[c]));
-            }
-          }
+          for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) fold_box(pk, T.vp[e], kl, ku);
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int q = qs[j];
-            if (q < 0) break;
-            for (int c = 0; c < 3; ++c) {
-              atomicMin(&pk[q][c], okey(l[c]));
-              atomicMax(&pk[q][3 + c], okey(u[c]));
-            }
+            if (qs[j] < 0) break;
+            fold_box(pk, qs[j], kl, ku);
           }
         }
       }
