@@ -183,13 +183,17 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 //    software-pipelined across the work items of a wavefront: the record of
 //    the item after next, the blobs of the next item and then its positions
 //    are loaded into registers while the current item is swept, and only
-//    written to LDS once the current item is finished.
+//    written to LDS once the current item is finished.  A pair's items come
+//    in the order of their first patch; an item with the pair and first
+//    patch of the one before it loads and writes only its second patch.
+//    The FP32 box of each whole patch comes from the box kernel's FP64 patch
+//    box, rounded outward like the vertex boxes.
 // 2. Per kind, build the left list (owned vertices, or owned edges; 64 at a
 //    time) and the right list (triangles, or owned edges) of primitives whose
 //    FP32 boxes meet the other patch's box; the FP32 boxes enclose the FP64
 //    ones, so the filter keeps a superset.
-// 3. All left x right pairs of the lists, 64 per round, FP32 box test; hits
-//    are buffered in LDS.
+// 3. All left x right pairs of the lists, 64 per round (two rounds' loads
+//    issued together), FP32 box test; hits are buffered in LDS.
 // 4. Buffered hits are processed 64 at a time with all lanes busy: the exact
 //    FP64 box test (the candidate definition), then the screens: candidates
 //    whose polynomial can have a root on [0,1] and whose closest-point test
