@@ -650,8 +650,11 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
                         WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt, hipStream_t st) {
+  // grids measured on the 1440-vesicle scene (order-32 meshes): 1024
+  // workgroups, each taking several pairs into its work-item buffer before a
+  // flush, 0.045 ms; 2048: 0.054; 4096: 0.067; 512: 0.062
   if (max_patches <= 128)
-    k_patch_pairs<128><<<4096, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
+    k_patch_pairs<128><<<1024, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
                                                     cnt, pairs_cap);
   else if (max_patches <= 512)
     k_patch_pairs<512><<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
