@@ -88,7 +88,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const TIn *in, int64
 // its tile -- matched across the wavefront by ballots on the 8 digit bits,
 // carried across rounds and wavefronts in LDS -- gives its output position.
 // Up to kRsFusedMaxBlocks tiles, (2) and (3) are one launch (k_rs_pass: each
-// workgroup sums the histogram itself), so a pass costs two launches.
+// workgroup sums the histogram itself), so a pass costs two launches; there,
+// a pass whose digit is the same for every key moves nothing.  Which of the
+// two buffers holds a pass's input is kept on the device (the key count is
+// read there too), and a last launch copies the result to buffer 0 if needed.
 // Equal keys keep their input order (stable), as Alg. 1 requires.
 // --------------------------------------------------------------------------
 constexpr int kRsThreads = 256, kRsItems = 8, kRsTile = kRsThreads * kRsItems, kRsWaves = kRsThreads / 64;
@@ -98,10 +101,19 @@ __device__ inline int64_t rs_count(const unsigned long long *n_dev, int64_t n_ho
   return n_dev ? ((int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host) : n_host;
 }
 
-__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, const unsigned long long *n_dev,
-                                                        int64_t n_host, int shift, int32_t *hist, int nblk,
-                                                        bool full_only) {
+// The two key / value buffers of the sort; which one holds the input of pass p
+// is par[p] (device memory, written by the pass before; pass 0 reads buffer 0).
+struct RsBufs {
+  uint64_t *k[2];
+  uint32_t *v[2];
+};
+__device__ inline int rs_cur(const int64_t *par, int p) { return p > 0 ? (int)par[p] : 0; }
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(RsBufs B, const int64_t *par, int p,
+                                                        const unsigned long long *n_dev, int64_t n_host, int shift,
+                                                        int32_t *hist, int nblk, bool full_only) {
   __shared__ int h[256];
+  const uint64_t *keys = B.k[rs_cur(par, p)];
   const int64_t n = rs_count(n_dev, n_host);
   const int t = threadIdx.x, b = blockIdx.x;
   // with full_only, tiles past the count are never read (k_rs_pass stops at the
@@ -118,13 +130,19 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, co
   hist[(int64_t)t * nblk + b] = h[t];
 }
 
-__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *sk, const uint32_t *sv, uint64_t *dk,
-                                                           uint32_t *dv, const unsigned long long *n_dev,
-                                                           int64_t n_host, int shift, const int64_t *hoff, int nblk) {
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(RsBufs B, int64_t *par, int p,
+                                                           const unsigned long long *n_dev, int64_t n_host, int shift,
+                                                           const int64_t *hoff, int nblk) {
   __shared__ int wcnt[kRsWaves][256];
   __shared__ int woff[kRsWaves][256];
   const int64_t n = rs_count(n_dev, n_host);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, b = blockIdx.x;
+  const int cur = rs_cur(par, p);
+  const uint64_t *sk = B.k[cur];
+  const uint32_t *sv = B.v[cur];
+  uint64_t *dk = B.k[cur ^ 1];
+  uint32_t *dv = B.v[cur ^ 1];
+  if (b == 0 && t == 0) par[p + 1] = cur ^ 1;
   for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -180,19 +198,31 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *sk, c
 // before), then ranks and scatters its keys as k_rs_scatter does.  This
 // replaces the scan launches between the histogram and the scatter.
 constexpr int kRsFusedMaxBlocks = 256;
-__global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint64_t *sk, const uint32_t *sv, uint64_t *dk,
-                                                        uint32_t *dv, const unsigned long long *n_dev,
-                                                        int64_t n_host, int shift, const int32_t *hin, int nblk) {
+__global__ __launch_bounds__(kRsThreads) void k_rs_pass(RsBufs B, int64_t *par, int p,
+                                                        const unsigned long long *n_dev, int64_t n_host, int shift,
+                                                        const int32_t *hin, int nblk) {
   __shared__ int wcnt[kRsWaves][256];
   __shared__ int woff[kRsWaves][256];
   __shared__ int64_t dbase[256];
   __shared__ int64_t sh[kRsWaves];
+  __shared__ int s_const;
   const int64_t n = rs_count(n_dev, n_host);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, b = blockIdx.x;
+  const int cur = rs_cur(par, p);
+  const uint64_t *sk = B.k[cur];
+  const uint32_t *sv = B.v[cur];
+  uint64_t *dk = B.k[cur ^ 1];
+  uint32_t *dv = B.v[cur ^ 1];
+  if (n == 0) {
+    if (b == 0 && t == 0) par[p + 1] = cur;
+    return;
+  }
   // tiles that hold keys (the grid is sized for the capacity, the count is
   // read on the device); the others have nothing to place
   const int nfull = (int)((n + kRsTile - 1) / kRsTile);
   if (b >= nfull) return;
+  if (t == 0) s_const = 0;
+  __syncthreads();
   {
     // thread t: digit t
     int64_t tot = 0, before = 0;
@@ -202,9 +232,17 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint64_t *sk, cons
       tot += c;
       before += bb < b ? c : 0;
     }
+    if (tot == n) s_const = 1;  // every key has digit t
     const int64_t inc = block_inclusive_scan<int64_t, kRsThreads>(tot, sh);
     dbase[t] = inc - tot + before;
   }
+  __syncthreads();
+  // a digit shared by all keys leaves the order as it is (the sort is
+  // stable): nothing moves and the next pass reads the same buffer.  Keys
+  // of a few levels of the Morton grid leave their high digits constant.
+  const bool constant = s_const != 0;
+  if (b == 0 && t == 0) par[p + 1] = constant ? cur : cur ^ 1;
+  if (constant) return;
   for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -252,12 +290,13 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint64_t *sk, cons
   }
 }
 
-__global__ void k_rs_copy(const uint64_t *sk, const uint32_t *sv, uint64_t *dk, uint32_t *dv,
-                          const unsigned long long *n_dev, int64_t n_host) {
+// The sorted keys to buffer 0 when the last pass left them in buffer 1.
+__global__ void k_rs_copy(RsBufs B, const int64_t *par, int passes, const unsigned long long *n_dev, int64_t n_host) {
+  if (rs_cur(par, passes) == 0) return;
   const int64_t n = rs_count(n_dev, n_host);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    dk[i] = sk[i];
-    dv[i] = sv[i];
+    B.k[0][i] = B.k[1][i];
+    B.v[0][i] = B.v[1][i];
   }
 }
 
@@ -405,31 +444,32 @@ void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long
   scan_any<int32_t>(in, out, n_dev, n_host, tmp, st);
 }
 int64_t radix_scratch_blocks(int64_t n_host) { return (n_host + kRsTile - 1) / kRsTile; }
+constexpr int kRsMaxPasses = 8;  // 64-bit keys
 int64_t radix_offset_elems(int64_t n_host) {
   const int64_t h = 256 * radix_scratch_blocks(n_host);
-  return h + 1 + scan_scratch_elems(h);
+  return h + 1 + scan_scratch_elems(h) + kRsMaxPasses + 1;  // offsets, scan scratch, buffer parity
 }
 
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
                            int64_t *hoff, hipStream_t st) {
-  if (n_host <= 0) return;
+  if (n_host <= 0 || key_bits <= 0) return;
   const int nblk = (int)radix_scratch_blocks(n_host);
-  uint64_t *sk = keys, *dk = tk;
-  uint32_t *sv = vals, *dv = tv;
+  const int64_t h = (int64_t)256 * nblk;
+  int64_t *par = hoff + h + 1 + scan_scratch_elems(h);  // par[p]: buffer holding pass p's input
+  const RsBufs B = {{keys, tk}, {vals, tv}};
   int passes = 0;
-  for (int shift = 0; shift < key_bits; shift += 8, ++passes) {
-    k_rs_hist<<<nblk, kRsThreads, 0, st>>>(sk, n_dev, n_host, shift, hist, nblk, nblk <= kRsFusedMaxBlocks);
+  for (int shift = 0; shift < key_bits && passes < kRsMaxPasses; shift += 8, ++passes) {
+    k_rs_hist<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hist, nblk,
+                                           nblk <= kRsFusedMaxBlocks);
     if (nblk <= kRsFusedMaxBlocks) {
-      k_rs_pass<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hist, nblk);
+      k_rs_pass<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hist, nblk);
     } else {
-      scan_any<int32_t>(hist, hoff, nullptr, (int64_t)256 * nblk, hoff + (int64_t)256 * nblk + 1, st);
-      k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(sk, sv, dk, dv, n_dev, n_host, shift, hoff, nblk);
+      scan_any<int32_t>(hist, hoff, nullptr, h, hoff + h + 1, st);
+      k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hoff, nblk);
     }
-    uint64_t *xk = sk; sk = dk; dk = xk;
-    uint32_t *xv = sv; sv = dv; dv = xv;
   }
-  if (passes & 1) k_rs_copy<<<grid_for(n_host, 256), 256, 0, st>>>(sk, sv, keys, vals, n_dev, n_host);
+  k_rs_copy<<<grid_for(n_host, 256), 256, 0, st>>>(B, par, passes, n_dev, n_host);
 }
 void launch_fill_multi(const FillJobs &J, hipStream_t st) {
   int64_t nmax = 0;
