@@ -240,28 +240,31 @@ __global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *bo
   }
 }
 
+// kCpLanes threads per vesicle, each emitting every kCpLanes-th of its check
+// points (index (kx * n_y + ky) * n_z + kz, as one thread would in order).
+constexpr int kCpLanes = 8;
 __global__ void k_cp_emit(DevScene S, const double *box, const int *ves_scene, const SceneGrid *grid,
                           const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap) {
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
+  const int64_t nt = (int64_t)S.n_ves * kCpLanes;
+  for (int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gid < nt; gid += (int64_t)gridDim.x * blockDim.x) {
+    const int v = (int)(gid / kCpLanes), part = (int)(gid % kCpLanes);
     const int sc = ves_scene[v];
     const SceneGrid g = grid[sc];
     const double *B = box + 6 * (int64_t)v;
     int n[3];
     bool full[3];
     for (int c = 0; c < 3; ++c) n[c] = axis_points(g, c, B[c], B[3 + c], &full[c]);
-    int64_t o = cp_off[v];
-    for (int kx = 0; kx < n[0]; ++kx) {
-      uint32_t cx = axis_cell(g, 0, B[0], B[3], kx, n[0], full[0]);
-      for (int ky = 0; ky < n[1]; ++ky) {
-        uint32_t cy = axis_cell(g, 1, B[1], B[4], ky, n[1], full[1]);
-        for (int kz = 0; kz < n[2]; ++kz) {
-          uint32_t cz = axis_cell(g, 2, B[2], B[5], kz, n[2], full[2]);
-          if (o < cap) {
-            keys[o] = ((uint64_t)sc << 30) | morton3(cx, cy, cz);
-            vals[o] = (uint32_t)v;
-          }
-          ++o;
-        }
+    const int64_t o0 = cp_off[v];
+    const int total = n[0] * n[1] * n[2];
+    for (int idx = part; idx < total; idx += kCpLanes) {
+      const int kx = idx / (n[1] * n[2]), ky = (idx / n[2]) % n[1], kz = idx % n[2];
+      const uint32_t cx = axis_cell(g, 0, B[0], B[3], kx, n[0], full[0]);
+      const uint32_t cy = axis_cell(g, 1, B[1], B[4], ky, n[1], full[1]);
+      const uint32_t cz = axis_cell(g, 2, B[2], B[5], kz, n[2], full[2]);
+      const int64_t o = o0 + idx;
+      if (o < cap) {
+        keys[o] = ((uint64_t)sc << 30) | morton3(cx, cy, cz);
+        vals[o] = (uint32_t)v;
       }
     }
   }
@@ -449,7 +452,8 @@ void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid
 }
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
                     const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st) {
-  k_cp_emit<<<grid1d(S.n_ves, 64), 64, 0, st>>>(S, ves_box, ves_scene, grid, cp_off, keys, vals, cap);
+  k_cp_emit<<<grid1d((int64_t)S.n_ves * kCpLanes, 256, 4096), 256, 0, st>>>(S, ves_box, ves_scene, grid, cp_off,
+                                                                              keys, vals, cap);
 }
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
                        const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
