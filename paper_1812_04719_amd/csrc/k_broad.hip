@@ -381,15 +381,36 @@ __global__ void k_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const i
 
 constexpr int kBucketRegs = 16;
 
+// One canonical pair record from its key (a, b, shift digits).
+__device__ inline void emit_pair(uint64_t k, int64_t i, const double L[3], PairRec *pairs, int32_t *pair_ab,
+                                 int32_t *pair_shift, int64_t cap_pairs) {
+  PairRec r;
+  r.a = (int)(k >> 36);
+  r.b = (int)((k >> 12) & 0xffffffull);
+  r.s[0] = (int)((k >> 8) & 15u) - 8;
+  r.s[1] = (int)((k >> 4) & 15u) - 8;
+  r.s[2] = (int)(k & 15u) - 8;
+  r.pad = 0;
+  for (int c = 0; c < 3; ++c) r.sh[c] = (double)r.s[c] * L[c];
+  pairs[i] = r;
+  if (i < cap_pairs) {
+    pair_ab[2 * i] = r.a;
+    pair_ab[2 * i + 1] = r.b;
+    for (int c = 0; c < 3; ++c) pair_shift[3 * i + c] = r.s[c];
+  }
+}
+
 __global__ void k_bucket_sort_emit(DevScene S, const int *ves_scene, const int64_t *off_a, uint64_t *sorted,
                                    int n_ves, PairRec *pairs, int32_t *pair_ab, int32_t *pair_shift,
                                    int64_t cap_pairs) {
   for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_ves; a += gridDim.x * blockDim.x) {
     const int64_t p0 = off_a[a], p1 = off_a[a + 1];
+    const double *Lp = S.box_len + 3 * ves_scene[a];
+    const double L[3] = {Lp[0], Lp[1], Lp[2]};
     if (p1 - p0 <= kBucketRegs) {
       // the usual case (a handful of pairs): all loads at once, an odd-even
-      // transposition network in registers, one store per pair (keys are
-      // distinct and below the ~0 padding)
+      // transposition network in registers, the records written from there
+      // (keys are distinct and below the ~0 padding)
       uint64_t v[kBucketRegs];
 #pragma unroll
       for (int k = 0; k < kBucketRegs; ++k) v[k] = p0 + k < p1 ? sorted[p0 + k] : ~0ull;
@@ -403,7 +424,7 @@ __global__ void k_bucket_sort_emit(DevScene S, const int *ves_scene, const int64
         }
 #pragma unroll
       for (int k = 0; k < kBucketRegs; ++k)
-        if (p0 + k < p1) sorted[p0 + k] = v[k];
+        if (p0 + k < p1) emit_pair(v[k], p0 + k, L, pairs, pair_ab, pair_shift, cap_pairs);
     } else {
       for (int64_t i = p0 + 1; i < p1; ++i) {  // insertion sort in place
         uint64_t k = sorted[i];
@@ -414,24 +435,7 @@ __global__ void k_bucket_sort_emit(DevScene S, const int *ves_scene, const int64
         }
         sorted[j + 1] = k;
       }
-    }
-    const double *L = S.box_len + 3 * ves_scene[a];
-    for (int64_t i = p0; i < p1; ++i) {
-      const uint64_t k = sorted[i];
-      PairRec r;
-      r.a = (int)(k >> 36);
-      r.b = (int)((k >> 12) & 0xffffffull);
-      r.s[0] = (int)((k >> 8) & 15u) - 8;
-      r.s[1] = (int)((k >> 4) & 15u) - 8;
-      r.s[2] = (int)(k & 15u) - 8;
-      r.pad = 0;
-      for (int c = 0; c < 3; ++c) r.sh[c] = (double)r.s[c] * L[c];
-      pairs[i] = r;
-      if (i < cap_pairs) {
-        pair_ab[2 * i] = r.a;
-        pair_ab[2 * i + 1] = r.b;
-        for (int c = 0; c < 3; ++c) pair_shift[3 * i + c] = r.s[c];
-      }
+      for (int64_t i = p0; i < p1; ++i) emit_pair(sorted[i], i, L, pairs, pair_ab, pair_shift, cap_pairs);
     }
   }
 }
