@@ -302,10 +302,7 @@ __global__ __launch_bounds__(256) void k_cell_pairs(DevScene S, const double *bo
       if (!(__ballot(in) >> 63)) break;
     }
   }
-}
-
-__global__ void k_self_pairs(DevScene S, const double *box, const int *ves_scene, uint64_t *hash, int64_t cap,
-                             Counters *cnt) {
+  // each vesicle against its own periodic images (no cell needed)
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.n_ves; v += gridDim.x * blockDim.x) {
     const double *L = S.box_len + 3 * ves_scene[v];
     if (!(L[0] > 0.0 || L[1] > 0.0 || L[2] > 0.0)) continue;
@@ -320,7 +317,7 @@ __global__ void k_self_pairs(DevScene S, const double *box, const int *ves_scene
 constexpr int kListThreads = 256;
 template <int kListItems>
 __global__ __launch_bounds__(kListThreads) void k_hash_list(const uint64_t *hash, int64_t cap, uint64_t *uniq,
-                                                            int64_t uniq_cap, Counters *cnt) {
+                                                            int64_t uniq_cap, int32_t *cnt_a, Counters *cnt) {
   __shared__ int wsum[kListThreads / 64];
   __shared__ unsigned long long base_sh;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -352,19 +349,15 @@ __global__ __launch_bounds__(kListThreads) void k_hash_list(const uint64_t *hash
       const unsigned long long m = __ballot(keep);
       if (keep) {
         const unsigned long long idx = o + __popcll(m & lt);
-        if ((int64_t)idx < uniq_cap) uniq[idx] = key[j];
+        if ((int64_t)idx < uniq_cap) {
+          uniq[idx] = key[j];
+          atomicAdd(&cnt_a[(int)(key[j] >> 36)], 1);  // pairs per first vesicle (bucket sizes)
+        }
       }
       o += __popcll(m);
     }
     __syncthreads();
   }
-}
-
-__global__ void k_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, const Counters *cnt) {
-  int64_t n = (int64_t)cnt->n_pairs;
-  n = n < uniq_cap ? n : uniq_cap;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt_a[(int)(uniq[i] >> 36)], 1);
 }
 
 __global__ void k_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const int64_t *off_a, int32_t *cursor,
@@ -466,25 +459,17 @@ void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_
   k_cell_pairs<<<grid1d(n_cp_cap, 4, 4096), 256, 0, st>>>(S, ves_box, ves_scene, keys, vals, n_cp, n_cp_cap, hash,
                                                           hash_cap, cnt);
 }
-void launch_self_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, uint64_t *hash,
-                       int64_t hash_cap, Counters *cnt, hipStream_t st) {
-  k_self_pairs<<<grid1d(S.n_ves, 256), 256, 0, st>>>(S, ves_box, ves_scene, hash, hash_cap, cnt);
-}
-void launch_hash_list(const uint64_t *hash, int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt,
-                      hipStream_t st) {
+void launch_hash_list(const uint64_t *hash, int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a,
+                      Counters *cnt, hipStream_t st) {
   // a small set is spread over more workgroups (4 slots per thread: 0.117 against 0.121 ms
   // for the vesicle broad phase at 1440 vesicles, 131K slots); a large one keeps 16 per thread
   // (2M slots in the 256-scene batch: 4 per thread costs 13 us there)
   if (hash_cap <= (int64_t)1 << 18)
     k_hash_list<4><<<grid1d(hash_cap, kListThreads * 4, 1024), kListThreads, 0, st>>>(hash, hash_cap, uniq,
-                                                                                      uniq_cap, cnt);
+                                                                                      uniq_cap, cnt_a, cnt);
   else
     k_hash_list<16><<<grid1d(hash_cap, kListThreads * 16, 1024), kListThreads, 0, st>>>(hash, hash_cap, uniq,
-                                                                                         uniq_cap, cnt);
-}
-void launch_pair_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, Counters *cnt,
-                              hipStream_t st) {
-  k_bucket_count<<<grid1d(uniq_cap, 256), 256, 0, st>>>(uniq, uniq_cap, cnt_a, cnt);
+                                                                                         uniq_cap, cnt_a, cnt);
 }
 void launch_pair_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const int64_t *off_a, int32_t *cursor_a,
                                 uint64_t *sorted, Counters *cnt, hipStream_t st) {

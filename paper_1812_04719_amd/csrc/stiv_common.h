@@ -186,12 +186,8 @@ void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_sce
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
                        const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
                        int64_t hash_cap, Counters *cnt, hipStream_t st);
-void launch_self_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, uint64_t *hash,
-                       int64_t hash_cap, Counters *cnt, hipStream_t st);
-void launch_hash_list(const uint64_t *hash, int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, Counters *cnt,
-                      hipStream_t st);
-void launch_pair_bucket_count(const uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a, Counters *cnt,
-                              hipStream_t st);
+void launch_hash_list(const uint64_t *hash, int64_t hash_cap, uint64_t *uniq, int64_t uniq_cap, int32_t *cnt_a,
+                      Counters *cnt, hipStream_t st);
 void launch_pair_bucket_scatter(const uint64_t *uniq, int64_t uniq_cap, const int64_t *off_a,
                                 int32_t *cursor_a, uint64_t *sorted, Counters *cnt, hipStream_t st);
 void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const int64_t *off_a,

@@ -569,9 +569,8 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                         P<int64_t>(ctx->rs_off), st);
   launch_cell_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->cp_keys),
                     P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap, cnt, st);
-  launch_self_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->hash), hash_cap, cnt, st);
-  launch_hash_list(P<uint64_t>(ctx->hash), hash_cap, P<uint64_t>(ctx->uniq), ctx->cap_pairs, cnt, st);
-  launch_pair_bucket_count(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a), cnt, st);
+  launch_hash_list(P<uint64_t>(ctx->hash), hash_cap, P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a),
+                   cnt, st);
   launch_scan_i32_to_i64(P<int32_t>(ctx->cnt_a), P<int64_t>(ctx->off_a), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_pair_bucket_scatter(P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int64_t>(ctx->off_a),
                              P<int32_t>(ctx->cursor_a), P<uint64_t>(ctx->sorted), cnt, st);
