@@ -391,12 +391,16 @@ def test_table3_sort_scatter():
     assert data == g["scattered_data"]
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_configs_general_position(k):
-    """The seeded configurations are certified: nothing within 1e-9 of a decision boundary."""
+    """The seeded configurations are certified: nothing within 1e-9 of a
+    decision boundary (roots near 0 or 1, inside margins, near-double roots,
+    near misses), with d and with d = 0."""
     sc = S.make_config(k)
+    for d in (sc.d, 0.0):
+        r = oracle.detect(sc, d=d)
+        assert r.n_flag == [0, 0, 0, 0], (d, r.n_flag, r.min_margin)
     r = oracle.detect(sc)
-    assert r.n_flag == [0, 0, 0, 0], (r.n_flag, r.min_margin)
     assert r.n_initially_within_d == 0
     assert r.n_ct > 0
     if k == 3:
@@ -443,3 +447,102 @@ def test_full_gradient_and_backward_vs_finite_differences(d):
         assert np.abs(b1 - want1).max() <= 1e-6 * np.abs(want1).max()
         assert np.abs(b0 - want0).max() <= 1e-6 * np.abs(want0).max()
         checked += 1
+
+
+def test_translating_planes_ee_set_geometric():
+    """Edge-edge analogue of Eq. 3.1 on translating planes: the planes stay
+    parallel, so an edge pair reaches distance d exactly when its xy
+    projections cross.  The oracle's EE contact set is the set of edge pairs
+    whose projected segments intersect (2D segment test, written out here)."""
+    sc = T.translating_planes()
+    r = oracle.detect(sc)
+    n_a = sc.vtx_off[1]
+    A = sc.x0[:2, :n_a].T
+    B = sc.x0[:2, n_a:].T
+    ea, eb = sc.topos[0].edge, sc.topos[1].edge
+
+    def cross2(u, v):
+        return u[..., 0] * v[..., 1] - u[..., 1] * v[..., 0]
+
+    p0, p1 = A[ea[:, 0]][:, None, :], A[ea[:, 1]][:, None, :]
+    q0, q1 = B[eb[:, 0]][None, :, :], B[eb[:, 1]][None, :, :]
+    ru, sv, qp = p1 - p0, q1 - q0, q0 - p0
+    den = cross2(ru, sv)
+    assert np.all(np.abs(den) > 1e-3)          # no parallel edge pairs (17 degree rotation)
+    t = cross2(qp, sv) / den
+    u = cross2(qp, ru) / den
+    margin = np.minimum.reduce([t, 1 - t, u, 1 - u])
+    assert np.abs(margin).min() > 1e-6         # general position: no crossing at an endpoint
+    want = set(zip(*[x.tolist() for x in np.nonzero(margin >= 0)]))
+    ee = r.ct_key[r.ct_key[:, 1] == 2]
+    got = set((int(i), int(j)) for i, j in ee[:, 2:])
+    assert len(want) > 100
+    assert got == want
+
+
+def _contact_vertex_ids(sc, r):
+    import parity
+    ids = set()
+    for key in r.ct_key[r.ct_key[:, 1] < 2]:
+        gid, _, _ = parity.contact_positions(sc, r.pair_ab, r.pair_shift, key)
+        ids.update(int(g) for g in gid)
+    return ids
+
+
+@pytest.mark.parametrize("case", ["two_spheres", "mixed_order_periodic"])
+def test_jacobian_rows_vs_finite_differences(case):
+    """Each J row is dV/dX1 of its volume at that vertex (Sec. 3.3.2, g_X and
+    g_I storage): central differences (h = 1e-6) of the oracle's own volume
+    with respect to that vertex's X1, with every contact key unchanged by the
+    step.  The rows of a volume are exactly the vertices of its
+    vertex-triangle contacts (kind 0: vertex of a, triangle of b; kind 1 the
+    reverse), and vertices outside them do not move V."""
+    sc = S.make_config(1) if case == "two_spheres" else T.mixed_order_periodic()
+    r = oracle.detect(sc)
+    assert r.n_vol >= 1
+    if case == "mixed_order_periodic":
+        kinds = set(r.ct_key[:, 1].tolist())
+        assert kinds == {0, 1, 2} and np.any(r.pair_shift != 0)
+        assert len({int(t) for t in sc.topo_id}) == 2
+    # row set == vertex set of the vertex-triangle contacts (one volume here)
+    assert set(r.j_vtx.tolist()) == _contact_vertex_ids(sc, r)
+    rows = np.arange(r.n_jrow)
+    if r.n_jrow > 36:
+        rows = np.random.default_rng(9).choice(r.n_jrow, 36, replace=False)
+    h = 1e-6
+    checked = 0
+    for row in rows:
+        v, g = int(r.j_vol[row]), int(r.j_vtx[row])
+        fd = np.zeros(3)
+        stable = True
+        for c in range(3):
+            vals = []
+            for sgn in (1.0, -1.0):
+                x1 = sc.x1.copy()
+                x1[c, g] += sgn * h
+                rr = oracle.detect(sc.with_params(x1=x1))
+                if not np.array_equal(rr.ct_key, r.ct_key):
+                    stable = False
+                    break
+                vals.append(rr.vol_V[v])
+            if not stable:
+                break
+            fd[c] = (vals[0] - vals[1]) / (2 * h)
+        if not stable:
+            continue
+        scale = np.abs(r.j_g[row]).max()
+        assert np.abs(r.j_g[row] - fd).max() <= 1e-6 * scale + 1e-13, (row, g, r.j_g[row], fd)
+        checked += 1
+    assert checked >= min(len(rows), 12)
+    # a vertex next to the contact region that is in no contact does not move V
+    ids = _contact_vertex_ids(sc, r)
+    v_of = int(np.searchsorted(sc.vtx_off, min(ids), side="right") - 1)
+    lo, hi = sc.vtx_off[v_of], sc.vtx_off[v_of + 1]
+    near = [q for q in range(lo, hi) if q not in ids]
+    dist = [np.min(np.linalg.norm(sc.x0[:, [q]] - sc.x0[:, sorted(ids)], axis=0)) for q in near]
+    for q in [near[k] for k in np.argsort(dist)[:3]]:
+        x1 = sc.x1.copy()
+        x1[:, q] += h
+        rr = oracle.detect(sc.with_params(x1=x1))
+        assert np.array_equal(rr.ct_key, r.ct_key)
+        assert np.array_equal(rr.vol_V, r.vol_V)

@@ -65,3 +65,23 @@ def tetra(center, scale=1.0, rot=None):
             tri[k] = tri[k][[0, 2, 1]]
     e = np.unique(np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1), axis=0)
     return pts, Topology(order=-4, nv=4, tri=tri, edge=e.astype(np.int32))
+
+
+def mixed_order_periodic(seed=123):
+    """An order-8 and an order-12 sphere that meet across the periodic boundary
+    of a box periodic in x only (shift -1), both moving toward each other, with
+    seeded grid orientations and a small per-vertex perturbation of X1: contacts
+    of both vertex-triangle directions and edge-edge contacts in one pair."""
+    from scipy.spatial.transform import Rotation
+
+    from paper_1812_04719_amd import scenes as S
+    rng = np.random.default_rng(seed)
+    pa = S.spheroid_body_points(8, 1.0, 1.0) @ Rotation.random(random_state=1).as_matrix().T
+    pb = S.spheroid_body_points(12, 1.0, 1.0) @ Rotation.random(random_state=2).as_matrix().T
+    ta, tb = S.grid_topology(8), S.grid_topology(12)
+    L = 6.0
+    a0 = pa + np.array([1.0, 0.3, 0.0])
+    b0 = pb + np.array([L - 1.02, 0.0, 0.2])
+    a1 = a0 + np.array([-0.06, 0.0, 0.01]) + rng.normal(0, 2e-3, a0.shape)
+    b1 = b0 + np.array([0.06, 0.01, 0.0]) + rng.normal(0, 2e-3, b0.shape)
+    return two_body_scene(a0, a1, ta, b0, b1, tb, box_len=(L, 0, 0), d=0.0099)
