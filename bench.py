@@ -46,14 +46,34 @@ ALG_BYTES = {"vertex": 48.0, "pair": 16.0, "vt": 128.0, "ee": 32.0, "vol": 8.0, 
 ALG_FLOPS_PER_CANDIDATE = 170.0
 FLUSH_BYTES = 1 << 30               # written before each cold-cache step (larger than the 256 MB MALL)
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE + WRITE_SIZE on this workload,
-# each scaled by the counter's reading for a plain 1 GiB copy (factors 2.0 and 1.0), for the
-# kernel as it was built when the counters were taken (profiles/, HBM traffic summary);
-# an entry is removed whenever its kernel changes.
-TRAFFIC_BYTES = {"k_prim_cand": 1.5124e9}
+# each scaled by the counter's reading for a plain 1 GiB copy (factors 2.0 and 1.0),
+# keyed by a hash of the sources the kernel is built from: a figure taken on another
+# build of the kernel no longer matches and is reported as null.
+TRAFFIC_BYTES = {"k_prim_cand": {"sources": ("k_prim.hip", "narrow_math.h", "stiv_common.h"),
+                                 "sha16": None, "bytes": None}}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def sources_sha16(names):
+    """First 16 hex digits of the SHA-256 of the kernel sources, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1812_04719_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """Measured HBM bytes per launch of `kernel`, or None when the figure was
+    taken on other sources than the ones built now."""
+    t = TRAFFIC_BYTES.get(kernel)
+    if not t or t["bytes"] is None or t["sha16"] != sources_sha16(t["sources"]):
+        return None
+    return t["bytes"]
 
 
 def main():
@@ -64,6 +84,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--cold-reps", type=int, default=50,
+                    help="cold-cache steps (each after a 1 GiB write that evicts the MALL); median reported")
     ap.add_argument("--plain-only", action="store_true", help="skip the learned-bracket timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-scene batch measurement")
     ap.add_argument("--no-single-thread", action="store_true", help="skip the single-thread oracle run")
@@ -158,32 +180,52 @@ def main():
     log("stages (ms): %s" % stage_ms)
     log("work: %s" % work)
 
-    # roofline of the dominant kernel (k_prim_cand: primitive box-pair sweep,
-    # exact FP64 box test and polynomial screen of every candidate)
+    # roofline of the dominant kernel, counted from the method's algorithmic work
+    # (FP64 flops of F's coefficients per candidate the kernel examines, of V and its
+    # gradient per vertex-triangle contact; bytes of X0 and X1 for the box kernel)
     dom = int(np.argmax(stages[:6]))
+    t_dom = float(stages[dom]) * 1e-3
+    b_alg_path = (ALG_BYTES["vertex"] * sc.n_vtx + ALG_BYTES["pair"] * res["n_pairs"]
+                  + ALG_BYTES["vt"] * res["n_ct_vt"] + ALG_BYTES["ee"] * res["n_ct_ee"]
+                  + ALG_BYTES["vol"] * res["n_vol"] + ALG_BYTES["jrow"] * res["n_jrow"])
     if dom == 0:
         n_patch_boxes = sc.n_ves * math.ceil(sc.topos[0].nt / 64)
         bytes_alg = BYTES_PER_VERTEX_BOXES * sc.n_vtx + BYTES_PER_BOX_OUT * (sc.n_ves + n_patch_boxes)
-        achieved = bytes_alg / (stages[0] * 1e-3) / 1e9
-        roof = {"kernel": "k_boxes", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+        achieved = bytes_alg / t_dom / 1e9
+        roof = {"kernel": "k_boxes", "stage": names[0], "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for("k_boxes"), "alg_bytes_per_launch": int(bytes_alg),
+                "avg_launch_ms": round(float(stages[0]), 4)}
     else:
         kern = {3: "k_prim_cand", 4: "k_narrow"}.get(dom, names[dom])
         if dom == 3:
-            ops = OPS_PER_BOX_TEST * work["box_tests"] + OPS_PER_CANDIDATE_SCREEN * n_cand
+            flops = ALG_FLOPS_PER_CANDIDATE * n_cand
+            per = "170 FP64 flops (coefficients of F) x %d candidates" % n_cand
+        elif dom == 4:
+            flops = ALG_FLOPS_PER_CANDIDATE * work["root_searches"] + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
+            per = "170 x %d searched candidates + 300 x %d VT contacts" % (work["root_searches"], res["n_ct_vt"])
         else:
-            ops = FLOPS_PER_CANDIDATE * n_cand + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
-        achieved = ops / (stages[dom] * 1e-3) / 1e12
+            flops = 0.0
+            per = "no FP64 work counted for this stage"
+        achieved = flops / t_dom / 1e12
         roof = {"kernel": kern, "stage": names[dom], "bound": "alu", "achieved": round(achieved, 4),
-                "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": TRAFFIC_BYTES.get(kern), "ops_per_launch": int(ops),
-                "avg_launch_ms": round(float(stages[dom]), 4)}
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
+                "traffic": traffic_for(kern), "alg_flops_per_launch": int(flops), "alg_work": per,
+                "avg_launch_ms": round(float(stages[dom]), 4),
+                "peak_note": "FP64 vector datasheet peak of MI355X"}
+        # the whole path's algorithmic bytes credited to this one launch, against HBM
+        roof["alg_bytes_hbm_frac"] = round(b_alg_path / t_dom / (HBM_PEAK_GBS * 1e9), 5)
         if roof["traffic"]:
-            roof["hbm_gbs"] = round(roof["traffic"] / (stages[dom] * 1e-3) / 1e9, 1)
+            roof["hbm_gbs"] = round(roof["traffic"] / t_dom / 1e9, 1)
             roof["hbm_frac"] = round(roof["hbm_gbs"] / HBM_PEAK_GBS, 4)
         if dom == 3:
-            # the sweep reads two 24-byte boxes from LDS per test
-            lds = LDS_BYTES_PER_BOX_TEST * work["box_tests"] / (stages[dom] * 1e-3) / 1e12
+            # the implementation's own operation count (box tests of the sweep, exact box
+            # test and screens per candidate) against one VALU lane-operation per clock
+            ops = OPS_PER_BOX_TEST * work["box_tests"] + OPS_PER_CANDIDATE_SCREEN * n_cand
+            roof["impl_valu"] = {"ops_per_launch": int(ops),
+                                 "achieved_tops": round(ops / t_dom / 1e12, 4), "peak_tops": VALU_PEAK_TOPS,
+                                 "frac": round(ops / t_dom / 1e12 / VALU_PEAK_TOPS, 4)}
+            lds = LDS_BYTES_PER_BOX_TEST * work["box_tests"] / t_dom / 1e12
             roof["lds_tbs"] = round(lds, 3)
             roof["lds_frac"] = round(lds / LDS_PEAK_TBS, 4)
 
@@ -205,7 +247,7 @@ def main():
     # cold cache: before every step a 1 GiB write evicts the input from the 256 MB MALL;
     # each step is timed alone with events (the write is outside the timed window)
     cold = []
-    for k in range(max(5, args.steps // 2)):
+    for k in range(args.cold_reps):
         dst.fill_(float(k))
         torch.cuda.synchronize()
         e0.record()
@@ -220,8 +262,7 @@ def main():
                   "flush_bytes": FLUSH_BYTES, "statistic": "median"}
     log("cold cache: %s" % cold_cache)
     # algorithmic fractions of the whole path
-    b_alg = (ALG_BYTES["vertex"] * sc.n_vtx + ALG_BYTES["pair"] * res["n_pairs"] + ALG_BYTES["vt"] * res["n_ct_vt"]
-             + ALG_BYTES["ee"] * res["n_ct_ee"] + ALG_BYTES["vol"] * res["n_vol"] + ALG_BYTES["jrow"] * res["n_jrow"])
+    b_alg = b_alg_path
     f_alg = ALG_FLOPS_PER_CANDIDATE * n_cand + FLOPS_PER_VT_CONTACT * res["n_ct_vt"]
     t_fp = float(stages[3] + stages[4] + stages[5]) * 1e-3  # screens, root search, volumes, aggregation
     algorithmic = {"bytes": int(b_alg), "hbm_frac": round(b_alg / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),
@@ -252,6 +293,9 @@ def main():
         "work": work,
         "roofline": roof,
         "launch": "one HIP graph replay per step (stiv_detect_async captured once)",
+        "protocol": ("value and ms_per_step: mean over K warm graph replays (wall clock between two "
+                     "synchronizations); cold_cache: median of cold_reps eager steps, each timed with events "
+                     "after a 1 GiB write that evicts the 256 MB MALL"),
         "eager": eager,
         "cold_cache": cold_cache,
         "algorithmic": algorithmic,

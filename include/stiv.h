@@ -57,7 +57,7 @@ typedef enum {
   STIV_E_ARG = -1,      /* bad argument: d < 0, eps <= 0, dt <= 0, box_len < 0, bad offsets, no topology */
   STIV_E_CAPACITY = -2, /* a caller-provided output array is too small (see n_* for the sizes needed) */
   STIV_E_HIP = -3,      /* a HIP runtime call failed */
-  STIV_E_NUMERIC = -4,  /* a position is NaN or infinite */
+  STIV_E_NUMERIC = -4,  /* a position is NaN or infinite, or a root search ran out of its budget */
   STIV_E_STATE = -5     /* call order violated (e.g. detect before set_topology) */
 } stiv_status;
 
@@ -116,7 +116,21 @@ typedef struct {
  *   ct_grad [cap_ct][12] dV_k/dX1 of (vertex, triangle corner 0, 1, 2)
  *   vol_pair, vol_V [cap_vol]: contact volumes (pairs with >= 1 VT contact)
  *   j_vol, j_vtx, j_g [cap_jrow] ([cap_jrow][3] for j_g): Jacobian rows
- *           (volume index, global vertex id, dV/dX1 of that vertex) */
+ *           (volume index, global vertex id, dV/dX1 of that vertex)
+ *   ct_s    [cap_ct] optional (NULL: not written): the contact parameter
+ *           s* in [0,1] itself (tau = s* dt); stiv_backward uses it when
+ *           given, so that it differentiates at the forward's own root
+ * Diagnostics (counts over the whole call):
+ *   n_initially_within_d   contacts at s* = 0 (vertex already within d and
+ *                          inside its triangle at t_n)
+ *   n_degenerate_skipped   candidates skipped because F vanishes
+ *                          identically or the normal vanishes at a root
+ *   n_search_exhausted     root searches (Eq. 3.1) that examined their
+ *                          whole budget of 4096 Bernstein intervals without
+ *                          settling; their contacts may be missing, so a
+ *                          nonzero count makes stiv_detect / stiv_collect
+ *                          return STIV_E_NUMERIC (all outputs are still
+ *                          written) */
 typedef struct {
   int64_t cap_pairs, n_pairs;
   int32_t *pair_ab;
@@ -133,6 +147,8 @@ typedef struct {
   int32_t *j_vol, *j_vtx;
   double *j_g;
   int64_t n_initially_within_d, n_degenerate_skipped;
+  double *ct_s;
+  int64_t n_search_exhausted;
 } stiv_result;
 
 /* Create a context on a HIP device.  *ctx is NULL on failure. */
@@ -189,9 +205,11 @@ stiv_status stiv_collect(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, 
  *   dL/dX = sum over VT contacts k of  gV grad V_k + H_k w,
  * grad over X0 and X1 including the contact time's dependence on them
  * (Eq. 3.1-3.2), H_k the Hessian of V_k, w the dL_dG rows of its vertices.
- * Edge-edge contacts contribute nothing (they add nothing to V).  Enqueued
- * on `stream`, no synchronisation.  Per-vertex sums are in a fixed order;
- * a vertex in three or more contact volumes is summed with atomics. */
+ * Edge-edge contacts contribute nothing (they add nothing to V).  The
+ * contact parameter of each contact is res->ct_s when given, else
+ * ct_tau / dt.  Enqueued on `stream`, no synchronisation.  Every vertex's
+ * sum runs in one fixed order (contacts in canonical order, then volumes in
+ * order), so repeated calls are bit-identical. */
 stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
                           const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, void *stream);
 

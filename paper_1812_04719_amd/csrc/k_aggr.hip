@@ -102,8 +102,8 @@ __device__ inline int pow2_ceil(int n) {
 __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
     DevScene S, DevTopo T, const PairRec *pairs, const Counters *cnt, const int64_t *pair_off, const int32_t *perm,
     const Cand *ct, const double *ct_s, const double *ct_vol, const double *ct_grad, double dt, uint64_t *gkeys,
-    int32_t *gidx, int32_t *out_key, double *out_tau, double *out_vol, double *out_grad, int64_t cap_ct,
-    double *pair_V, int32_t *pair_hasvt, int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp,
+    int32_t *gidx, int32_t *out_key, double *out_tau, double *out_s, double *out_vol, double *out_grad,
+    int64_t cap_ct, double *pair_V, int32_t *pair_hasvt, int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp,
     int64_t pairs_cap) {
   __shared__ uint64_t skey[kLdsSort];
   __shared__ int32_t sidx[kLdsSort];
@@ -154,6 +154,7 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
         out_key[4 * o + 2] = cd.i;
         out_key[4 * o + 3] = cd.j;
         out_tau[o] = ct_s[c] * dt;
+        if (out_s) out_s[o] = ct_s[c];
         out_vol[o] = ct_vol[c];
         for (int q = 0; q < 12; ++q) out_grad[12 * o + q] = ct_grad[12 * (int64_t)c + q];
       }
@@ -312,11 +313,11 @@ void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, cons
 void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                               const Counters *cnt, const int64_t *pair_off, const int32_t *perm, const Cand *ct,
                               const double *ct_s, const double *ct_vol, const double *ct_grad, double dt,
-                              uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_vol,
-                              double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
+                              uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_s,
+                              double *out_vol, double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
                               int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp, hipStream_t st) {
   k_ct_sort_aggregate<<<g1(pairs_cap, 1), kAggThreads, 0, st>>>(
-      S, T, pairs, cnt, pair_off, perm, ct, ct_s, ct_vol, ct_grad, dt, gkeys, gidx, out_key, out_tau, out_vol,
+      S, T, pairs, cnt, pair_off, perm, ct, ct_s, ct_vol, ct_grad, dt, gkeys, gidx, out_key, out_tau, out_s, out_vol,
       out_grad, cap_ct, pair_V, pair_hasvt, pair_rows, row_vtx_tmp, row_g_tmp, pairs_cap);
 }
 void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,

@@ -10,7 +10,10 @@
 // the contact time on the positions.  The directional derivative is taken
 // in forward mode with dual numbers (narrow_math.h).  Contributions are
 // summed per (volume, vertex) in canonical contact order, as the forward
-// forms J rows, and added to the output vertex with one atomic per row.
+// forms J rows, into that J row's slot; the rows are then sorted by vertex
+// (stably, so volumes stay in order) and each vertex adds its rows in that
+// order and is written once.  No floating-point atomics: repeated calls give
+// the same bits.
 #include "narrow_math.h"
 
 namespace stiv {
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_volume(
     DevScene S, DevTopo T, double d, double eps, double dt, int64_t n_ct, const int32_t *ct_key,
     const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift, int64_t n_vol, const int32_t *vol_pair,
     int64_t n_jrow, const int32_t *j_vol, const int32_t *j_vtx, const double *dV, const double *dG, double *contrib,
-    uint64_t *gkeys, int32_t *gidx, double *dX0, double *dX1) {
+    uint64_t *gkeys, int32_t *gidx, const double *ct_s, double *rowc) {
   __shared__ uint64_t skey[kBwdLds];
   __shared__ int32_t sidx[kBwdLds];
   const int64_t NV = S.n_vtx;
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_volume(
         const bool found = lo < r1 && j_vtx[lo] == gid[r];
         for (int c = 0; c < 3; ++c) w[3 * r + c] = (dG && found) ? dG[3 * lo + c] : 0.0;
       }
-      const double s = ct_tau[c0 + k] / dt;
+      const double s = ct_s ? ct_s[c0 + k] : ct_tau[c0 + k] / dt;
       double g0[12], g1[12];
       nm::vt_vjp(X0, X1, s, d, eps, dt, s == 0.0, gV, w, g0, g1);
       for (int r = 0; r < 4; ++r) {
@@ -118,17 +121,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_volume(
     __threadfence_block();
     __syncthreads();
     bitonic_sort(key, idx, nj2);
-    // one thread per run of equal vertices adds the run in contact order
+    // one thread per run of equal vertices adds the run in contact order and
+    // stores the sum in the slot of that vertex's J row of this volume (every
+    // vertex of a vertex-triangle contact has one: the rows are sorted by
+    // vertex inside the volume)
     for (int e = threadIdx.x; e < nj; e += blockDim.x) {
       const uint64_t gv = key[e] >> 24;
       if (e > 0 && (key[e - 1] >> 24) == gv) continue;
       double acc[6] = {0, 0, 0, 0, 0, 0};
       for (int f = e; f < nj && (key[f] >> 24) == gv; ++f)
         for (int c = 0; c < 6; ++c) acc[c] += contrib[6 * (int64_t)idx[f] + c];
-      for (int c = 0; c < 3; ++c) {
-        if (dX0) atomicAdd(&dX0[c * NV + (int64_t)gv], acc[c]);
-        if (dX1) atomicAdd(&dX1[c * NV + (int64_t)gv], acc[3 + c]);
+      int64_t lo = r0, hi = r1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((uint64_t)j_vtx[mid] < gv) lo = mid + 1; else hi = mid;
       }
+      if (lo < r1 && (uint64_t)j_vtx[lo] == gv)
+        for (int c = 0; c < 6; ++c) rowc[6 * lo + c] = acc[c];
     }
     __syncthreads();
   }
@@ -139,23 +148,57 @@ __global__ void k_zero(double *p, int64_t n) {
     p[i] = 0.0;
 }
 
+// Row sums start at zero (a row whose vertices have no vertex-triangle
+// contact in its volume cannot occur, but a zero keeps every slot defined);
+// sort keys are the rows' vertices, values the row indices.
+__global__ void k_bwd_rows_init(const int32_t *j_vtx, int64_t n_jrow, double *rowc, uint64_t *rkey, uint32_t *rval) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_jrow; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int c = 0; c < 6; ++c) rowc[6 * i + c] = 0.0;
+    rkey[i] = (uint64_t)(uint32_t)j_vtx[i];
+    rval[i] = (uint32_t)i;
+  }
+}
+
+// Rows sorted by vertex (stable: volumes in order): the first entry of each
+// run adds the run in order and writes its vertex once.
+__global__ void k_bwd_vertex_sum(const uint64_t *rkey, const uint32_t *rval, int64_t n_jrow, const double *rowc,
+                                 int64_t NV, double *dX0, double *dX1) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_jrow; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t gv = rkey[e];
+    if (e > 0 && rkey[e - 1] == gv) continue;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t f = e; f < n_jrow && rkey[f] == gv; ++f)
+      for (int c = 0; c < 6; ++c) acc[c] += rowc[6 * (int64_t)rval[f] + c];
+    for (int c = 0; c < 3; ++c) {
+      if (dX0) dX0[c * NV + (int64_t)gv] = acc[c];
+      if (dX1) dX1[c * NV + (int64_t)gv] = acc[3 + c];
+    }
+  }
+}
+
 }  // namespace
 
 void launch_backward(const DevScene &S, const DevTopo &T, double d, double eps, double dt, int64_t n_ct,
                      const int32_t *ct_key, const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift,
                      int64_t n_vol, const int32_t *vol_pair, int64_t n_jrow, const int32_t *j_vol,
-                     const int32_t *j_vtx, const double *dV, const double *dG, double *contrib, uint64_t *gkeys,
-                     int32_t *gidx, double *dX0, double *dX1, hipStream_t st) {
+                     const int32_t *j_vtx, const double *dV, const double *dG, const double *ct_s, double *contrib,
+                     uint64_t *gkeys, int32_t *gidx, double *rowc, uint64_t *rkey, uint32_t *rval, uint64_t *tk,
+                     uint32_t *tv, int32_t *hist, int64_t *hoff, double *dX0, double *dX1, hipStream_t st) {
   const int64_t n3 = 3 * (int64_t)S.n_vtx;
   int64_t gz = (n3 + 255) / 256;
   gz = gz > 4096 ? 4096 : (gz < 1 ? 1 : gz);
   if (dX0) k_zero<<<(int)gz, 256, 0, st>>>(dX0, n3);
   if (dX1) k_zero<<<(int)gz, 256, 0, st>>>(dX1, n3);
-  if (n_vol <= 0) return;
+  if (n_vol <= 0 || n_jrow <= 0) return;
+  int64_t gr = (n_jrow + 255) / 256;
+  gr = gr > 4096 ? 4096 : gr;
+  k_bwd_rows_init<<<(int)gr, 256, 0, st>>>(j_vtx, n_jrow, rowc, rkey, rval);
   int64_t g = n_vol < 8192 ? n_vol : 8192;
   k_bwd_volume<<<(int)g, kBwdThreads, 0, st>>>(S, T, d, eps, dt, n_ct, ct_key, ct_tau, pair_ab, pair_shift, n_vol,
-                                               vol_pair, n_jrow, j_vol, j_vtx, dV, dG, contrib, gkeys, gidx, dX0,
-                                               dX1);
+                                               vol_pair, n_jrow, j_vol, j_vtx, dV, dG, contrib, gkeys, gidx, ct_s,
+                                               rowc);
+  launch_radix_sort_u64(rkey, rval, tk, tv, nullptr, n_jrow, 32, hist, hoff, st);
+  k_bwd_vertex_sum<<<(int)gr, 256, 0, st>>>(rkey, rval, n_jrow, rowc, (int64_t)S.n_vtx, dX0, dX1);
 }
 
 }  // namespace stiv

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
                                                 Counters *cnt) {
   int64_t nc = (int64_t)cnt->n_hard;
   nc = nc < hard_cap ? nc : hard_cap;
-  int within = 0, deg = 0, cert = 0;
+  int within = 0, deg = 0, exh = 0, cert = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   extern __shared__ char dyn_lds[];
   BracketLds &L = *reinterpret_cast<BracketLds *>(dyn_lds);
@@ -166,13 +166,13 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
         lo = lo < 0.0 ? 0.0 : lo;
         hi = hi > 1.0 ? 1.0 : hi;
         int certified = 0;
-        hit = earliest_bracket<N>(Q, d, lo, hi, (double)mu, &s, &within, &deg, &certified);
+        hit = earliest_bracket<N>(Q, d, lo, hi, (double)mu, &s, &within, &deg, &exh, &certified);
         cert += certified;
       }
       mlp::wave_lds_sync();
     } else if (i < nc) {
       load_geo(geo, hard_cap, i, c.kind == 2, Q);
-      hit = earliest<N>(Q, d, &s, &within, &deg);
+      hit = earliest<N>(Q, d, &s, &within, &deg, &exh);
     }
     if (hit && !Q.ee) volume_grad(Q, s, d, eps, dt, s == 0.0, &V, g);
     const unsigned long long m = __ballot(hit != 0);
@@ -198,6 +198,7 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
   }
   if (within) atomicAdd(&cnt->within_d, (unsigned long long)within);
   if (deg) atomicAdd(&cnt->degenerate, (unsigned long long)deg);
+  if (exh) atomicAdd(&cnt->search_exhausted, (unsigned long long)exh);
   if (LEARNED && cert) atomicAdd(&cnt->n_bracket_ok, (unsigned long long)cert);
 }
 

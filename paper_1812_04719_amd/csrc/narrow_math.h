@@ -194,12 +194,22 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
   return x;
 }
 
+// Budget of one root search: intervals examined (shared by the calls of one
+// candidate) and subdivision depth.  A search that runs out of intervals
+// stops without a result and is counted in *exh: the caller reports it (its
+// contacts may be missing), it is never taken for "no contact".  At the
+// depth limit an interval 2^-44 of the search range wide is decided by the
+// signs of F at its ends (a root there would be a near-double root).
+constexpr int kMaxSearchLevel = 44;
+constexpr int kMaxSearchVisits = 4096;
+
 // Earliest valid root of F (degree N, coefficients f) in [lo, hi] by
 // depth-first Bernstein subdivision of that interval into the pieces
 // lo + (hi - lo) [idx 2^-level, (idx + 1) 2^-level].  Returns 1 with *s_out on
 // contact.  *visits counts the intervals examined (shared budget across
-// calls); *deg counts degenerate skips.  guess (optional) is the start of
-// the refinement of a root isolated in an interval that contains it.
+// calls); *deg counts degenerate skips, *exh searches that ran out of their
+// budget of intervals.  guess (optional) is the start of the refinement of a
+// root isolated in an interval that contains it.
 //
 // The search alternates two phases: subdivide until the next interval that
 // isolates a root (or the end), then refine that root and test it.  On a
@@ -209,9 +219,9 @@ __host__ __device__ double refine(const double f[N + 1], double lo, double hi, d
 // roots computed are those of a plain depth-first traversal.
 template <int N>
 __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double lo, double hi, double *s_out,
-                                  int *visits, int *deg, double guess = -1.0) {
-  const int kMaxLevel = 44;
-  const int kMaxVisits = 4096;
+                                  int *visits, int *deg, int *exh, double guess = -1.0) {
+  const int kMaxLevel = kMaxSearchLevel;
+  const int kMaxVisits = kMaxSearchVisits;
   const double span = hi - lo;
   int level = 0;
   long long idx = 0;
@@ -222,7 +232,7 @@ __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double l
     double u = 0.0, v = 0.0, fu = 0.0, root = -1.0;
     while (!done && !iso) {
       if (++(*visits) > kMaxVisits) {
-        (*deg)++;
+        (*exh)++;
         return 0;
       }
       const double wd = ldexp(1.0, -level);
@@ -300,15 +310,15 @@ __host__ __device__ inline int prepare(const Quad &Q, double d, double f[N + 1],
 }
 
 // Earliest valid root of F (degree N) on [0,1].  Returns 1 with *s on contact.
-// *deg counts degenerate skips (vanishing normal at a root, F == 0, or a
-// polynomial that stays zero up to rounding over a whole interval).
+// *deg counts degenerate skips (vanishing normal at a root, or F == 0),
+// *exh searches stopped by their budget (search_in).
 template <int N>
-__host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *within, int *deg) {
+__host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *within, int *deg, int *exh) {
   double f[N + 1];
   const int pre = prepare<N>(Q, d, f, s_out, within, deg);
   if (pre >= 0) return pre;
   int visits = 0;
-  return search_in<N>(Q, f, 0.0, 1.0, s_out, &visits, deg);
+  return search_in<N>(Q, f, 0.0, 1.0, s_out, &visits, deg, exh);
 }
 
 // The same earliest valid root, searched first inside a predicted bracket
@@ -321,7 +331,7 @@ __host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *wi
 // from a different enclosing interval).  *certified reports the path taken.
 template <int N>
 __host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, double hi, double guess, double *s_out,
-                                         int *within, int *deg, int *certified) {
+                                         int *within, int *deg, int *exh, int *certified) {
   double f[N + 1];
   const int pre = prepare<N>(Q, d, f, s_out, within, deg);
   *certified = 0;
@@ -345,7 +355,7 @@ __host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, dou
   const int parts = (ok && hi < 1.0) ? 2 : 1;
   int visits = 0;
   for (int part = 0; part < parts; ++part) {
-    if (search_in<N>(Q, f, a0, a1, s_out, &visits, deg, guess)) return 1;
+    if (search_in<N>(Q, f, a0, a1, s_out, &visits, deg, exh, guess)) return 1;
     a0 = a1;
     a1 = 1.0;
   }

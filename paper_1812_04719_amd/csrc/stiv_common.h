@@ -122,7 +122,7 @@ struct Counters {
   unsigned long long n_tests;      // primitive box-pair tests of the candidate sweep
   unsigned long long n_bracket_ok;  // root searches whose predicted bracket was certified
   unsigned long long work_claimed;  // work-item chunks handed out by the primitive kernel
-  unsigned long long pad;
+  unsigned long long search_exhausted;  // root searches stopped by their budget of intervals
 };
 
 // Narrow-phase candidate record.
@@ -247,8 +247,8 @@ void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, cons
 void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                               const Counters *cnt, const int64_t *pair_off, const int32_t *perm, const Cand *ct,
                               const double *ct_s, const double *ct_vol, const double *ct_grad, double dt,
-                              uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_vol,
-                              double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
+                              uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_s,
+                              double *out_vol, double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
                               int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp, hipStream_t st);
 void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,
                           const int64_t *row_off, const int32_t *pair_hasvt, const double *pair_V,
@@ -259,7 +259,8 @@ void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_
 void launch_backward(const DevScene &S, const DevTopo &T, double d, double eps, double dt, int64_t n_ct,
                      const int32_t *ct_key, const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift,
                      int64_t n_vol, const int32_t *vol_pair, int64_t n_jrow, const int32_t *j_vol,
-                     const int32_t *j_vtx, const double *dV, const double *dG, double *contrib, uint64_t *gkeys,
-                     int32_t *gidx, double *dX0, double *dX1, hipStream_t st);
+                     const int32_t *j_vtx, const double *dV, const double *dG, const double *ct_s, double *contrib,
+                     uint64_t *gkeys, int32_t *gidx, double *rowc, uint64_t *rkey, uint32_t *rval, uint64_t *tk,
+                     uint32_t *tv, int32_t *hist, int64_t *hoff, double *dX0, double *dX1, hipStream_t st);
 
 }  // namespace stiv

@@ -68,8 +68,8 @@ struct stiv_ctx {
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
-      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, hard_geo, rs_hist, rs_off,
-      scan_tmp;
+      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, bwd_rowc, bwd_rkey, bwd_rval,
+      hard_geo, rs_hist, rs_off, scan_tmp;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
   Buf toi_params, toi_packed, mlp_part;
   // LCP matrix assembly scratch
@@ -161,7 +161,7 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
                 &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
                 &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv,
-                &ctx->bwd_contrib, &ctx->bwd_keys, &ctx->bwd_idx};
+                &ctx->bwd_contrib, &ctx->bwd_keys, &ctx->bwd_idx, &ctx->bwd_rowc, &ctx->bwd_rkey, &ctx->bwd_rval};
   for (Buf *b : all)
     if (b->p) hipFree(b->p);
   for (auto &e : ctx->ev)
@@ -603,7 +603,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_ct_sort_aggregate(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, cnt, P<int64_t>(ctx->pair_off),
                            P<int32_t>(ctx->perm), P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol),
                            P<double>(ctx->ct_grad), p->dt, P<uint64_t>(ctx->gkeys), P<int32_t>(ctx->gidx),
-                           out->ct_key, out->ct_tau, out->ct_vol, out->ct_grad, out->cap_ct, P<double>(ctx->pair_V),
+                           out->ct_key, out->ct_tau, out->ct_s, out->ct_vol, out->ct_grad, out->cap_ct, P<double>(ctx->pair_V),
                            P<int32_t>(ctx->pair_hasvt), P<int32_t>(ctx->pair_rows), P<int32_t>(ctx->row_vtx),
                            P<double>(ctx->row_g), st);
   launch_scan2_i32_to_i64(P<int32_t>(ctx->pair_hasvt), P<int64_t>(ctx->vol_off), P<int32_t>(ctx->pair_rows),
@@ -635,6 +635,17 @@ static stiv_status read_counts(stiv_ctx *ctx, const stiv_params *p, stiv_result 
   out->n_jrow = (int64_t)c.n_jrow;
   out->n_initially_within_d = (int64_t)c.within_d;
   out->n_degenerate_skipped = (int64_t)c.degenerate;
+  out->n_search_exhausted = (int64_t)c.search_exhausted;
+  return STIV_OK;
+}
+
+// A root search that ran out of its budget may have missed contacts: the
+// outputs are written, but the call reports it.
+static stiv_status check_exhausted(stiv_ctx *ctx, const stiv_result *out) {
+  if (out->n_search_exhausted > 0)
+    return fail(ctx, STIV_E_NUMERIC,
+                std::to_string(out->n_search_exhausted) +
+                    " root search(es) exhausted their interval budget; contacts of those candidates may be missing");
   return STIV_OK;
 }
 
@@ -647,7 +658,7 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (s->n_ves == 0) {
     out->n_pairs = out->n_cand_vt = out->n_cand_ee = out->n_ct_vt = out->n_ct_ee = out->n_vol = out->n_jrow = 0;
-    out->n_initially_within_d = out->n_degenerate_skipped = 0;
+    out->n_initially_within_d = out->n_degenerate_skipped = out->n_search_exhausted = 0;
     return STIV_OK;
   }
   stiv_status sv = check_structure(ctx, s);
@@ -705,7 +716,7 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
                       out->n_vol > out->cap_vol || out->n_jrow > out->cap_jrow ||
                       ((p->flags & STIV_EMIT_CANDIDATES) && n_cand > out->cap_cand);
     if (over) return fail(ctx, STIV_E_CAPACITY, "an output array is too small; n_* hold the required sizes");
-    return STIV_OK;
+    return check_exhausted(ctx, out);
   }
   return fail(ctx, STIV_E_CAPACITY, "internal buffers did not converge after growing");
 }
@@ -748,7 +759,7 @@ stiv_status stiv_collect(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, 
   const bool over = out->n_pairs > out->cap_pairs || out->n_ct_vt + out->n_ct_ee > out->cap_ct ||
                     out->n_vol > out->cap_vol || out->n_jrow > out->cap_jrow;
   if (over) return fail(ctx, STIV_E_CAPACITY, "an output array is too small; n_* hold the required sizes");
-  return STIV_OK;
+  return check_exhausted(ctx, out);
 }
 
 stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch);
@@ -797,14 +808,23 @@ stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params 
   HIPCHK(ensure(ctx->bwd_contrib, 6 * 8 * 4 * (size_t)(n_ct + 1)));
   HIPCHK(ensure(ctx->bwd_keys, 8 * 8 * (size_t)(n_ct + 1)));
   HIPCHK(ensure(ctx->bwd_idx, 4 * 8 * (size_t)(n_ct + 1)));
+  const int64_t nj = res->n_jrow;
+  HIPCHK(ensure(ctx->bwd_rowc, 6 * 8 * (size_t)(nj + 1)));
+  HIPCHK(ensure(ctx->bwd_rkey, 8 * (size_t)(nj + 1)));
+  HIPCHK(ensure(ctx->bwd_rval, 4 * (size_t)(nj + 1)));
+  HIPCHK(ensure(ctx->sort_tk, 8 * (size_t)(nj + 1)));
+  HIPCHK(ensure(ctx->sort_tv, 4 * (size_t)(nj + 1)));
+  HIPCHK(ensure_sort_scratch(ctx, nj));
   DevScene S;
   S.n_ves = s->n_ves; S.n_vtx = s->n_vtx; S.n_scenes = s->n_scenes;
   S.vtx_off = s->vtx_off; S.topo_id = s->topo_id; S.scene_off = s->scene_off;
   S.box_len = s->box_len; S.x0 = s->x0; S.x1 = s->x1;
   launch_backward(S, ctx->topo, p->d, p->eps, p->dt, n_ct, res->ct_key, res->ct_tau, res->pair_ab, res->pair_shift,
-                  res->n_vol, res->vol_pair, res->n_jrow, res->j_vol, res->j_vtx, dL_dV, dL_dG,
-                  P<double>(ctx->bwd_contrib), P<uint64_t>(ctx->bwd_keys), P<int32_t>(ctx->bwd_idx), dL_dX0, dL_dX1,
-                  st);
+                  res->n_vol, res->vol_pair, res->n_jrow, res->j_vol, res->j_vtx, dL_dV, dL_dG, res->ct_s,
+                  P<double>(ctx->bwd_contrib), P<uint64_t>(ctx->bwd_keys), P<int32_t>(ctx->bwd_idx),
+                  P<double>(ctx->bwd_rowc), P<uint64_t>(ctx->bwd_rkey), P<uint32_t>(ctx->bwd_rval),
+                  P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), P<int32_t>(ctx->rs_hist),
+                  P<int64_t>(ctx->rs_off), dL_dX0, dL_dX1, st);
   HIPCHK(hipGetLastError());
   return STIV_OK;
 }

@@ -61,7 +61,8 @@ class stiv_result(C.Structure):
                 ("cap_vol", C.c_int64), ("n_vol", C.c_int64), ("vol_pair", C.c_void_p), ("vol_V", C.c_void_p),
                 ("cap_jrow", C.c_int64), ("n_jrow", C.c_int64), ("j_vol", C.c_void_p), ("j_vtx", C.c_void_p),
                 ("j_g", C.c_void_p),
-                ("n_initially_within_d", C.c_int64), ("n_degenerate_skipped", C.c_int64)]
+                ("n_initially_within_d", C.c_int64), ("n_degenerate_skipped", C.c_int64),
+                ("ct_s", C.c_void_p), ("n_search_exhausted", C.c_int64)]
 
 
 _lock = threading.Lock()
@@ -269,6 +270,7 @@ class Outputs:
         self.cand = torch.empty((max(cap_cand, 1), 4), dtype=i32, device=d)
         self.ct_key = torch.empty((cap_ct, 4), dtype=i32, device=d)
         self.ct_tau = torch.empty(cap_ct, dtype=f64, device=d)
+        self.ct_s = torch.empty(cap_ct, dtype=f64, device=d)
         self.ct_vol = torch.empty(cap_ct, dtype=f64, device=d)
         self.ct_grad = torch.empty((cap_ct, 12), dtype=f64, device=d)
         self.vol_pair = torch.empty(cap_vol, dtype=i32, device=d)
@@ -284,6 +286,7 @@ class Outputs:
         r.cap_cand, r.cand = c["cand"], self.cand.data_ptr()
         r.cap_ct, r.ct_key = c["ct"], self.ct_key.data_ptr()
         r.ct_tau, r.ct_vol, r.ct_grad = self.ct_tau.data_ptr(), self.ct_vol.data_ptr(), self.ct_grad.data_ptr()
+        r.ct_s = self.ct_s.data_ptr()
         r.cap_vol, r.vol_pair, r.vol_V = c["vol"], self.vol_pair.data_ptr(), self.vol_V.data_ptr()
         r.cap_jrow, r.j_vol, r.j_vtx, r.j_g = c["jrow"], self.j_vol.data_ptr(), self.j_vtx.data_ptr(), \
             self.j_g.data_ptr()
@@ -377,9 +380,9 @@ def _collect(r, o, emit, to_numpy):
     out = DetectResult(
         n_pairs=r.n_pairs, n_cand_vt=r.n_cand_vt, n_cand_ee=r.n_cand_ee, n_ct_vt=r.n_ct_vt, n_ct_ee=r.n_ct_ee,
         n_ct=nct, n_vol=r.n_vol, n_jrow=r.n_jrow, n_initially_within_d=r.n_initially_within_d,
-        n_degenerate_skipped=r.n_degenerate_skipped,
+        n_degenerate_skipped=r.n_degenerate_skipped, n_search_exhausted=r.n_search_exhausted,
         pair_ab=o.pair_ab[: r.n_pairs], pair_shift=o.pair_shift[: r.n_pairs],
-        ct_key=o.ct_key[:nct], ct_tau=o.ct_tau[:nct], ct_vol=o.ct_vol[:nct], ct_grad=o.ct_grad[:nct],
+        ct_key=o.ct_key[:nct], ct_tau=o.ct_tau[:nct], ct_s=o.ct_s[:nct], ct_vol=o.ct_vol[:nct], ct_grad=o.ct_grad[:nct],
         vol_pair=o.vol_pair[: r.n_vol], vol_V=o.vol_V[: r.n_vol],
         j_vol=o.j_vol[: r.n_jrow], j_vtx=o.j_vtx[: r.n_jrow], j_g=o.j_g[: r.n_jrow],
     )

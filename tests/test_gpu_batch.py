@@ -31,7 +31,7 @@ def test_batch_parity(ctx, batch):
     g, _ = stiv.detect(ctx, stiv.DeviceScene(batch), batch.d, batch.eps, batch.dt, emit_candidates=True)
     o = oracle.detect(batch, emit_candidates=True)
     assert len({t.order for t in batch.topos}) >= 2
-    parity.compare(g, o, batch.dt, batch.eps, check_cand=True)
+    parity.compare(g, o, batch, batch.dt, batch.eps, check_cand=True)
     # pairs never cross scenes
     sc_of = np.searchsorted(batch.scene_off, np.arange(batch.n_ves), side="right") - 1
     assert np.all(sc_of[g["pair_ab"][:, 0]] == sc_of[g["pair_ab"][:, 1]])
@@ -79,19 +79,38 @@ def test_autotune(ctx, tmp_path):
     cfg2, table2 = autotune.tune(ctx, ds, sc.d, sc.eps, sc.dt, cache_file=cache, candidates=cand)
     assert cfg2 == cfg and table2 == []
     g, _ = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt)
-    parity.compare(g, oracle.detect(sc), sc.dt, sc.eps)
+    parity.compare(g, oracle.detect(sc), sc, sc.dt, sc.eps)
     autotune.apply(ctx, dict(tile=64, prim_blocks=8192, narrow_blocks=8192))
 
 
-@pytest.mark.timeout(600)
-def test_batch_config_256_scenes(ctx):
+@pytest.fixture(scope="module")
+def batch_256():
+    return S.make_config(4)
+
+
+@pytest.mark.timeout(900)
+def test_batch_config_256_scenes(ctx, batch_256):
     """The full batching configuration: 256 independent scenes of 8-128
     vesicles, orders 16/24/32, 10-60 % volume fraction, in one call; every
-    set exact against the oracle (candidate counts, contacts, volumes, J)."""
+    set exact against the oracle (pairs, the primitive candidate set,
+    contacts, volumes, J rows, counters)."""
     from paper_1812_04719_amd import stiv
-    b = S.make_config(4)
+    b = batch_256
     print("batch config: scenes=%d vesicles=%d vertices=%d" % (b.n_scenes, b.n_ves, b.n_vtx), flush=True)
-    g, _ = stiv.detect(ctx, stiv.DeviceScene(b), b.d, b.eps, b.dt)
-    o = oracle.detect(b)
+    g, _ = stiv.detect(ctx, stiv.DeviceScene(b), b.d, b.eps, b.dt, emit_candidates=True)
+    o = oracle.detect(b, emit_candidates=True)
     assert b.n_scenes == 256
-    parity.compare(g, o, b.dt, b.eps)
+    st = parity.compare(g, o, b, b.dt, b.eps, check_cand=True)
+    print("parity statistics: %s" % st, flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_batch_config_256_scenes_d0(ctx, batch_256):
+    """The 256-scene batch with d = 0 (coplanarity cubic)."""
+    from paper_1812_04719_amd import stiv
+    b = batch_256
+    print("batch config d=0", flush=True)
+    g, _ = stiv.detect(ctx, stiv.DeviceScene(b), 0.0, b.eps, b.dt)
+    o = oracle.detect(b, d=0.0)
+    st = parity.compare(g, o, b, b.dt, b.eps)
+    print("parity statistics: %s" % st, flush=True)

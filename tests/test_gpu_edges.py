@@ -27,7 +27,7 @@ def _check(ctx, sc, emit=True):
     print("edge case: n_ves=%d n_vtx=%d" % (sc.n_ves, sc.n_vtx), flush=True)
     g, _ = stiv.detect(ctx, stiv.DeviceScene(sc), sc.d, sc.eps, sc.dt, emit_candidates=emit)
     o = oracle.detect(sc, emit_candidates=emit)
-    parity.compare(g, o, sc.dt, sc.eps, check_cand=emit)
+    parity.compare(g, o, sc, sc.dt, sc.eps, check_cand=emit)
     return g, o
 
 

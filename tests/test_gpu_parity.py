@@ -27,18 +27,21 @@ def ctx():
     c.close()
 
 
-def run_gpu(ctx, sc, emit=True, d=None):
+def run_gpu(ctx, sc, emit=True, d=None, eps=None):
     from paper_1812_04719_amd import stiv
-    print("gpu case: n_ves=%d n_vtx=%d d=%s" % (sc.n_ves, sc.n_vtx, sc.d if d is None else d), flush=True)
+    d = sc.d if d is None else d
+    eps = sc.eps if eps is None else eps
+    print("gpu case: n_ves=%d n_vtx=%d d=%s eps=%s" % (sc.n_ves, sc.n_vtx, d, eps), flush=True)
     ds = stiv.DeviceScene(sc)
-    res, _ = stiv.detect(ctx, ds, sc.d if d is None else d, sc.eps, sc.dt, emit_candidates=emit)
+    res, _ = stiv.detect(ctx, ds, d, eps, sc.dt, emit_candidates=emit)
     return res
 
 
-def check(ctx, sc, d=None, emit=True):
-    g = run_gpu(ctx, sc, emit=emit, d=d)
-    o = oracle.detect(sc, d=d, emit_candidates=emit)
-    parity.compare(g, o, sc.dt, sc.eps, check_cand=emit)
+def check(ctx, sc, d=None, emit=True, eps=None):
+    g = run_gpu(ctx, sc, emit=emit, d=d, eps=eps)
+    o = oracle.detect(sc, d=d, eps=eps, emit_candidates=emit)
+    st = parity.compare(g, o, sc, sc.dt, sc.eps if eps is None else eps, check_cand=emit)
+    print("parity statistics: %s" % st, flush=True)
     return g, o
 
 
@@ -112,22 +115,38 @@ def test_parity_fcc_small(ctx):
     check(ctx, sc)
 
 
-def test_parity_1440_sampled(ctx):
-    """Full-size 1440-vesicle scene: all pairs, all candidate counts, and the
-    contacts / volumes / J rows of a seeded sample of 80 vesicle pairs."""
-    sc = S.make_config(3)
-    g = run_gpu(ctx, sc, emit=False)
-    rng = np.random.default_rng(33)
-    vol_pairs = g["vol_pair"]
-    pick = np.unique(np.concatenate([rng.choice(vol_pairs, 40, replace=False),
-                                     rng.choice(g["n_pairs"], 40, replace=False)]))
-    o = oracle.detect(sc, pair_subset=pick)
-    parity.compare(g, o, sc.dt, sc.eps, pair_subset=pick)
-    # whole-scene totals from the full oracle run
-    full = oracle.detect(sc)
-    assert g["n_cand_vt"] == full["n_cand_vt"] and g["n_cand_ee"] == full["n_cand_ee"]
-    assert np.array_equal(g["ct_key"], full["ct_key"])
-    assert g["n_vol"] == full["n_vol"]
+def test_parity_rsa_64_d0(ctx):
+    """The coplanarity variant (Eq. 3.1 with d = 0: F = g, a cubic) on the
+    64-vesicle periodic scene."""
+    check(ctx, S.make_config(2), d=0.0)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_parity_eps_01(ctx, cfg):
+    """A tenth of the default velocity scale of App. A (eps = 0.1): volumes,
+    gradients and J rows change, contacts do not."""
+    check(ctx, S.make_config(cfg), eps=0.1)
+
+
+@pytest.fixture(scope="module")
+def scene_1440():
+    return S.make_config(3)
+
+
+@pytest.mark.timeout(600)
+def test_parity_1440_full(ctx, scene_1440):
+    """Full-size 1440-vesicle scene, every output element by element against
+    the oracle's whole-scene run: pairs, the primitive candidate set (3.3M
+    vertex-triangle and edge-edge pairs), contacts with their times, volumes,
+    gradients, volumes per pair and J rows, and the diagnostic counters."""
+    g, o = check(ctx, scene_1440, emit=True)
+    assert g["n_ct_vt"] > 10000 and g["n_vol"] > 1000
+
+
+@pytest.mark.timeout(600)
+def test_parity_1440_d0(ctx, scene_1440):
+    """The 1440-vesicle scene with d = 0 (coplanarity cubic), all outputs."""
+    check(ctx, scene_1440, d=0.0, emit=False)
 
 
 def test_determinism(ctx):
@@ -167,7 +186,7 @@ def test_capacity_retry(ctx):
     outs = stiv.Outputs(ds.x0.device, cap_pairs=1, cap_ct=2, cap_vol=1, cap_jrow=2)
     res, outs = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs)
     o = oracle.detect(sc)
-    parity.compare(res, o, sc.dt, sc.eps)
+    parity.compare(res, o, sc, sc.dt, sc.eps)
 
 
 @pytest.mark.parametrize("tile", [16, 32, 64])
@@ -181,4 +200,4 @@ def test_patch_size_does_not_change_results(ctx, tile):
     finally:
         ctx.set_patch_size(64)
     o = oracle.detect(sc, emit_candidates=True)
-    parity.compare(g, o, sc.dt, sc.eps, check_cand=True)
+    parity.compare(g, o, sc, sc.dt, sc.eps, check_cand=True)

@@ -178,8 +178,35 @@ def test_bracket_same_contacts(ctx, model):
         assert np.array_equal(plain["vol_pair"], learned["vol_pair"])
         assert np.array_equal(plain["j_vtx"], learned["j_vtx"])
         o = oracle.detect(sc)
-        parity.compare(learned, o, sc.dt, sc.eps)
+        parity.compare(learned, o, sc, sc.dt, sc.eps)
         assert 0 <= st["bracket_certified"] <= st["root_searches"]
+    ctx.set_toi_model(None)
+
+
+@pytest.mark.parametrize("model", ["const_0.3", "random", "trained"])
+def test_bracket_same_contacts_d0(ctx, model):
+    """The bracketed search of the coplanarity variant (d = 0: F = g, degree
+    3) returns the plain search's contacts, and both match the oracle."""
+    from paper_1812_04719_amd import stiv, toi_model
+    if model == "trained":
+        if not os.path.exists(toi_model.DEFAULT_WEIGHTS):
+            pytest.skip("no trained bracket model in the package")
+        toi_model.install(ctx)
+    elif model == "random":
+        ctx.set_toi_model(_rand_params(6), 2.0)
+    else:
+        ctx.set_toi_model(_const_model(0.3, -8.0), 3.0)
+    for name, sc in [("two_spheres", S.make_two_spheres(seed=1)), ("rsa64", S.make_config(2))]:
+        print("bracket d=0 %s on %s" % (model, name), flush=True)
+        ds = stiv.DeviceScene(sc)
+        plain, _ = stiv.detect(ctx, ds, 0.0, sc.eps, sc.dt)
+        learned, _ = stiv.detect(ctx, ds, 0.0, sc.eps, sc.dt, learned_bracket=True)
+        st = ctx.stats()
+        assert np.array_equal(plain["ct_key"], learned["ct_key"])
+        assert np.all(np.abs(plain["ct_tau"] - learned["ct_tau"]) <= 1e-12 * sc.dt)
+        o = oracle.detect(sc, d=0.0)
+        parity.compare(learned, o, sc, sc.dt, sc.eps)
+        assert st["root_searches"] > 0 and 0 <= st["bracket_certified"] <= st["root_searches"]
     ctx.set_toi_model(None)
 
 
