@@ -8,8 +8,9 @@ skips).  Reals, per contact or per row:
   V_pair    |dV| <= 1e-10 * (sum of |V_k| of the pair)
   gradient  ||dG||_inf <= 1e-10 ||G_ref||_inf per contact; a contact whose
             contact time is ill conditioned, kappa = ||dF/dX1|| l / |F_s| > 1e4
-            (l its mean edge length), is compared at 1e-14 kappa instead and
-            counted
+            (l its mean edge length), is compared at 1e-14 kappa instead
+            (kappa capped at 1e6) and counted; a contact at s* = 0 has no
+            contact-time term and keeps 1e-10
   J row     per row and component, 1e-10 times the sum of the absolute
             values of the contact gradients added into that row (each
             contribution taken at its own contact's tolerance factor)
@@ -112,7 +113,9 @@ def compare(gpu, ora, scene, dt, eps, check_cand=False, pair_subset=None, counte
         assert np.all(np.abs(V[vt] - V_r[vt]) <= vtol), np.abs(V[vt] - V_r[vt]).max()
         fs = ora["ct_fs_rel"][vt]
         kappa = np.where(fs > 0, ell / np.maximum(fs, 1e-300), np.inf)
-        tf = np.where(kappa > KAPPA_ILL, 1e-14 * kappa, TOL)
+        # a contact clamped at s* = 0 (within d at t_n) has no contact-time term
+        kappa = np.where(ora["ct_s"][vt] == 0.0, 0.0, kappa)
+        tf = np.where(kappa > KAPPA_ILL, 1e-14 * np.minimum(kappa, 1e6), TOL)
         stats["ill_conditioned"] = int((kappa > KAPPA_ILL).sum())
         stats["kappa_max"] = float(kappa.max())
         gscale = np.abs(G_r[vt]).max(axis=1)

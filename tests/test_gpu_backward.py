@@ -115,9 +115,7 @@ def test_autograd_function_vs_finite_differences(ctx):
 
 
 def test_backward_deterministic_1440(ctx):
-    """Two backward calls on the same 1440-vesicle detect give the same bits:
-    every vertex's sum runs in one fixed order (no floating-point atomics),
-    also for vertices in several contact volumes."""
+    """Two backward calls on the same 1440-vesicle detect give the same bits."""
     import torch
     from paper_1812_04719_amd import stiv
     sc = S.make_config(3)
@@ -129,34 +127,65 @@ def test_backward_deterministic_1440(ctx):
     a0, a1 = stiv.backward(ctx, ds, sc.d, sc.eps, sc.dt, res["_struct"], gV, gG)
     b0, b1 = stiv.backward(ctx, ds, sc.d, sc.eps, sc.dt, res["_struct"], gV, gG)
     assert torch.equal(a0, b0) and torch.equal(a1, b1)
-    # vertices in more than one volume exist in this scene
+
+
+def test_backward_vertices_in_several_volumes(ctx):
+    """A tetrahedron with a sphere pressing on each face: each of its vertices
+    has Jacobian rows in three or four contact volumes, whose adjoints are
+    added into one vertex.  The sum runs in a fixed order (rows by volume),
+    so 20 calls give the same bits, and it matches the oracle's backward."""
+    import torch
+    import tinyscenes as T
+    from paper_1812_04719_amd import stiv
+    sc = T.tetra_crowd(2)
+    ds = stiv.DeviceScene(sc)
+    res, _ = stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, to_numpy=False)
     jv = res["j_vtx"].cpu().numpy()
     _, counts = np.unique(jv, return_counts=True)
-    print("vertices in >= 2 volumes: %d, >= 3: %d" % ((counts >= 2).sum(), (counts >= 3).sum()), flush=True)
-    assert (counts >= 2).sum() > 0
+    assert (counts >= 3).sum() >= 3
+    rng = np.random.default_rng(12)
+    gV = rng.normal(size=int(res["n_vol"]))
+    gG = rng.normal(size=(int(res["n_jrow"]), 3))
+    tV, tG = torch.tensor(gV, device="cuda:0"), torch.tensor(gG, device="cuda:0")
+    a0, a1 = stiv.backward(ctx, ds, sc.d, sc.eps, sc.dt, res["_struct"], tV, tG)
+    for _ in range(19):
+        b0, b1 = stiv.backward(ctx, ds, sc.d, sc.eps, sc.dt, res["_struct"], tV, tG)
+        assert torch.equal(a0, b0) and torch.equal(a1, b1)
+    ora = oracle.detect(sc)
+    o0, o1 = parity.oracle_backward(sc, ora, gV, gG)
+    for got, want in ((a0.cpu().numpy(), o0), (a1.cpu().numpy(), o1)):
+        scale = np.abs(want).max()
+        assert scale > 0
+        assert np.abs(got - want).max() <= 1e-10 * scale, np.abs(got - want).max() / scale
 
 
-def _fd_contact_adjoint(x0, x1, d, eps, dt, gV, w, h=1e-6):
-    """Central differences (h) of L = gV V_k + sum_r w_r . dV_k/dX1_r with
-    respect to X0 and X1 of the contact's four vertices, the contact time
-    re-found at every perturbed position (oracle)."""
-    def L(a, b):
+def _fd_contact_jacobian(x0, x1, d, eps, dt, h=1e-6):
+    """Central differences (h) of (V_k, dV_k/dX1 [12]) with respect to X0 and
+    X1 of the contact's four vertices: [13, 2, 4, 3], the contact time re-found
+    at every perturbed position (oracle).  None when a step of h loses the
+    contact or moves its time by more than 1e-3 (a contact within h of an
+    inside-test or root boundary has no usable difference quotient)."""
+    s0 = oracle.narrow(x0, x1, ee=False, d=d)
+
+    def f(a, b):
         s = oracle.narrow(a, b, ee=False, d=d)
-        assert s is not None
+        if s is None or abs(s - s0) > 1e-3:
+            return None
         V, _, g1 = oracle.vt_grad_full(a, b, s, d, eps, dt)
-        return gV * V + float((w * g1).sum())
+        return np.concatenate([[V], g1.ravel()])
 
-    out = []
+    J = np.zeros((13, 2, 4, 3))
     for which in (0, 1):
-        fd = np.zeros((4, 3))
         for r in range(4):
             for c in range(3):
                 ap, am = [x0.copy(), x1.copy()], [x0.copy(), x1.copy()]
                 ap[which][r, c] += h
                 am[which][r, c] -= h
-                fd[r, c] = (L(*ap) - L(*am)) / (2 * h)
-        out.append(fd)
-    return out
+                fp, fm = f(*ap), f(*am)
+                if fp is None or fm is None:
+                    return None
+                J[:, which, r, c] = (fp - fm) / (2 * h)
+    return J
 
 
 @pytest.mark.timeout(900)
@@ -165,7 +194,8 @@ def test_backward_vs_finite_differences_config5(ctx, case):
     """Adjoint of V and dV/dX1 against central finite differences (h = 1e-6,
     FP64): every vertex-triangle contact of the two-sphere scene, and a seeded
     sample of about 10^4 contacts of the 1440-vesicle scene (whole volumes
-    drawn at random until 10^4 contacts are covered; cotangents are zero on
+    drawn at random until 10^4 contacts are covered, leaving out the few
+    volumes with a contact that a step of h destroys; cotangents are zero on
     all other volumes and rows, so the GPU adjoint is the sum over exactly
     the sampled contacts)."""
     import torch
@@ -176,12 +206,36 @@ def test_backward_vs_finite_differences_config5(ctx, case):
     keys, vp = res["ct_key"], res["vol_pair"]
     vt = keys[:, 1] < 2
     rng = np.random.default_rng(51)
-    vol_ids = np.arange(len(vp))
-    if case == "1440_sample":
-        order = rng.permutation(len(vp))
-        n_of = np.bincount(keys[vt, 0], minlength=int(res["n_pairs"]))[vp]
-        take = np.cumsum(n_of[order]) <= 10000
-        vol_ids = np.sort(order[take])
+    order = np.arange(len(vp)) if case == "two_spheres_all" else rng.permutation(len(vp))
+    target = 10 ** 9 if case == "two_spheres_all" else 10000
+    cts_of = {}
+    for k in np.nonzero(vt)[0]:
+        cts_of.setdefault(int(keys[k, 0]), []).append(k)
+    jac, vol_ids, skipped = {}, [], 0
+    n_done = 0
+    for v in order:
+        if n_done >= target:
+            break
+        Js = {}
+        for k in cts_of[int(vp[v])]:
+            gid, x0, x1 = parity.contact_positions(sc, res["pair_ab"], res["pair_shift"], keys[k])
+            J = _fd_contact_jacobian(x0, x1, sc.d, sc.eps, sc.dt)
+            if J is None:
+                break
+            Js[k] = (gid, J)
+        else:
+            jac.update(Js)
+            vol_ids.append(int(v))
+            n_done += len(Js)
+            continue
+        skipped += 1
+    vol_ids = np.sort(np.array(vol_ids))
+    print("FD-checked contacts: %d in %d volumes (%d volumes left out)" % (n_done, len(vol_ids), skipped),
+          flush=True)
+    if case == "two_spheres_all":
+        assert skipped == 0 and n_done == int(vt.sum())
+    else:
+        assert n_done >= 9000 and skipped <= 0.05 * len(vol_ids)
     gV = np.zeros(len(vp))
     gV[vol_ids] = rng.normal(size=len(vol_ids))
     rows = np.isin(res["j_vol"], vol_ids)
@@ -190,27 +244,19 @@ def test_backward_vs_finite_differences_config5(ctx, case):
     dX0, dX1 = stiv.backward(ctx, ds, sc.d, sc.eps, sc.dt, res["_struct"], torch.tensor(gV, device="cuda:0"),
                              torch.tensor(gG, device="cuda:0"))
     dX0, dX1 = dX0.cpu().numpy(), dX1.cpu().numpy()
-    # finite differences per sampled contact, summed per vertex
-    f0 = np.zeros_like(dX0)
-    f1 = np.zeros_like(dX1)
+    # the FD adjoint: cotangents contracted with each contact's FD Jacobian, summed per vertex
+    f = [np.zeros_like(dX0), np.zeros_like(dX1)]
     vol_of_pair = {int(p): v for v, p in enumerate(vp)}
     row_of = {(int(v), int(g)): r for r, (v, g) in enumerate(zip(res["j_vol"], res["j_vtx"]))}
-    sel = set(vol_ids.tolist())
-    n_done = 0
-    for k in np.nonzero(vt)[0]:
+    for k, (gid, J) in jac.items():
         v = vol_of_pair[int(keys[k, 0])]
-        if v not in sel:
-            continue
-        gid, x0, x1 = parity.contact_positions(sc, res["pair_ab"], res["pair_shift"], keys[k])
-        w = np.array([gG[row_of[(v, int(g))]] for g in gid])
-        a0, a1 = _fd_contact_adjoint(x0, x1, sc.d, sc.eps, sc.dt, gV[v], w)
-        for r in range(4):
-            f0[:, gid[r]] += a0[r]
-            f1[:, gid[r]] += a1[r]
-        n_done += 1
-    print("FD-checked contacts: %d in %d volumes" % (n_done, len(vol_ids)), flush=True)
-    assert n_done >= (79 if case == "two_spheres_all" else 9000)
-    for got, want in ((dX0, f0), (dX1, f1)):
+        w = np.array([gG[row_of[(v, int(g))]] for g in gid]).ravel()
+        cot = np.concatenate([[gV[v]], w])
+        adj = np.tensordot(cot, J, axes=(0, 0))  # [2, 4, 3]
+        for which in (0, 1):
+            for r in range(4):
+                f[which][:, gid[r]] += adj[which, r]
+    for got, want in ((dX0, f[0]), (dX1, f[1])):
         scale = np.abs(want).max()
         assert scale > 0
         assert np.abs(got - want).max() <= 1e-6 * scale, np.abs(got - want).max() / scale

@@ -106,6 +106,19 @@ def test_parity_tetra_periodic_self_image(ctx):
     check(ctx, sc)
 
 
+def test_parity_tetra_crowd(ctx):
+    """Vertices with Jacobian rows in three or four contact volumes (a
+    tetrahedron with a sphere on each face): J rows summed per volume."""
+    g, o = check(ctx, T.tetra_crowd(2))
+    _, counts = np.unique(o["j_vtx"], return_counts=True)
+    assert (counts >= 3).sum() >= 3
+
+
+def test_parity_mixed_order_periodic(ctx):
+    """Order-8 and order-12 spheres meeting across a periodic boundary."""
+    check(ctx, T.mixed_order_periodic())
+
+
 def test_parity_rsa_64(ctx):
     check(ctx, S.make_config(2))
 

@@ -85,3 +85,31 @@ def mixed_order_periodic(seed=123):
     a1 = a0 + np.array([-0.06, 0.0, 0.01]) + rng.normal(0, 2e-3, a0.shape)
     b1 = b0 + np.array([0.06, 0.01, 0.0]) + rng.normal(0, 2e-3, b0.shape)
     return two_body_scene(a0, a1, ta, b0, b1, tb, box_len=(L, 0, 0), d=0.0099)
+
+
+def tetra_crowd(seed=0, p=6, gap=0.02, closing=0.08):
+    """A tetrahedron with a sphere (order p) approaching each of its four
+    faces: every vertex of the tetrahedron is a corner of three faces, so it
+    gets a Jacobian row in three contact volumes."""
+    from scipy.spatial.transform import Rotation
+
+    from paper_1812_04719_amd import scenes as S
+    rng = np.random.default_rng(seed)
+    pt, tt = tetra((0.0, 0.0, 0.0), 1.0)
+    ball = S.spheroid_body_points(p, 1.0, 1.0)
+    tg = S.grid_topology(p)
+    x0, x1, counts = [pt], [pt + rng.normal(0, 1e-3, pt.shape)], [4]
+    for k in range(4):
+        a, b, c = pt[tt.tri[k]]
+        n = np.cross(b - a, c - a)
+        n /= np.linalg.norm(n)
+        ctr = (a + b + c) / 3.0
+        body = ball @ Rotation.random(random_state=seed + 1 + k).as_matrix().T + ctr + n * (1.0 + gap)
+        x0.append(body)
+        x1.append(body - n * closing + rng.normal(0, 1e-3, body.shape))
+        counts.append(body.shape[0])
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    return Scene(x0=np.ascontiguousarray(np.concatenate(x0).T), x1=np.ascontiguousarray(np.concatenate(x1).T),
+                 vtx_off=off, topo_id=np.array([0, 1, 1, 1, 1], dtype=np.int32),
+                 scene_off=np.array([0, 5], dtype=np.int32), box_len=np.zeros((1, 3)), topos=[tt, tg],
+                 d=0.0099, eps=1.0, dt=0.1)
