@@ -213,6 +213,27 @@ stiv_status stiv_collect(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, 
 stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
                           const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): stiv_backward with all of its scratch in one static device
+ * array of STIV_BACKWARD_STATIC_BYTES per GPU, owned by the library and held
+ * until the process ends.  Same arguments, kernels, results and summation
+ * order as stiv_backward (bit-identical outputs).  It allocates nothing, makes
+ * no host copy and does not synchronise: the scene's structural arrays
+ * (vtx_off, topo_id, scene_off, box_len and the sizes) must be the ones a
+ * previous stiv_detect or stiv_reserve on this context validated
+ * (STIV_E_STATE otherwise).  Scratch needed: about 288 bytes per contact
+ * (n_ct_vt + n_ct_ee) plus 72 bytes per Jacobian row, rounded up;
+ * STIV_E_CAPACITY with a message giving the need when it exceeds the array
+ * (the 1440-vesicle workload, 196K contacts and 55K rows, fits).  All calls
+ * on one GPU share the array and each call writes every part of it it reads:
+ * calls that overlap in time on one GPU (other streams, other contexts,
+ * other threads) race and must be serialised by the caller. */
+#define STIV_BACKWARD_STATIC_BYTES (64ull << 20)
+stiv_status stiv_backward_static(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
+                                 const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1,
+                                 void *stream);
+
 /* Milliseconds of the last detect, measured with HIP events on the call's
  * stream: 0 box kernel, 1 vesicle broad phase (Morton grid), 2 patch-pair
  * cull, 3 primitive candidates, 4 narrow phase with volumes and gradients,

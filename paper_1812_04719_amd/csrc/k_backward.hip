@@ -14,11 +14,20 @@
 // (stably, so volumes stay in order) and each vertex adds its rows in that
 // order and is written once.  No floating-point atomics: repeated calls give
 // the same bits.
+#include <mutex>
+
 #include "narrow_math.h"
 
 namespace stiv {
 
 namespace {
+
+// Scratch of stiv_backward_static: one array per GPU, held by the process
+// for as long as it runs.  Host code never passes `scratch` itself to a
+// kernel (on the host that name is not a device address): it passes the
+// address hipGetSymbolAddress reports for the current device.
+constexpr size_t kBwdStaticBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kBwdStaticBytes];
 
 constexpr int kBwdThreads = 256;
 constexpr int kBwdLds = 2048;
@@ -177,6 +186,56 @@ __global__ void k_bwd_vertex_sum(const uint64_t *rkey, const uint32_t *rval, int
 }
 
 }  // namespace
+
+size_t backward_static_bytes() { return kBwdStaticBytes; }
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current and kept for the life of the process.
+hipError_t backward_static_scratch(int device, void **ptr) {
+  static std::mutex mu;
+  static void *addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) {
+      e = hipSetDevice(device);
+      if (e != hipSuccess) return e;
+    }
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
+BwdLayout backward_layout(int64_t n_ct, int64_t n_jrow) {
+  BwdLayout L{};
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = at;
+    at += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t nc = (size_t)(n_ct + 1), nj = (size_t)(n_jrow + 1);
+  L.contrib = take(6 * 8 * 4 * nc);
+  L.gkeys = take(8 * 8 * nc);
+  L.gidx = take(4 * 8 * nc);
+  L.rowc = take(6 * 8 * nj);
+  L.rkey = take(8 * nj);
+  L.rval = take(4 * nj);
+  L.tk = take(8 * nj);
+  L.tv = take(4 * nj);
+  L.hist = take(4 * (size_t)(256 * radix_scratch_blocks((int64_t)nj)));
+  L.hoff = take(8 * (size_t)radix_offset_elems((int64_t)nj));
+  L.total = at;
+  return L;
+}
 
 void launch_backward(const DevScene &S, const DevTopo &T, double d, double eps, double dt, int64_t n_ct,
                      const int32_t *ct_key, const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift,

@@ -255,7 +255,16 @@ void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_
                           const int32_t *pair_rows, const int32_t *row_vtx_tmp, const double *row_g_tmp,
                           int32_t *vol_pair, double *vol_V, int64_t cap_vol, int32_t *j_vol, int32_t *j_vtx,
                           double *j_g, int64_t cap_jrow, const int64_t *cp_total, hipStream_t st);
-// Backward pass
+// Backward pass.  Its scratch, carved from one buffer at these byte offsets
+// (256-aligned) for n_ct contacts and n_jrow Jacobian rows.
+struct BwdLayout {
+  size_t contrib, gkeys, gidx, rowc, rkey, rval, tk, tv, hist, hoff, total;
+};
+BwdLayout backward_layout(int64_t n_ct, int64_t n_jrow);
+// The static scratch of stiv_backward_static: its size, and its device
+// address on `device` (looked up once per device).
+size_t backward_static_bytes();
+hipError_t backward_static_scratch(int device, void **ptr);
 void launch_backward(const DevScene &S, const DevTopo &T, double d, double eps, double dt, int64_t n_ct,
                      const int32_t *ct_key, const double *ct_tau, const int32_t *pair_ab, const int32_t *pair_shift,
                      int64_t n_vol, const int32_t *vol_pair, int64_t n_jrow, const int32_t *j_vol,

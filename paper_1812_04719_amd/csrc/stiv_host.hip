@@ -28,7 +28,7 @@ struct Buf {
 hipError_t ensure(Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return hipSuccess;
-  if (b.p) hipFree(b.p);
+  if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
   hipError_t e = hipMalloc(&b.p, bytes);
@@ -68,8 +68,7 @@ struct stiv_ctx {
       cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
-      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_contrib, bwd_keys, bwd_idx, bwd_rowc, bwd_rkey, bwd_rval,
-      hard_geo, rs_hist, rs_off, scan_tmp;
+      row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_scratch, hard_geo, rs_hist, rs_off, scan_tmp;
   // learned contact-time bracket: FP32 parameters on the device, width in units of sd
   Buf toi_params, toi_packed, mlp_part;
   // LCP matrix assembly scratch
@@ -138,13 +137,19 @@ stiv_status stiv_create(stiv_ctx **out, int dev) {
       delete ctx;
       return STIV_E_HIP;
     }
+  // the device address of stiv_backward_static's scratch, once per device
+  void *scratch_addr = nullptr;
+  if (backward_static_scratch(dev, &scratch_addr) != hipSuccess) {
+    stiv_destroy(ctx);
+    return STIV_E_HIP;
+  }
   *out = ctx;
   return STIV_OK;
 }
 
 stiv_status stiv_destroy(stiv_ctx *ctx) {
   if (!ctx) return STIV_E_ARG;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   Buf *all[] = {&ctx->t_nv, &ctx->t_nt, &ctx->t_ne, &ctx->t_tri_off, &ctx->t_edge_off, &ctx->t_tri, &ctx->t_edge,
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
@@ -161,12 +166,12 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->ct_s, &ctx->ct_vol, &ctx->ct_grad, &ctx->pair_cnt, &ctx->pair_cursor, &ctx->pair_off,
                 &ctx->perm, &ctx->gkeys, &ctx->gidx, &ctx->pair_V, &ctx->pair_hasvt, &ctx->pair_rows,
                 &ctx->vol_off, &ctx->row_off, &ctx->row_vtx, &ctx->row_g, &ctx->sort_tk, &ctx->sort_tv,
-                &ctx->bwd_contrib, &ctx->bwd_keys, &ctx->bwd_idx, &ctx->bwd_rowc, &ctx->bwd_rkey, &ctx->bwd_rval};
+                &ctx->bwd_scratch};
   for (Buf *b : all)
-    if (b->p) hipFree(b->p);
+    if (b->p) (void)hipFree(b->p);
   for (auto &e : ctx->ev)
-    if (e) hipEventDestroy(e);
-  if (ctx->h_cnt) hipHostFree(ctx->h_cnt);
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->h_cnt) (void)hipHostFree(ctx->h_cnt);
   delete ctx;
   return STIV_OK;
 }
@@ -788,15 +793,11 @@ stiv_status stiv_get_stage_times(stiv_ctx *ctx, float *ms, int n) {
   return STIV_OK;
 }
 
-stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
-                          const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, void *stream) {
-  if (!ctx) return STIV_E_ARG;
+static stiv_status check_backward_args(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p,
+                                       const stiv_result *res) {
   if (!res) return fail(ctx, STIV_E_ARG, "null result");
   stiv_status st0 = check_args(ctx, s, p);
   if (st0 != STIV_OK) return st0;
-  HIPCHK(hipSetDevice(ctx->device));
-  stiv_status sv = check_structure(ctx, s);
-  if (sv != STIV_OK) return sv;
   const int64_t n_ct = res->n_ct_vt + res->n_ct_ee;
   if (res->n_pairs > res->cap_pairs || n_ct > res->cap_ct || res->n_vol > res->cap_vol || res->n_jrow > res->cap_jrow)
     return fail(ctx, STIV_E_ARG, "backward needs a complete detect result (no capacity overflow)");
@@ -804,27 +805,72 @@ stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params 
     return fail(ctx, STIV_E_ARG, "backward needs the contact and pair arrays of the detect result");
   if (res->n_vol > 0 && (!res->vol_pair || !res->j_vol || !res->j_vtx))
     return fail(ctx, STIV_E_ARG, "backward needs the volume and Jacobian arrays of the detect result");
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  HIPCHK(ensure(ctx->bwd_contrib, 6 * 8 * 4 * (size_t)(n_ct + 1)));
-  HIPCHK(ensure(ctx->bwd_keys, 8 * 8 * (size_t)(n_ct + 1)));
-  HIPCHK(ensure(ctx->bwd_idx, 4 * 8 * (size_t)(n_ct + 1)));
-  const int64_t nj = res->n_jrow;
-  HIPCHK(ensure(ctx->bwd_rowc, 6 * 8 * (size_t)(nj + 1)));
-  HIPCHK(ensure(ctx->bwd_rkey, 8 * (size_t)(nj + 1)));
-  HIPCHK(ensure(ctx->bwd_rval, 4 * (size_t)(nj + 1)));
-  HIPCHK(ensure(ctx->sort_tk, 8 * (size_t)(nj + 1)));
-  HIPCHK(ensure(ctx->sort_tv, 4 * (size_t)(nj + 1)));
-  HIPCHK(ensure_sort_scratch(ctx, nj));
+  return STIV_OK;
+}
+
+static DevScene dev_scene(const stiv_scene *s) {
   DevScene S;
   S.n_ves = s->n_ves; S.n_vtx = s->n_vtx; S.n_scenes = s->n_scenes;
   S.vtx_off = s->vtx_off; S.topo_id = s->topo_id; S.scene_off = s->scene_off;
   S.box_len = s->box_len; S.x0 = s->x0; S.x1 = s->x1;
-  launch_backward(S, ctx->topo, p->d, p->eps, p->dt, n_ct, res->ct_key, res->ct_tau, res->pair_ab, res->pair_shift,
-                  res->n_vol, res->vol_pair, res->n_jrow, res->j_vol, res->j_vtx, dL_dV, dL_dG, res->ct_s,
-                  P<double>(ctx->bwd_contrib), P<uint64_t>(ctx->bwd_keys), P<int32_t>(ctx->bwd_idx),
-                  P<double>(ctx->bwd_rowc), P<uint64_t>(ctx->bwd_rkey), P<uint32_t>(ctx->bwd_rval),
-                  P<uint64_t>(ctx->sort_tk), P<uint32_t>(ctx->sort_tv), P<int32_t>(ctx->rs_hist),
-                  P<int64_t>(ctx->rs_off), dL_dX0, dL_dX1, st);
+  return S;
+}
+
+// The backward kernels on scratch at `base` (layout L).
+static void run_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
+                         const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, char *base,
+                         const BwdLayout &L, hipStream_t st) {
+  const int64_t n_ct = res->n_ct_vt + res->n_ct_ee;
+  launch_backward(dev_scene(s), ctx->topo, p->d, p->eps, p->dt, n_ct, res->ct_key, res->ct_tau, res->pair_ab,
+                  res->pair_shift, res->n_vol, res->vol_pair, res->n_jrow, res->j_vol, res->j_vtx, dL_dV, dL_dG,
+                  res->ct_s, reinterpret_cast<double *>(base + L.contrib), reinterpret_cast<uint64_t *>(base + L.gkeys),
+                  reinterpret_cast<int32_t *>(base + L.gidx), reinterpret_cast<double *>(base + L.rowc),
+                  reinterpret_cast<uint64_t *>(base + L.rkey), reinterpret_cast<uint32_t *>(base + L.rval),
+                  reinterpret_cast<uint64_t *>(base + L.tk), reinterpret_cast<uint32_t *>(base + L.tv),
+                  reinterpret_cast<int32_t *>(base + L.hist), reinterpret_cast<int64_t *>(base + L.hoff), dL_dX0,
+                  dL_dX1, st);
+}
+
+stiv_status stiv_backward(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
+                          const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1, void *stream) {
+  if (!ctx) return STIV_E_ARG;
+  stiv_status sa = check_backward_args(ctx, s, p, res);
+  if (sa != STIV_OK) return sa;
+  HIPCHK(hipSetDevice(ctx->device));
+  stiv_status sv = check_structure(ctx, s);
+  if (sv != STIV_OK) return sv;
+  const BwdLayout L = backward_layout(res->n_ct_vt + res->n_ct_ee, res->n_jrow);
+  HIPCHK(ensure(ctx->bwd_scratch, L.total));
+  run_backward(ctx, s, p, res, dL_dV, dL_dG, dL_dX0, dL_dX1, P<char>(ctx->bwd_scratch), L,
+               reinterpret_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return STIV_OK;
+}
+
+stiv_status stiv_backward_static(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p, const stiv_result *res,
+                                 const double *dL_dV, const double *dL_dG, double *dL_dX0, double *dL_dX1,
+                                 void *stream) {
+  if (!ctx) return STIV_E_ARG;
+  stiv_status sa = check_backward_args(ctx, s, p, res);
+  if (sa != STIV_OK) return sa;
+  // no host copies here: the scene's structural arrays must be the ones a
+  // previous stiv_detect (or stiv_reserve) on this context validated
+  const void *ptrs[4] = {s->vtx_off, s->topo_id, s->scene_off, s->box_len};
+  const int64_t sizes[3] = {s->n_ves, s->n_vtx, s->n_scenes};
+  if (std::memcmp(ptrs, ctx->val_ptr, sizeof ptrs) != 0 || std::memcmp(sizes, ctx->val_size, sizeof sizes) != 0)
+    return fail(ctx, STIV_E_STATE, "stiv_backward_static needs a prior stiv_detect or stiv_reserve on this scene");
+  const BwdLayout L = backward_layout(res->n_ct_vt + res->n_ct_ee, res->n_jrow);
+  if (L.total > backward_static_bytes())
+    return fail(ctx, STIV_E_CAPACITY,
+                "stiv_backward_static: " + std::to_string(res->n_ct_vt + res->n_ct_ee) + " contacts and " +
+                    std::to_string(res->n_jrow) + " Jacobian rows need " + std::to_string(L.total) +
+                    " bytes of scratch, more than its static " + std::to_string(backward_static_bytes()) +
+                    " (use stiv_backward)");
+  HIPCHK(hipSetDevice(ctx->device));
+  void *base = nullptr;
+  HIPCHK(backward_static_scratch(ctx->device, &base));
+  run_backward(ctx, s, p, res, dL_dV, dL_dG, dL_dX0, dL_dX1, static_cast<char *>(base), L,
+               reinterpret_cast<hipStream_t>(stream));
   HIPCHK(hipGetLastError());
   return STIV_OK;
 }

@@ -23,7 +23,8 @@ _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HI
            -5: "STIV_E_STATE"}
 
 EXPORTS = ("stiv_create", "stiv_destroy", "stiv_set_topology", "stiv_reserve", "stiv_detect",
-           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_detect_async",
+           "stiv_get_stage_times", "stiv_get_stats", "stiv_set_patch_size", "stiv_backward", "stiv_backward_static",
+           "stiv_detect_async",
            "stiv_collect", "stiv_set_option", "stiv_sort_pairs_u64", "stiv_mlp_nparam", "stiv_set_toi_model",
            "stiv_mlp_forward", "stiv_mlp_grad", "stiv_mlp_adam", "stiv_lcp_layout", "stiv_form_lcp",
            "stiv_last_error")
@@ -92,6 +93,9 @@ def lib():
                                             C.POINTER(stiv_result), C.c_void_p]
             L.stiv_collect.argtypes = [C.c_void_p, C.POINTER(stiv_params), C.POINTER(stiv_result), C.c_void_p]
             L.stiv_backward.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_params),
+                                        C.POINTER(stiv_result), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]
+            L.stiv_backward_static.argtypes = [C.c_void_p, C.POINTER(stiv_scene), C.POINTER(stiv_params),
                                         C.POINTER(stiv_result), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p]
             L.stiv_sort_pairs_u64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
@@ -356,21 +360,27 @@ class AsyncDetect:
         return res
 
 
-def backward(ctx: Context, dscene: DeviceScene, d, eps, dt, result_struct, dL_dV=None, dL_dG=None, stream=None):
-    """dL/dX0, dL/dX1 ([3, n_vtx] float64 tensors) for cotangents of V and G."""
+def backward(ctx: Context, dscene: DeviceScene, d, eps, dt, result_struct, dL_dV=None, dL_dG=None, stream=None,
+             static_scratch=False, out=None):
+    """dL/dX0, dL/dX1 ([3, n_vtx] float64 tensors) for cotangents of V and G.
+    static_scratch: call stiv_backward_static (no device allocation in the
+    library); out: optional preallocated (dX0, dX1)."""
     torch = _torch()
     dev = dscene.x0.device
-    dX0 = torch.empty_like(dscene.x0)
-    dX1 = torch.empty_like(dscene.x1)
+    if out is not None:
+        dX0, dX1 = out
+    else:
+        dX0 = torch.empty_like(dscene.x0)
+        dX1 = torch.empty_like(dscene.x1)
     p = stiv_params(float(d), float(eps), float(dt), 0)
     s = dscene.struct()
     st_ptr = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
     gv = dL_dV.contiguous() if dL_dV is not None else None
     gg = dL_dG.contiguous() if dL_dG is not None else None
-    st = lib().stiv_backward(ctx._h, C.byref(s), C.byref(p), C.byref(result_struct),
-                             C.c_void_p(gv.data_ptr() if gv is not None else 0),
-                             C.c_void_p(gg.data_ptr() if gg is not None else 0), C.c_void_p(dX0.data_ptr()),
-                             C.c_void_p(dX1.data_ptr()), C.c_void_p(st_ptr))
+    fn = lib().stiv_backward_static if static_scratch else lib().stiv_backward
+    st = fn(ctx._h, C.byref(s), C.byref(p), C.byref(result_struct),
+            C.c_void_p(gv.data_ptr() if gv is not None else 0), C.c_void_p(gg.data_ptr() if gg is not None else 0),
+            C.c_void_p(dX0.data_ptr()), C.c_void_p(dX1.data_ptr()), C.c_void_p(st_ptr))
     ctx._check(st)
     return dX0, dX1
 
