@@ -197,11 +197,19 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
 // 4. Buffered hits are processed 64 at a time with all lanes busy: the exact
 //    FP64 box test (the candidate definition), then the screens: candidates
 //    whose polynomial can have a root on [0,1] and whose closest-point test
-//    can pass somewhere on [0,1] are queued for the root-search kernel
-//    together with their FP64 geometry (structure of arrays), so the root
-//    search reads them coalesced; the rest are finished here.
+//    can pass somewhere on [0,1] are listed in LDS and the rest are finished
+//    here.
+// 5. At the end of the item the listed candidates are queued for the
+//    root-search kernel together with their FP64 geometry (structure of
+//    arrays, so the root search reads them coalesced), with one atomic for
+//    the item.  Nothing between the prefetch of the next item and its use
+//    waits on a global load or on a returning atomic: the wait counter of
+//    vector memory completes in order, so such a wait would also wait for
+//    the prefetch.  The primitive ids come from the staged blob for the same
+//    reason.
 // --------------------------------------------------------------------------
 constexpr int kHitBuf = 256;
+constexpr int kQueueBuf = 256;  // candidates of one item listed for the root search
 
 template <int TILE>
 struct WaveLds {
@@ -217,7 +225,8 @@ struct WaveLds {
   uint8_t lk[kL];          // patch-local indices of the left-hand list
   uint8_t rk[kR];          // and of the right-hand list
   uint32_t hits[kHitBuf];  // kind << 16 | left << 8 | right (patch-local indices)
-  alignas(16) int blob[2][Lay::lds];  // header and slot arrays of the two patch blobs
+  uint32_t queued[kQueueBuf];  // hits of the current item that need the root search (same encoding)
+  alignas(16) int blob[2][Lay::stage];  // header, slot and id arrays of the two patch blobs
 };
 
 // Overlap of two FP32 boxes in registers (branch-free).
@@ -246,13 +255,64 @@ __device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, in
   return reinterpret_cast<const uint8_t *>(&W.blob[side][off]);
 }
 
-// Exact FP64 box test of a buffered hit and the polynomial screen; queue the
-// candidates that need a root search.  All 64 lanes take part.  P[2] are the
-// patch-table indices of the current work item and p its pair.
+// Queue the listed candidates of the current item (W.queued[0 .. nq)) for
+// the root search: keys with global primitive ids, and the FP64 geometry from
+// LDS.  One atomic for all of them.  All 64 lanes take part.
+template <int TILE>
+__device__ void flush_queued(WaveLds<TILE> &W, int p, Cand *hard, double *geo, int64_t hard_cap, Counters *cnt,
+                             int nq) {
+  using Lay = BlobLayout<TILE>;
+  const int lane = threadIdx.x;
+  unsigned long long b = 0;
+  if (lane == 0) b = atomicAdd(&cnt->n_hard, (unsigned long long)nq);
+  b = __shfl(b, 0, 64);
+  for (int r0 = 0; r0 < nq; r0 += 64) {
+    const int k = r0 + lane;
+    if (k >= nq) break;
+    const uint32_t hv = W.queued[k];
+    const int kind = (int)((hv >> 16) & 3u), kl = (int)((hv >> 8) & 0xffu), kr = (int)(hv & 0xffu);
+    const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
+    const bool ee = kind == 2;
+    int slots[4];
+    if (ee) {
+      const uint8_t *el = blob_bytes(W, sl, Lay::eslot), *er = blob_bytes(W, sr, Lay::eslot);
+      slots[0] = el[2 * kl]; slots[1] = el[2 * kl + 1];
+      slots[2] = er[2 * kr]; slots[3] = er[2 * kr + 1];
+    } else {
+      const uint8_t *vl = blob_bytes(W, sl, Lay::vslot), *tr = blob_bytes(W, sr, Lay::tslot);
+      slots[0] = vl[kl];
+      slots[1] = tr[3 * kr]; slots[2] = tr[3 * kr + 1]; slots[3] = tr[3 * kr + 2];
+    }
+    const unsigned long long slot = b + (unsigned long long)k;
+    if ((int64_t)slot >= hard_cap) continue;
+    Cand c;
+    c.pair = p;
+    c.kind = kind;
+    c.i = W.blob[sl][(ee ? Lay::pedge : Lay::pvtx) + kl];
+    c.j = W.blob[sr][(ee ? Lay::pedge : Lay::ptri) + kr];
+    hard[slot] = c;
+    const int nfirst = ee ? 2 : 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int side = v >= nfirst ? sr : sl;
+      const double *pp = W.pos[side][slots[v]];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? W.sh[q] : 0.0);
+        geo[(12 + 3 * v + q) * hard_cap + slot] = pp[3 + q] - pp[q];
+      }
+    }
+  }
+}
+
+// Exact FP64 box test of a buffered hit and the polynomial screen; list the
+// candidates that need a root search in W.queued (*nq of them; flushed
+// early when the list could overflow).  All 64 lanes take part.  p is the
+// pair of the current work item.
 template <int N, int TILE>
-__device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2], int p, double d, Cand *hard,
-                             double *geo, int64_t hard_cap, Cand *list, int64_t list_cap, Counters *cnt,
-                             unsigned long long &nvt, unsigned long long &nee, int nh) {
+__device__ void process_hits(WaveLds<TILE> &W, int p, double d, Cand *hard, double *geo, int64_t hard_cap,
+                             Cand *list, int64_t list_cap, Counters *cnt, unsigned long long &nvt,
+                             unsigned long long &nee, int nh, int &nq) {
   using Lay = BlobLayout<TILE>;
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
@@ -261,16 +321,17 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2],
     const int k = r0 + lane;
     bool is_cand = false, need = false;
     int kind = 0, kl = 0, kr = 0, sl = 0, sr = 1;
-    int slots[4] = {0, 0, 0, 0};
+    uint32_t hv = 0;
     if (k < nh) {
       nm::Quad Q;
-      const uint32_t hv = W.hits[k];
+      hv = W.hits[k];
       kind = (int)((hv >> 16) & 3u);
       kl = (int)((hv >> 8) & 0xffu);
       kr = (int)(hv & 0xffu);
       sl = (kind == 1) ? 1 : 0;
       sr = 1 - sl;
       const bool ee = kind == 2;
+      int slots[4];
       if (ee) {
         const uint8_t *el = blob_bytes(W, sl, Lay::eslot), *er = blob_bytes(W, sr, Lay::eslot);
         slots[0] = el[2 * kl]; slots[1] = el[2 * kl + 1];
@@ -317,42 +378,12 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2],
         need = nm::needs_root_search<N>(Q, d) && nm::may_be_inside(Q);
       }
     }
-    // global primitive ids, only where a record is written; the loads are
-    // issued before the queue's atomic so that both latencies overlap
-    Cand c;
-    c.pair = p; c.kind = kind; c.i = 0; c.j = 0;
-    if (need || (list && is_cand)) {
-      const bool ee = kind == 2;
-      c.i = gblob[(int64_t)P[sl] * Lay::stride + (ee ? Lay::pedge : Lay::pvtx) + kl];
-      c.j = gblob[(int64_t)P[sr] * Lay::stride + (ee ? Lay::pedge : Lay::ptri) + kr];
-    }
+    // candidates for the root search: listed in LDS, queued at the end of the item
     const unsigned long long mh = __ballot(need);
-    if (mh) {
-      const int leader = __ffsll((long long)mh) - 1;
-      unsigned long long b = 0;
-      if (lane == leader) b = atomicAdd(&cnt->n_hard, (unsigned long long)__popcll(mh));
-      b = __shfl(b, leader, 64);
-      if (need) {
-        const unsigned long long slot = b + __popcll(mh & lanemask_lt());
-        if ((int64_t)slot < hard_cap) {
-          hard[slot] = c;
-          // the geometry again from LDS (same arithmetic as above), so that it
-          // is not held in registers through the screen
-          const int nfirst = c.kind == 2 ? 2 : 1;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int side = v >= nfirst ? sr : sl;
-            const double *pp = W.pos[side][slots[v]];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              geo[(3 * v + q) * hard_cap + slot] = pp[q] + (side ? W.sh[q] : 0.0);
-              geo[(12 + 3 * v + q) * hard_cap + slot] = pp[3 + q] - pp[q];
-            }
-          }
-        }
-      }
-    }
+    if (need) W.queued[nq + __popcll(mh & lanemask_lt())] = hv;
+    nq += __popcll(mh);
     if (list) {
+      // the optional candidate list (a diagnostic output): one atomic per round
       const unsigned long long mc = __ballot(is_cand);
       if (mc) {
         const int leader = __ffsll((long long)mc) - 1;
@@ -361,9 +392,21 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2],
         b = __shfl(b, leader, 64);
         if (is_cand) {
           const unsigned long long slot = b + __popcll(mc & lanemask_lt());
+          Cand c;
+          c.pair = p;
+          c.kind = kind;
+          const bool ee = kind == 2;
+          c.i = W.blob[sl][(ee ? Lay::pedge : Lay::pvtx) + kl];
+          c.j = W.blob[sr][(ee ? Lay::pedge : Lay::ptri) + kr];
           if ((int64_t)slot < list_cap) list[slot] = c;
         }
       }
+    }
+    if (nq > kQueueBuf - 64) {  // rare: a long list is queued before the item ends
+      __syncthreads();
+      flush_queued<TILE>(W, p, hard, geo, hard_cap, cnt, nq);
+      nq = 0;
+      __syncthreads();
     }
   }
   __syncthreads();
@@ -371,14 +414,14 @@ __device__ void process_hits(WaveLds<TILE> &W, const int *gblob, const int P[2],
 
 // Registers of a work item in flight: its record (lanes 0-7 hold the eight
 // ints of WorkRec), the pair's image shift (lanes 0-2), the FP64 boxes of both
-// patches (lanes 0-11), the header and slot ints of both blobs (one int4 per
-// lane), the referenced vertex ids and, once those have arrived, the positions
-// of the referenced vertices.
+// patches (lanes 0-11), the staged part of both blobs (header, slots and ids:
+// two int4 per lane), the referenced vertex ids and, once those have arrived,
+// the positions of the referenced vertices.
 template <int TILE>
 struct Prefetch {
   using Lay = BlobLayout<TILE>;
-  static_assert(Lay::lds / 4 <= 64 && Lay::ref <= 64, "one int4 of each blob and one vertex per lane");
-  int4 blob[2];
+  static_assert(Lay::stage / 4 <= 128 && Lay::ref <= 64, "two int4 of each blob and one vertex per lane");
+  int4 blob[2][2];
   int ref[2];
   double sh;
   double pbox;  // lanes 0-11: the FP64 box of patch lane / 6, component lane % 6
@@ -429,7 +472,10 @@ __device__ inline void load_blobs(Prefetch<TILE> &F, const DevTopo &T, const Pai
   for (int side = 0; side < 2; ++side) {
     if (side == 0 && keep0) continue;
     const int *gb = T.blob + (int64_t)P[side] * Lay::stride;
-    F.blob[side] = lane < Lay::lds / 4 ? reinterpret_cast<const int4 *>(gb)[lane] : int4{0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      F.blob[side][h] =
+          64 * h + lane < Lay::stage / 4 ? reinterpret_cast<const int4 *>(gb)[64 * h + lane] : int4{0, 0, 0, 0};
     // unused entries of the referenced list are 0: a valid vertex of the vesicle
     F.ref[side] = lane < Lay::ref ? gb[Lay::pref + lane] : 0;
   }
@@ -495,7 +541,9 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       if (side == 0 && same0) continue;
-      if (lane < Lay::lds / 4) reinterpret_cast<int4 *>(&W.blob[side][0])[lane] = F.blob[side];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (64 * h + lane < Lay::stage / 4) reinterpret_cast<int4 *>(&W.blob[side][0])[64 * h + lane] = F.blob[side][h];
       if (lane < Lay::ref)
 #pragma unroll
         for (int c = 0; c < 6; ++c) W.pos[side][lane][c] = F.pos[side][c];
@@ -545,6 +593,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     const int wr_after = load_workrec(work, w_after, nw, lane);
     __syncthreads();
     int nh = 0;  // buffered hits (wave-uniform)
+    int nq = 0;  // listed candidates of this item (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
       if (kind == 1 && more) load_positions<TILE>(F, S, wr_next, lane, same0_next);
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
@@ -614,7 +663,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           if (hb) W.hits[nh + __popcll(mb & lanemask_lt())] = rb;
           nh += __popcll(mb);
           if (nh > kHitBuf - 128) {
-            process_hits<N, TILE>(W, T.blob, P, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+            process_hits<N, TILE>(W, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh, nq);
             npre += (unsigned long long)nh;
             nh = 0;
           }
@@ -624,9 +673,10 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     }
     // the hits refer to this item's LDS data: finish them before the next item
     if (nh) {
-      process_hits<N, TILE>(W, T.blob, P, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh);
+      process_hits<N, TILE>(W, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh, nq);
       npre += (unsigned long long)nh;
     }
+    if (nq) flush_queued<TILE>(W, p, hard, geo, hard_cap, cnt, nq);
     w = w_next;
     w_next = w_after;
     wr_cur = wr_next;

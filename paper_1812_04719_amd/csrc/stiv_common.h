@@ -34,17 +34,18 @@ struct TileCaps<64> {
 // of referenced vertices, owned vertices, triangles, owned edges); byte
 // arrays packed four to an int: slot (index into the referenced list) of
 // every owned vertex, of the three corners of every triangle and of the two
-// ends of every owned edge; then the referenced vertices' local ids and the
-// owned vertex, triangle and owned edge ids.  The header and slots (the
-// first `lds` ints) are what a work item keeps in LDS; the ids are read from
-// global memory where needed.
+// ends of every owned edge; the owned vertex, triangle and owned edge ids;
+// then the referenced vertices' local ids.  The first `stage` ints (header,
+// slots and ids) are what a work item keeps in LDS; the referenced ids only
+// address the positions it loads.
 template <int TILE>
 struct BlobLayout {
   static constexpr int ref = TileCaps<TILE>::ref, ownv = TileCaps<TILE>::ownv, owne = TileCaps<TILE>::owne;
   static constexpr int hdr = 0, vslot = 4, tslot = vslot + ownv / 4, eslot = tslot + 3 * TILE / 4,
-                       lds = (eslot + 2 * owne / 4 + 3) / 4 * 4, pref = lds, pvtx = pref + ref, ptri = pvtx + ownv,
-                       pedge = ptri + TILE, used = pedge + owne, stride = (used + 63) / 64 * 64;
+                       lds = (eslot + 2 * owne / 4 + 3) / 4 * 4, pvtx = lds, ptri = pvtx + ownv, pedge = ptri + TILE,
+                       pref = pedge + owne, stage = pref, used = pref + ref, stride = (used + 63) / 64 * 64;
   static_assert(ownv % 4 == 0 && (3 * TILE) % 4 == 0 && (2 * owne) % 4 == 0, "byte arrays fill whole ints");
+  static_assert(stage % 4 == 0 && stage / 4 <= 128, "the staged part is at most two int4 per lane");
 };
 
 // Patch-pair work item: pair index, global patch-table indices of the two
