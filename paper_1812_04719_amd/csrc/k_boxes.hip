@@ -7,6 +7,8 @@
 // primitive broad phase.  One workgroup streams one vesicle's SoA positions
 // with coalesced 8-byte lanes, once; this is the one stage that reads every
 // byte of X0 and X1.
+#include <hip/hip_fp16.h>
+
 #include "stiv_common.h"
 
 namespace stiv {
@@ -48,18 +50,96 @@ __device__ inline void fold_box(unsigned long long (*pk)[6], int q, const unsign
   }
 }
 
+// Order-preserving map of floats to unsigned 32-bit keys (finite or infinite).
+__device__ inline unsigned int fkey(float x) {
+  const unsigned int b = __float_as_uint(x);
+  return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float fkey_inv(unsigned int k) {
+  const unsigned int b = (k >> 31) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(b);
+}
+
+// FP32 values at or below (above) x: the nearest float moved down (up) by
+// 2^-22 of its magnitude, at least two units in its last place (plus 1e-30
+// for values near zero); cheaper than a conversion with a directed rounding
+// mode.
+__device__ inline float f32_below(double x) {
+  const float f = (float)x;
+  return f - (fabsf(f) * 2.384185791015625e-07f + 1e-30f);
+}
+__device__ inline float f32_above(double x) {
+  const float f = (float)x;
+  return f + (fabsf(f) * 2.384185791015625e-07f + 1e-30f);
+}
+
+// Lower and upper support of the box anchor + [lo, hi] along the six face
+// diagonals, in FP64 and rounded outward to FP32.
+__device__ inline void dop_support(const float lo[3], const float hi[3], const double an[3], float out[kDopVals]) {
+  const double lx = lo[0], ly = lo[1], lz = lo[2], hx = hi[0], hy = hi[1], hz = hi[2];
+  const double axy = an[0] + an[1], axmy = an[0] - an[1], axz = an[0] + an[2], axmz = an[0] - an[2],
+               ayz = an[1] + an[2], aymz = an[1] - an[2];
+  const double dn[kDopDirs] = {(lx + ly) + axy, (lx - hy) + axmy, (lx + lz) + axz,
+                               (lx - hz) + axmz, (ly + lz) + ayz, (ly - hz) + aymz};
+  const double up[kDopDirs] = {(hx + hy) + axy, (hx - ly) + axmy, (hx + hz) + axz,
+                               (hx - lz) + axmz, (hy + hz) + ayz, (hy - lz) + aymz};
+#pragma unroll
+  for (int j = 0; j < kDopDirs; ++j) {
+    out[2 * j] = f32_below(dn[j]);
+    out[2 * j + 1] = f32_above(up[j]);
+  }
+}
+
+// Supports of a triangle's box, the union of its vertices' boxes: rows of
+// vb (indexed by local vertex id) hold each vertex's box relative to the
+// vesicle's anchor in FP16, rounded outward, as three half pairs (lo x, lo y),
+// (lo z, hi x), (hi y, hi z).
+__device__ inline void tri_support(const unsigned int *vb, int4 rec, const double an[3], float sp[kDopVals]) {
+  float v[3][6];
+  const int ids[3] = {rec.x, rec.y, rec.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const unsigned int u = vb[3 * ids[k] + w];
+      v[k][2 * w] = __half2float(__ushort_as_half((unsigned short)(u & 0xffffu)));
+      v[k][2 * w + 1] = __half2float(__ushort_as_half((unsigned short)(u >> 16)));
+    }
+  float tl[3], th[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    tl[c] = fminf(fminf(v[0][c], v[1][c]), v[2][c]);
+    th[c] = fmaxf(fmaxf(v[0][3 + c], v[1][3 + c]), v[2][3 + c]);
+  }
+  dop_support(tl, th, an, sp);
+}
+
 // One workgroup per vesicle: each thread streams vertices (coalesced SoA
 // loads of X0 and X1), folds them into the vesicle box and, through the
 // vertex -> patch incidence (packed four to a vertex), into the LDS boxes of
-// the patches that reference the vertex.
+// the patches that reference the vertex.  With `dop`, each vertex's
+// space-time box is also kept in LDS, relative to the vesicle's first vertex
+// in FP16 rounded outward (an offset wider than FP16's range becomes
+// infinite, which only loosens the bound), and a second pass forms every
+// patch's supports along the face diagonals from its triangles' boxes (the
+// union of their vertices' boxes).  The patch's 9-DOP (its box
+// and these supports) contains the boxes of all its primitives, since every
+// owned vertex and edge lies in one of its triangles: two patches whose
+// supports do not meet along some diagonal hold no primitive pair with
+// meeting boxes.
 // MAXP bounds the patches of any vesicle's topology (LDS is sized for it, so
 // small meshes keep more workgroups resident).
 constexpr int kBoxU = 4;
+constexpr int kTriPerThread = 4;
 
 template <int MAXP>
 __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, const int64_t *ves_patch_off,
-                                               double *ves_box, double *patch_box, Counters *cnt) {
+                                               double *ves_box, double *patch_box, float *patch_dop, bool dop,
+                                               Counters *cnt) {
   __shared__ unsigned long long pk[MAXP][6];  // lo as key, hi as key
+  constexpr int kDopP = MAXP <= 512 ? MAXP : 1;  // supports for meshes of up to 512 patches
+  __shared__ unsigned int dk[kDopP][kDopVals];   // the patches' supports as keys
+  extern __shared__ unsigned int vbox[];  // with dop: [n_vertices][3] half pairs, each vertex's box (tri_support)
   __shared__ double red[4][6];
   __shared__ int bad_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -70,8 +150,13 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
     const int t = S.topo_id[v];
     const int np = T.patch_off[t + 1] - T.patch_off[t];
     const int vb = T.vbase[t];
-    for (int k = threadIdx.x; k < np; k += blockDim.x)
+    // anchor of the FP16 vertex boxes: the vesicle's first vertex at t_n
+    const double an[3] = {S.x0[base], S.x0[nv_all + base], S.x0[2 * nv_all + base]};
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
       for (int c = 0; c < 3; ++c) { pk[k][c] = ~0ull; pk[k][3 + c] = 0ull; }
+      if (dop)
+        for (int j = 0; j < kDopDirs; ++j) { dk[k][2 * j] = ~0u; dk[k][2 * j + 1] = 0u; }
+    }
     if (threadIdx.x == 0) bad_any = 0;
     __syncthreads();
     double lo[3], hi[3];
@@ -110,6 +195,17 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
         }
         const unsigned long long kl[3] = {okey(l[0]), okey(l[1]), okey(l[2])};
         const unsigned long long ku[3] = {okey(u[0]), okey(u[1]), okey(u[2])};
+        if (dop) {
+          // the vertex box relative to the anchor, rounded outward to FP16
+          unsigned short hv[6];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            hv[c] = __half_as_ushort(__float2half_rd(f32_below((l[c] - h) - an[c])));
+            hv[3 + c] = __half_as_ushort(__float2half_ru(f32_above((u[c] + h) - an[c])));
+          }
+#pragma unroll
+          for (int w = 0; w < 3; ++w) vbox[3 * i + w] = (unsigned int)hv[2 * w] | ((unsigned int)hv[2 * w + 1] << 16);
+        }
         const int qs[4] = {q4[k].x, q4[k].y, q4[k].z, q4[k].w};
         if (qs[3] == -2) {  // more than four patches: the full list
           for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) fold_box(pk, T.vp[e], kl, ku);
@@ -118,6 +214,49 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
           for (int j = 0; j < 4; ++j) {
             if (qs[j] < 0) break;
             fold_box(pk, qs[j], kl, ku);
+          }
+        }
+      }
+    }
+    if (dop) {
+      // face-diagonal supports of each patch: the vesicle's triangles in patch
+      // order, kTriPerThread consecutive ones per thread (mostly of one patch:
+      // kept in registers, folded into the patch's LDS supports once per run)
+      __syncthreads();
+      const int pt0 = T.patch_off[t];
+      const int r_beg = T.ptri_off[pt0], r_end = T.ptri_off[pt0 + np];
+      for (int r0 = r_beg + kTriPerThread * threadIdx.x; r0 < r_end; r0 += kTriPerThread * blockDim.x) {
+        int4 rec[kTriPerThread];
+#pragma unroll
+        for (int u = 0; u < kTriPerThread; ++u) rec[u] = r0 + u < r_end ? T.tri_rec[r0 + u] : make_int4(0, 0, 0, -1);
+        float acc[kDopVals];
+        int cur = rec[0].w;
+#pragma unroll
+        for (int j = 0; j < kDopDirs; ++j) { acc[2 * j] = INFINITY; acc[2 * j + 1] = -INFINITY; }
+#pragma unroll
+        for (int u = 0; u <= kTriPerThread; ++u) {
+          const int pu = u < kTriPerThread ? rec[u].w : -1;
+          if (pu != cur) {  // end of a run of one patch: fold it (skipping what cannot improve)
+#pragma unroll
+            for (int j = 0; j < kDopDirs; ++j) {
+              const unsigned int kd = fkey(acc[2 * j]), ku = fkey(acc[2 * j + 1]);
+              const unsigned int cd = __hip_atomic_load(&dk[cur][2 * j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              const unsigned int cu =
+                  __hip_atomic_load(&dk[cur][2 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              if (kd < cd) atomicMin(&dk[cur][2 * j], kd);
+              if (ku > cu) atomicMax(&dk[cur][2 * j + 1], ku);
+              acc[2 * j] = INFINITY;
+              acc[2 * j + 1] = -INFINITY;
+            }
+            cur = pu;
+          }
+          if (pu < 0) break;
+          float sp[kDopVals];
+          tri_support(vbox, rec[u], an, sp);
+#pragma unroll
+          for (int j = 0; j < kDopDirs; ++j) {
+            acc[2 * j] = fminf(acc[2 * j], sp[2 * j]);
+            acc[2 * j + 1] = fmaxf(acc[2 * j + 1], sp[2 * j + 1]);
           }
         }
       }
@@ -141,11 +280,14 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
     }
     const int64_t slot0 = ves_patch_off[v];
     if (!bad_any)
-      for (int k = threadIdx.x; k < np; k += blockDim.x)
+      for (int k = threadIdx.x; k < np; k += blockDim.x) {
         for (int c = 0; c < 3; ++c) {
           patch_box[6 * (slot0 + k) + c] = okey_inv(pk[k][c]) - h;
           patch_box[6 * (slot0 + k) + 3 + c] = okey_inv(pk[k][3 + c]) + h;
         }
+        for (int j = 0; j < kDopVals; ++j)
+          patch_dop[kDopVals * (slot0 + k) + j] = dop ? fkey_inv(dk[k][j]) : ((j & 1) ? INFINITY : -INFINITY);
+      }
     __syncthreads();
   }
 }
@@ -164,18 +306,29 @@ __global__ void k_ves_tables(DevScene S, DevTopo T, int64_t *patch_cnt, int *ves
   }
 }
 
+
+
 }  // namespace
 
+// The FP16 vertex boxes for the patch supports (12 bytes per vertex) fit in
+// LDS up to this many vertices per mesh (order-32 meshes have 2114, order 44
+// 3962); meshes of more vertices or
+// more than 512 patches keep the axis-aligned patch boxes alone (their
+// supports are written as -inf, +inf, which never cull).
+constexpr int kDopMaxVertices = 4096;
+
 void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
-                  double *patch_box, int max_patches, Counters *cnt, hipStream_t st) {
+                  double *patch_box, float *patch_dop, int max_patches, Counters *cnt, hipStream_t st) {
   int g = S.n_ves < 8192 ? S.n_ves : 8192;
   if (g < 1) return;
+  const bool dop = T.tri_rec != nullptr && T.max_nv <= kDopMaxVertices && max_patches <= 512;
+  const size_t lds = dop ? sizeof(unsigned int) * 3 * (size_t)T.max_nv : 0;
   if (max_patches <= 128)
-    k_boxes<128><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
+    k_boxes<128><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, dop, cnt);
   else if (max_patches <= 512)
-    k_boxes<512><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
+    k_boxes<512><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, dop, cnt);
   else
-    k_boxes<kMaxPatchesPerVes><<<g, 256, 0, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, cnt);
+    k_boxes<kMaxPatchesPerVes><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, dop, cnt);
 }
 
 void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st) {

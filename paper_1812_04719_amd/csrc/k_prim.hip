@@ -57,19 +57,40 @@ __device__ inline bool ov6f_lds(const float *A, const float *B) {
   return (a0.x <= b1.y) & (b0.x <= a1.y) & (a0.y <= b2.x) & (b0.y <= a2.x) & (a1.x <= b2.y) & (b1.x <= a2.y);
 }
 
+// Overlap of two patches' face-diagonal supports (9-DOP minus the box):
+// A's unshifted, B's with the pair's shift already added.  The supports are
+// rounded outward; the comparison in FP64 allows 1e-6 (1 + |x|) more, far
+// above the roundings of the sums that formed them, so it never rejects a
+// pair of patches that hold primitives with meeting boxes.
+__device__ inline bool dop_meet(const float *A, const float *B) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < kDopDirs; ++j) {
+    const double adn = A[2 * j], aup = A[2 * j + 1], bdn = B[2 * j], bup = B[2 * j + 1];
+    ok &= (adn <= bup + 1e-6 * (1.0 + fabs(bup))) & (bdn <= aup + 1e-6 * (1.0 + fabs(aup)));
+  }
+  return ok;
+}
+
 // One workgroup per vesicle pair.  Each side's patch boxes that meet the
 // other vesicle's box are staged in LDS as FP32 boxes rounded outward (a
 // conservative filter: the primitive kernel applies the exact test later),
-// the surviving patch pairs are tested, and the work items are buffered in
-// LDS and written with one atomic per flush.
+// with their face-diagonal supports; the surviving patch pairs are tested
+// (boxes, then supports), and the work items are buffered in LDS and written
+// with one atomic per flush.
 // MAXP bounds the patches of any vesicle's topology (LDS is sized for it).
 template <int MAXP>
 __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo T, const PairRec *pairs,
                                                             const double *ves_box, const int64_t *ves_patch_off,
-                                                            const double *patch_box, WorkRec *work,
-                                                            int64_t work_cap, Counters *cnt, int64_t pairs_cap) {
+                                                            const double *patch_box, const float *patch_dop,
+                                                            WorkRec *work, int64_t work_cap, Counters *cnt,
+                                                            int64_t pairs_cap) {
   __shared__ alignas(8) float bA[MAXP][6];
   __shared__ alignas(8) float bB[MAXP][6];
+  constexpr bool kDop = MAXP <= 512;  // larger meshes have no face-diagonal supports
+  constexpr int kDopP = kDop ? MAXP : 1;
+  __shared__ alignas(8) float dA[kDopP][kDopVals];
+  __shared__ alignas(8) float dB[kDopP][kDopVals];
   __shared__ short iA[MAXP], iB[MAXP];
   __shared__ WorkRec buf[kPPBuf];
   __shared__ int nA, nB, nbuf;
@@ -106,6 +127,8 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
           bA[q][c] = __double2float_rd(P[c]);
           bA[q][3 + c] = __double2float_ru(P[3 + c]);
         }
+        if (kDop)
+          for (int j = 0; j < kDopVals; ++j) dA[q][j] = patch_dop[kDopVals * (pa0 + k) + j];
         iA[q] = (short)k;
       }
     }
@@ -126,6 +149,14 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
           bB[q][c] = __double2float_rd(Q[c]);
           bB[q][3 + c] = __double2float_ru(Q[3 + c]);
         }
+        // B's supports shifted by the image: (1,1,0).sh, (1,-1,0).sh, ...
+        const double shd[kDopDirs] = {pr.sh[0] + pr.sh[1], pr.sh[0] - pr.sh[1], pr.sh[0] + pr.sh[2],
+                                      pr.sh[0] - pr.sh[2], pr.sh[1] + pr.sh[2], pr.sh[1] - pr.sh[2]};
+        if (kDop)
+          for (int j = 0; j < kDopDirs; ++j) {
+            dB[q][2 * j] = __double2float_rd((double)patch_dop[kDopVals * (pb0 + k) + 2 * j] + shd[j]);
+            dB[q][2 * j + 1] = __double2float_ru((double)patch_dop[kDopVals * (pb0 + k) + 2 * j + 1] + shd[j]);
+          }
         iB[q] = (short)k;
       }
     }
@@ -135,7 +166,7 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
     for (int t0 = 0; t0 < tot; t0 += blockDim.x) {
       const int t = t0 + threadIdx.x;
       const int x = t < tot ? t / mb : 0, y = t < tot ? t - x * mb : 0;
-      const bool hit = t < tot && ov6f_lds(bA[x], bB[y]);
+      const bool hit = t < tot && ov6f_lds(bA[x], bB[y]) && (!kDop || dop_meet(dA[kDop ? x : 0], dB[kDop ? y : 0]));
       const int q = wave_slot(&nbuf, hit);
       {
         if (hit) {
@@ -699,19 +730,20 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
 
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
-                        WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt, hipStream_t st) {
+                        const float *patch_dop, WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt,
+                        hipStream_t st) {
   // grids measured on the 1440-vesicle scene (order-32 meshes): 1024
   // workgroups, each taking several pairs into its work-item buffer before a
   // flush, 0.045 ms; 2048: 0.054; 4096: 0.067; 512: 0.062
   if (max_patches <= 128)
-    k_patch_pairs<128><<<1024, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
-                                                    cnt, pairs_cap);
+    k_patch_pairs<128><<<1024, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, patch_dop, work,
+                                                    work_cap, cnt, pairs_cap);
   else if (max_patches <= 512)
-    k_patch_pairs<512><<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, work, work_cap,
-                                                    cnt, pairs_cap);
+    k_patch_pairs<512><<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box, patch_dop, work,
+                                                    work_cap, cnt, pairs_cap);
   else
     k_patch_pairs<kMaxPatchesPerVes><<<2048, kPPThreads, 0, st>>>(S, T, pairs, ves_box, ves_patch_off, patch_box,
-                                                                  work, work_cap, cnt, pairs_cap);
+                                                                  patch_dop, work, work_cap, cnt, pairs_cap);
 }
 
 template <int TILE>

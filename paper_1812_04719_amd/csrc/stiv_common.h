@@ -84,7 +84,18 @@ struct DevTopo {
                                        // more than 4, read vp_off / vp
   const int *blob;                     // [n_ptab][blob_stride] patch blobs (BlobLayout of the current tile)
   int blob_stride;
+  const int4 *tri_rec;                 // [sum nt] (three local vertex ids, local patch index) of every
+                                       // triangle, in patch order: patch P's from ptri_off[P] on
+  int max_nv;                          // largest vertex count of the topologies
 };
+
+// Patch bounds beyond the axis-aligned box: the support of the patch's
+// triangles' space-time boxes along the six face diagonals of the cube,
+// (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1), (0,1,-1) (a 9-DOP together
+// with the box).  Per patch 12 floats, [direction][low, high], rounded
+// outward (computed by the box kernel from FP32 vertex boxes).
+constexpr int kDopDirs = 6;
+constexpr int kDopVals = 2 * kDopDirs;
 
 struct DevScene {
   int n_ves, n_vtx, n_scenes;
@@ -177,8 +188,10 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // K0
 void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st);
+// patch_dop: every patch's face-diagonal supports (kDopVals floats per patch
+// slot).
 void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
-                  double *patch_box, int max_patches, Counters *cnt, hipStream_t st);
+                  double *patch_box, float *patch_dop, int max_patches, Counters *cnt, hipStream_t st);
 
 // K1
 void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st);
@@ -198,7 +211,8 @@ void launch_pair_bucket_sort_emit(const DevScene &S, const int *ves_scene, const
 // K2
 void launch_patch_pairs(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                         const double *ves_box, const int64_t *ves_patch_off, const double *patch_box,
-                        WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt, hipStream_t st);
+                        const float *patch_dop, WorkRec *work, int64_t work_cap, int max_patches, Counters *cnt,
+                        hipStream_t st);
 // hard_geo: geometry of the queued candidates for the root search, SoA
 // [24][hard_cap]: X0 (shifted) x, y, z of vertices 0..3, then D = X1 - X0.
 void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs,

@@ -56,7 +56,7 @@ struct stiv_ctx {
   // topology (device)
   Buf t_nv, t_nt, t_ne, t_tri_off, t_edge_off, t_tri, t_edge, t_patch_off, t_ptri_off, t_ptri, t_ptri_slot,
       t_pvtx_off, t_pvtx, t_pvtx_slot, t_pedge_off, t_pedge, t_pedge_slot, t_pref_off, t_pref, t_vbase, t_vp_off,
-      t_vp, t_vp4, t_blob;
+      t_vp, t_vp4, t_blob, t_tri_rec;
   DevTopo topo{};
   std::vector<int> h_npatch;  // patches per topology
   int max_patches = 0;
@@ -65,7 +65,8 @@ struct stiv_ctx {
   int narrow_blocks = 8192; // upper bound on workgroups of the root-search kernel
   // arena
   Buf counters, ves_box, ves_scene, grid, cp_cnt, cp_off, cp_keys, cp_vals, cp_tk, cp_tv, hash, uniq, sorted,
-      cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, work, cand, hard, cand_list, ct,
+      cnt_a, cursor_a, off_a, pairs, ves_patch_cnt, ves_patch_off, patch_box, patch_dop, work, cand, hard, cand_list,
+      ct,
       ct_s, ct_vol,
       ct_grad, pair_cnt, pair_cursor, pair_off, perm, gkeys, gidx, pair_V, pair_hasvt, pair_rows, vol_off,
       row_off, row_vtx, row_g, sort_tk, sort_tv, bwd_scratch, hard_geo, rs_hist, rs_off, scan_tmp;
@@ -154,10 +155,10 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
                 &ctx->t_patch_off, &ctx->t_ptri_off, &ctx->t_ptri, &ctx->t_ptri_slot, &ctx->t_pvtx_off,
                 &ctx->t_pvtx, &ctx->t_pvtx_slot, &ctx->t_pedge_off, &ctx->t_pedge, &ctx->t_pedge_slot,
                 &ctx->t_pref_off, &ctx->t_pref, &ctx->t_vbase, &ctx->t_vp_off, &ctx->t_vp, &ctx->t_vp4,
-                &ctx->t_blob, &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->scan_tmp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
+                &ctx->t_blob, &ctx->t_tri_rec, &ctx->hard_geo, &ctx->rs_hist, &ctx->rs_off, &ctx->scan_tmp, &ctx->counters, &ctx->ves_box, &ctx->ves_scene, &ctx->grid,
                 &ctx->cp_cnt, &ctx->cp_off, &ctx->cp_keys, &ctx->cp_vals, &ctx->cp_tk, &ctx->cp_tv, &ctx->hash,
                 &ctx->uniq, &ctx->sorted, &ctx->cnt_a, &ctx->cursor_a, &ctx->off_a, &ctx->pairs,
-                &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->work, &ctx->cand, &ctx->hard,
+                &ctx->ves_patch_cnt, &ctx->ves_patch_off, &ctx->patch_box, &ctx->patch_dop, &ctx->work, &ctx->cand, &ctx->hard,
                 &ctx->cand_list, &ctx->ct,
                 &ctx->toi_params, &ctx->toi_packed, &ctx->mlp_part, &ctx->lcp_flag, &ctx->lcp_a, &ctx->lcp_m9, &ctx->lcp_vcnt,
                 &ctx->lcp_vcur, &ctx->lcp_voff, &ctx->lcp_vlist, &ctx->lcp_c2, &ctx->lcp_coff, &ctx->lcp_ckey,
@@ -195,6 +196,8 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
       pref_off(1, 0), pref;
   std::vector<uint8_t> ptri_slot, pvtx_slot, pedge_slot;
   std::vector<int> vbase, vp_off(1, 0), vp, vp4;
+  std::vector<int> tri_rec;  // per triangle in patch order: its three local vertex ids, its local patch
+  int max_nv = 0;
   ctx->h_npatch.assign(nt_topo, 0);
   ctx->max_patches = 0;
   for (int t = 0; t < nt_topo; ++t) {
@@ -272,6 +275,11 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
     if (np > kMaxPatchesPerVes) return fail(ctx, STIV_E_ARG, "set_topology: mesh too large for the patch table");
     ctx->h_npatch[t] = np;
     ctx->max_patches = std::max(ctx->max_patches, np);
+    max_nv = std::max(max_nv, NV);
+    // the triangles' local vertex ids in patch order (the order of the patch
+    // table's triangle lists), for the face-diagonal supports of each patch
+    for (int pi = 0; pi < np; ++pi)
+      for (int k : patches[pi]) tri_rec.insert(tri_rec.end(), {T3[3 * k], T3[3 * k + 1], T3[3 * k + 2], pi});
     {
       std::vector<std::vector<int>> vpl(NV);
       for (int pi = 0; pi < np; ++pi)
@@ -392,6 +400,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   HIPCHK(upload(ctx->t_vp_off, vp_off));
   HIPCHK(upload(ctx->t_vp, vp));
   HIPCHK(upload(ctx->t_vp4, vp4));
+  HIPCHK(upload(ctx->t_tri_rec, tri_rec));
   DevTopo &D = ctx->topo;
   D.n_topo = nt_topo;
   D.nv = P<int>(ctx->t_nv); D.nt = P<int>(ctx->t_nt); D.ne = P<int>(ctx->t_ne);
@@ -407,6 +416,8 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
   D.vp4 = P<int4>(ctx->t_vp4);
   D.blob = P<int>(ctx->t_blob);
   D.blob_stride = bs;
+  D.tri_rec = P<int4>(ctx->t_tri_rec);
+  D.max_nv = max_nv;
   ctx->have_topo = true;
   return STIV_OK;
 }
@@ -447,6 +458,7 @@ static stiv_status arena(stiv_ctx *ctx, const stiv_scene *s) {
   HIPCHK(ensure(ctx->ves_patch_cnt, 8 * (N + 1)));
   HIPCHK(ensure(ctx->ves_patch_off, 8 * (N + 2)));
   HIPCHK(ensure(ctx->patch_box, 6 * 8 * (ctx->cap_patch + 1)));
+  HIPCHK(ensure(ctx->patch_dop, kDopVals * 4 * (ctx->cap_patch + 1)));
   HIPCHK(ensure(ctx->work, sizeof(WorkRec) * ctx->cap_work));
   HIPCHK(ensure(ctx->cand, sizeof(Cand) * ctx->cap_cand));
   HIPCHK(ensure(ctx->hard_geo, 24 * sizeof(double) * ctx->cap_cand));
@@ -559,7 +571,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   // ---- K0 boxes
   if (timed) (void)hipEventRecord(ctx->ev[0], st);
   launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box),
-               ctx->max_patches, cnt, st);
+               P<float>(ctx->patch_dop), ctx->max_patches, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[1], st);
   // ---- K1 vesicle broad phase
   launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), P<int64_t>(ctx->cp_cnt), st);
@@ -584,8 +596,8 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   if (timed) (void)hipEventRecord(ctx->ev[2], st);
   // ---- K2 primitive broad phase
   launch_patch_pairs(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, P<double>(ctx->ves_box),
-                     P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<WorkRec>(ctx->work),
-                     ctx->cap_work, ctx->max_patches, cnt, st);
+                     P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<float>(ctx->patch_dop),
+                     P<WorkRec>(ctx->work), ctx->cap_work, ctx->max_patches, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[3], st);
   const bool emit = (p->flags & STIV_EMIT_CANDIDATES) != 0;
   launch_prim_cand(ctx->tile, ctx->prim_blocks, S, T, P<PairRec>(ctx->pairs), P<WorkRec>(ctx->work),
