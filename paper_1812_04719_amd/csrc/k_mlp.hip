@@ -53,11 +53,15 @@ __global__ __launch_bounds__(kThreads) void k_mlp_forward(const float *params, c
     const int64_t t = t0 + wave;
     load_x(B, x, 16 * t, t < tiles ? n : 0);
     __syncthreads();
-    forward_tile(W, B);
-    if (t < tiles && lane < 32) {
-      const int r = lane >> 1, c = lane & 1;
-      const int64_t s = 16 * t + r;
-      if (s < n) out[s * kOut + c] = B.o[r][c];
+    // the inference form of the forward (activations in registers), the
+    // one the narrow phase runs
+    const f32x4 o = forward_t16(W, &B.x[0][0]);
+    if (t < tiles && lane < 16) {
+      const int64_t s = 16 * t + lane;
+      if (s < n) {
+        out[s * kOut] = o[0];
+        out[s * kOut + 1] = o[1];
+      }
     }
     __syncthreads();
   }

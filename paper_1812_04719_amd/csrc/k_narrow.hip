@@ -29,10 +29,12 @@
 // Learned bracket (optional): a small perceptron (mlp_tile.h) predicts the
 // contact time of each queued candidate from its shape (the other three
 // vertices relative to the first vertex of the triangle, resp. of the first
-// edge, at both ends of the step, over the mean edge length at t_n).  The
-// search then certifies [0, lo) root-free with one Bernstein test and looks
-// in [lo, hi] first (earliest_bracket in narrow_math.h); the contacts found
-// are the same as without the prediction.
+// edge, at both ends of the step, over the mean edge length at t_n), on the
+// matrix cores with its activations in registers.  When [0, 1] is undecided
+// the search certifies [0, lo) root-free with one Bernstein test and then
+// traverses [lo, hi] and [hi, 1] instead of the halves of [0, 1], and the
+// prediction starts the refinement of the root it lies in (search_in in
+// narrow_math.h); the contacts found are the same as without it.
 #include "mlp_tile.h"
 #include "narrow_math.h"
 
@@ -61,19 +63,23 @@ __device__ inline void load_geo(const double *geo, int64_t cap, int64_t i, bool 
   Q.ee = ee;
 }
 
-__device__ inline double len3(const d3 &v) { return sqrt(dotp(v, v)); }
+__device__ inline float len3f(const d3 &v) {
+  const float x = (float)v.x, y = (float)v.y, z = (float)v.z;
+  return sqrtf(x * x + y * y + z * z);
+}
 
 // Features of the learned bracket from the candidate's positions (selects,
-// not indices, pick the vertices so that Q stays in registers).
+// not indices, pick the vertices so that Q stays in registers).  Differences
+// are taken in FP64 and the rest in FP32 (the network reads bf16).
 __device__ inline void bracket_features(const Quad &Q, float out[mlp::kIn]) {
   const bool ee = Q.ee;
-  double ell;
+  float ell;
   if (ee) {
-    ell = 0.5 * (len3(Q.X0[1] - Q.X0[0]) + len3(Q.X0[3] - Q.X0[2]));
+    ell = 0.5f * (len3f(Q.X0[1] - Q.X0[0]) + len3f(Q.X0[3] - Q.X0[2]));
   } else {
-    ell = (len3(Q.X0[2] - Q.X0[1]) + len3(Q.X0[3] - Q.X0[1]) + len3(Q.X0[3] - Q.X0[2])) / 3.0;
+    ell = (len3f(Q.X0[2] - Q.X0[1]) + len3f(Q.X0[3] - Q.X0[1]) + len3f(Q.X0[3] - Q.X0[2])) * (1.0f / 3.0f);
   }
-  const double inv = ell > 0.0 ? 1.0 / ell : 1.0;
+  const float inv = ell > 0.0f ? 1.0f / ell : 1.0f;
   const d3 A0 = ee ? Q.X0[0] : Q.X0[1], AD = ee ? Q.D[0] : Q.D[1];
   const d3 P0[3] = {ee ? Q.X0[1] : Q.X0[2], ee ? Q.X0[2] : Q.X0[3], ee ? Q.X0[3] : Q.X0[0]};
   const d3 PD[3] = {ee ? Q.D[1] : Q.D[2], ee ? Q.D[2] : Q.D[3], ee ? Q.D[3] : Q.D[0]};
@@ -82,20 +88,18 @@ __device__ inline void bracket_features(const Quad &Q, float out[mlp::kIn]) {
   for (int r = 0; r < 3; ++r) {
     const d3 a = P0[r] - A0;
     const d3 b = (P0[r] + PD[r]) - A1;
-    out[3 * r + 0] = (float)(a.x * inv);
-    out[3 * r + 1] = (float)(a.y * inv);
-    out[3 * r + 2] = (float)(a.z * inv);
-    out[9 + 3 * r + 0] = (float)(b.x * inv);
-    out[9 + 3 * r + 1] = (float)(b.y * inv);
-    out[9 + 3 * r + 2] = (float)(b.z * inv);
+    out[3 * r + 0] = (float)a.x * inv;
+    out[3 * r + 1] = (float)a.y * inv;
+    out[3 * r + 2] = (float)a.z * inv;
+    out[9 + 3 * r + 0] = (float)b.x * inv;
+    out[9 + 3 * r + 1] = (float)b.y * inv;
+    out[9 + 3 * r + 2] = (float)b.z * inv;
   }
 }
 
 struct BracketLds {
   mlp::Weights W;
   alignas(16) unsigned short x[256][mlp::kXS];
-  mlp::Act act[4];
-  float br[256][2];
 };
 
 // Root search on the queued candidates, then volume and gradient on contact.
@@ -118,24 +122,41 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
     mlp::load_packed(L.W, reinterpret_cast<const mlp::Weights *>(mlp_packed));
     __syncthreads();  // the only workgroup barrier: after it each wavefront uses its own LDS rows
   }
+  // Plain search: the next candidate's record and geometry are loaded while
+  // the current one is searched (the loop's only global loads; in-order
+  // completion would otherwise expose their latency every iteration).  The
+  // learned search has no registers to spare for that and loads each
+  // candidate once, at the start of its iteration.
+  Cand cn;
+  Quad Qn;
+  cn.pair = cn.kind = cn.i = cn.j = 0;
+  if (!LEARNED) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 < nc) {
+      cn = hard[i0];
+      load_geo(geo, hard_cap, i0, cn.kind == 2, Qn);
+    }
+  }
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {
     const int64_t i = base + threadIdx.x;
     int hit = 0;
     double s = 0.0, V = 0.0, g[12];
-    Cand c;
-    c.pair = c.kind = c.i = c.j = 0;
+    if (LEARNED && i < nc) {
+      cn = hard[i];
+      load_geo(geo, hard_cap, i, cn.kind == 2, Qn);
+    }
+    const Cand c = cn;
+    const Quad Q = Qn;
     for (int k = 0; k < 12; ++k) g[k] = 0.0;
-    Quad Q;
-    if (i < nc) c = hard[i];
+    if (!LEARNED && i + stride < nc) {
+      cn = hard[i + stride];
+      load_geo(geo, hard_cap, i + stride, cn.kind == 2, Qn);
+    }
     if (LEARNED) {
-      // features first; the geometry is loaded again for the search so that
-      // it is not live (spilled) across the perceptron
       {
         float ft[mlp::kIn];
         if (i < nc) {
-          Quad Qf;
-          load_geo(geo, hard_cap, i, c.kind == 2, Qf);
-          bracket_features(Qf, ft);
+          bracket_features(Q, ft);
         } else {
 #pragma unroll
           for (int k = 0; k < mlp::kIn; ++k) ft[k] = 0.0f;
@@ -150,18 +171,21 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
         }
       }
       mlp::wave_lds_sync();
+      // the wavefront's 64 samples, 16 at a time; the outputs of sample
+      // 16 q + c arrive in lane c and go to the lane that owns the sample
       const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      float o_mu = 0.0f, o_sd = 0.0f;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row0 = 64 * wave + 16 * q;
-        const mlp::f32x4 o = mlp::forward16<true>(L.W, &L.x[row0][0], L.act[wave]);
-        const int col = lane & 15, gq = lane >> 4;
-        if (col < 2)
-          for (int j = 0; j < 4; ++j) L.br[row0 + 4 * gq + j][col] = o[j];
-        mlp::wave_lds_sync();
+        const mlp::f32x4 o = mlp::forward_t16(L.W, &L.x[64 * wave + 16 * q][0]);
+        const float a = __shfl(o[0], lane & 15, 64), b = __shfl(o[1], lane & 15, 64);
+        if ((lane >> 4) == q) {
+          o_mu = a;
+          o_sd = b;
+        }
       }
       if (i < nc) {
-        load_geo(geo, hard_cap, i, c.kind == 2, Q);
-        const float mu = mlp::head_mu(L.br[threadIdx.x][0]), sd = mlp::head_sd(L.br[threadIdx.x][1]);
+        const float mu = mlp::head_mu(o_mu), sd = mlp::head_sd(o_sd);
         double lo = (double)mu - (double)kwidth * (double)sd, hi = (double)mu + (double)kwidth * (double)sd;
         lo = lo < 0.0 ? 0.0 : lo;
         hi = hi > 1.0 ? 1.0 : hi;
@@ -171,7 +195,6 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
       }
       mlp::wave_lds_sync();
     } else if (i < nc) {
-      load_geo(geo, hard_cap, i, c.kind == 2, Q);
       hit = earliest<N>(Q, d, &s, &within, &deg, &exh);
     }
     if (hit && !Q.ee) volume_grad(Q, s, d, eps, dt, s == 0.0, &V, g);

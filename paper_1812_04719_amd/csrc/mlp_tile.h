@@ -138,6 +138,51 @@ __device__ inline f32x4 forward16(const Weights &W, const unsigned short *x, Act
   return acc;
 }
 
+// The same forward for inference, with every layer computed transposed
+// (H^T = W^T X^T: the weights are the A operand, the samples the columns):
+// then the output tile of one layer is, lane for lane, the B operand of the
+// next, and the activations stay in registers.  x holds the 16 samples as
+// rows (bf16, row stride kXS, columns kIn .. kInP - 1 zero).  Lane l
+// receives the outputs 4 (l / 16) + j of sample l % 16, so lanes 0..15 hold
+// the two outputs in elements 0 and 1.
+__device__ inline f32x4 forward_t16(const Weights &W, const unsigned short *x) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, g = lane >> 4;
+  bf16x4 h1[kH / 16], h2[kH / 16];
+#pragma unroll
+  for (int nt = 0; nt < kH / 16; ++nt) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < kInP; k0 += 16) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&W.w1t[16 * nt + col][k0 + 4 * g]);
+      const bf16x4 b = *reinterpret_cast<const bf16x4 *>(x + col * kXS + k0 + 4 * g);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h1[nt][j] = (short)f2bf(fmaxf(acc[j] + W.b1[16 * nt + 4 * g + j], 0.0f));
+  }
+#pragma unroll
+  for (int nt = 0; nt < kH / 16; ++nt) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kt = 0; kt < kH / 16; ++kt) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&W.w2t[16 * nt + col][16 * kt + 4 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[kt], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h2[nt][j] = (short)f2bf(fmaxf(acc[j] + W.b2[16 * nt + 4 * g + j], 0.0f));
+  }
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int kt = 0; kt < kH / 16; ++kt) {
+    const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&W.w3t[col][16 * kt + 4 * g]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h2[kt], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] += W.b3[4 * g + j];
+  return acc;
+}
+
 __device__ inline float head_mu(float o0) { return 1.0f / (1.0f + __expf(-o0)); }
 __device__ inline float head_sd(float o1) { return (o1 > 20.0f ? o1 : log1pf(__expf(o1))) + kSdFloor; }
 

@@ -211,6 +211,13 @@ constexpr int kMaxSearchVisits = 4096;
 // budget of intervals.  guess (optional) is the start of the refinement of a
 // root isolated in an interval that contains it.
 //
+// With a predicted bracket lo <= blo < bhi <= hi (blo >= 0 to use it): when
+// the whole interval neither excludes a root nor isolates one, and the
+// Bernstein coefficients of F on [lo, blo] all have one strict sign (no root
+// before blo), the traversal continues on [blo, bhi] and then on [bhi, hi]
+// instead of the halves of [lo, hi]; *certified is then set.  The roots are
+// met in the same left-to-right order, so the result is the same contact.
+//
 // The search alternates two phases: subdivide until the next interval that
 // isolates a root (or the end), then refine that root and test it.  On a
 // wavefront, lanes that have isolated a root wait at the end of the first
@@ -219,10 +226,13 @@ constexpr int kMaxSearchVisits = 4096;
 // roots computed are those of a plain depth-first traversal.
 template <int N>
 __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double lo, double hi, double *s_out,
-                                  int *visits, int *deg, int *exh, double guess = -1.0) {
+                                  int *visits, int *deg, int *exh, double guess = -1.0, double blo = -1.0,
+                                  double bhi = -1.0, int *certified = nullptr) {
   const int kMaxLevel = kMaxSearchLevel;
   const int kMaxVisits = kMaxSearchVisits;
-  const double span = hi - lo;
+  // the segment being traversed, and the one after it (when pend_hi > pend_lo)
+  double seg_lo = lo, span = hi - lo, pend_lo = 0.0, pend_hi = 0.0;
+  bool bracket = blo >= lo && blo < bhi && bhi <= hi;
   int level = 0;
   long long idx = 0;
   bool done = false;
@@ -236,8 +246,8 @@ __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double l
         return 0;
       }
       const double wd = ldexp(1.0, -level);
-      u = lo + span * ((double)idx * wd);
-      v = lo + span * ((double)(idx + 1) * wd);
+      u = seg_lo + span * ((double)idx * wd);
+      v = seg_lo + span * ((double)(idx + 1) * wd);
       double b[N + 1];
       bernstein_on<N>(f, u, v - u, b);
       bool pos = true, neg = true;
@@ -267,6 +277,34 @@ __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double l
           iso = true;
         }
       }
+      if (descend && bracket) {
+        // first interval of the search, undecided: try the predicted bracket
+        bracket = false;
+        bool ok = true;
+        if (blo > seg_lo) {
+          if (++(*visits) > kMaxVisits) {
+            (*exh)++;
+            return 0;
+          }
+          double c[N + 1];
+          bernstein_on<N>(f, seg_lo, blo - seg_lo, c);
+          bool cp = true, cn = true;
+#pragma unroll
+          for (int k = 0; k <= N; ++k) {
+            cp &= c[k] > 0.0;
+            cn &= c[k] < 0.0;
+          }
+          ok = cp || cn;
+        }
+        if (ok) {
+          if (certified) *certified = 1;
+          pend_lo = bhi;
+          pend_hi = seg_lo + span;
+          seg_lo = blo;
+          span = bhi - blo;
+          continue;  // level 0, idx 0 of [blo, bhi]
+        }
+      }
       if (descend) {
         ++level;
         idx <<= 1;
@@ -274,8 +312,16 @@ __host__ __device__ int search_in(const Quad &Q, const double f[N + 1], double l
       }
       // move past this interval (the traversal resumes there if the root is not valid)
       while (level > 0 && (idx & 1)) { idx >>= 1; --level; }
-      if (level == 0) done = true;
-      else ++idx;
+      if (level > 0) {
+        ++idx;
+      } else if (pend_hi > pend_lo) {
+        seg_lo = pend_lo;
+        span = pend_hi - pend_lo;
+        pend_lo = pend_hi = 0.0;
+        idx = 0;
+      } else {
+        done = true;
+      }
     }
     if (!iso) break;
     // phase 2: refine and test
@@ -321,14 +367,13 @@ __host__ __device__ int earliest(const Quad &Q, double d, double *s_out, int *wi
   return search_in<N>(Q, f, 0.0, 1.0, s_out, &visits, deg, exh);
 }
 
-// The same earliest valid root, searched first inside a predicted bracket
-// [lo, hi] of [0,1]: when the Bernstein coefficients of F on [0, lo] all have
-// one strict sign, F has no root before lo, so the earliest valid root is
-// the first one found in [lo, hi], else in [hi, 1].  Without that
-// certificate the whole of [0,1] is searched.  The predicted root `guess`
-// starts the refinement of an isolated root when it lies in that interval.  The result is the root of
-// earliest() (up to the last bits of the final refinement, which starts
-// from a different enclosing interval).  *certified reports the path taken.
+// The same earliest valid root, searched with a predicted root `guess` and
+// bracket [lo, hi] of [0,1] (search_in: the bracket replaces the halving of
+// [0, 1] when that interval is undecided and F has no root before lo; the
+// prediction starts the refinement of an isolated root that it lies in).
+// The result is the root of earliest() (up to the last bits of the final
+// refinement, which starts from a different point).  *certified reports
+// whether the bracket was used.
 template <int N>
 __host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, double hi, double guess, double *s_out,
                                          int *within, int *deg, int *exh, int *certified) {
@@ -336,30 +381,8 @@ __host__ __device__ int earliest_bracket(const Quad &Q, double d, double lo, dou
   const int pre = prepare<N>(Q, d, f, s_out, within, deg);
   *certified = 0;
   if (pre >= 0) return pre;
-  // the intervals to search, in order: [lo, hi] then [hi, 1] when [0, lo) is
-  // certified root-free, else [0, 1] alone (one call site keeps the search inline)
-  bool ok = lo >= 0.0 && lo < hi && hi <= 1.0;
-  if (ok && lo > 0.0) {
-    double b[N + 1];
-    bernstein_on<N>(f, 0.0, lo, b);
-    bool pos = true, neg = true;
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-      pos &= b[k] > 0.0;
-      neg &= b[k] < 0.0;
-    }
-    ok = pos || neg;
-  }
-  *certified = ok ? 1 : 0;
-  double a0 = ok ? lo : 0.0, a1 = ok ? hi : 1.0;
-  const int parts = (ok && hi < 1.0) ? 2 : 1;
   int visits = 0;
-  for (int part = 0; part < parts; ++part) {
-    if (search_in<N>(Q, f, a0, a1, s_out, &visits, deg, exh, guess)) return 1;
-    a0 = a1;
-    a1 = 1.0;
-  }
-  return 0;
+  return search_in<N>(Q, f, 0.0, 1.0, s_out, &visits, deg, exh, guess, lo, hi, certified);
 }
 
 // V and dV/dX1 (order p, a, b, c) of a vertex-triangle contact at s.

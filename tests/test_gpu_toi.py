@@ -227,7 +227,11 @@ def test_learned_flag_without_model_is_an_error(ctx):
 
 def test_trained_model_same_contacts_and_speed(ctx):
     """The shipped model on the 1440-vesicle workload: identical contacts,
-    and the narrow-phase times of both searches (reported, not asserted)."""
+    and the speed of the narrow phase with the bracket relative to the plain
+    search.  The bracket does not beat the plain search on this workload (the
+    plain subdivision decides about half of the searches in one interval and
+    needs 2.5 on average); the ratio is reported in the assertion message and
+    only a collapse below 0.7 fails."""
     from paper_1812_04719_amd import stiv, toi_model
     if not os.path.exists(toi_model.DEFAULT_WEIGHTS):
         pytest.skip("no trained bracket model in the package")
@@ -246,6 +250,9 @@ def test_trained_model_same_contacts_and_speed(ctx):
         stiv.detect(ctx, ds, sc.d, sc.eps, sc.dt, outputs=outs, to_numpy=False, learned_bracket=True)
         tl.append(ctx.stage_times()[4])
     st = ctx.stats()
-    print("narrow phase ms: plain %.4f learned %.4f (certified %d of %d)"
-          % (np.median(tp), np.median(tl), st["bracket_certified"], st["root_searches"]), flush=True)
     ctx.set_toi_model(None)
+    gain = float(np.median(tp) / np.median(tl))
+    msg = ("narrow phase ms: plain %.4f learned %.4f, learned speed / plain speed = %.3f (bracket used in %d of %d "
+           "searches)" % (np.median(tp), np.median(tl), gain, st["bracket_certified"], st["root_searches"]))
+    print(msg, flush=True)
+    assert gain > 0.7, msg
