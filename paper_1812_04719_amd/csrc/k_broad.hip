@@ -244,8 +244,12 @@ __global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *bo
 // points (index (kx * n_y + ky) * n_z + kz, as one thread would in order).
 constexpr int kCpLanes = 8;
 __global__ void k_cp_emit(DevScene S, const double *box, const int *ves_scene, const SceneGrid *grid,
-                          const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap) {
+                          const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, Counters *cnt) {
   const int64_t nt = (int64_t)S.n_ves * kCpLanes;
+  // which key bits vary: OR of the keys and of their complements (the sort
+  // skips digits that are the same in every key: a shallow grid leaves the
+  // high Morton digits zero)
+  uint64_t k_or = 0, k_nor = 0;
   for (int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gid < nt; gid += (int64_t)gridDim.x * blockDim.x) {
     const int v = (int)(gid / kCpLanes), part = (int)(gid % kCpLanes);
     const int sc = ves_scene[v];
@@ -263,10 +267,21 @@ __global__ void k_cp_emit(DevScene S, const double *box, const int *ves_scene, c
       const uint32_t cz = axis_cell(g, 2, B[2], B[5], kz, n[2], full[2]);
       const int64_t o = o0 + idx;
       if (o < cap) {
-        keys[o] = ((uint64_t)sc << 30) | morton3(cx, cy, cz);
+        const uint64_t key = ((uint64_t)sc << 30) | morton3(cx, cy, cz);
+        keys[o] = key;
         vals[o] = (uint32_t)v;
+        k_or |= key;
+        k_nor |= ~key;
       }
     }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    k_or |= __shfl_xor(k_or, off, 64);
+    k_nor |= __shfl_xor(k_nor, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && (k_or | k_nor)) {
+    atomicOr(&cnt->cp_key_bits[0], (unsigned long long)k_or);
+    atomicOr(&cnt->cp_key_bits[1], (unsigned long long)k_nor);
   }
 }
 
@@ -448,9 +463,10 @@ void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid
   k_scene_grid<<<g, 256, 0, st>>>(S, ves_box, grid, cp_cnt);
 }
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
-                    const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st) {
+                    const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, Counters *cnt,
+                    hipStream_t st) {
   k_cp_emit<<<grid1d((int64_t)S.n_ves * kCpLanes, 256, 4096), 256, 0, st>>>(S, ves_box, ves_scene, grid, cp_off,
-                                                                              keys, vals, cap);
+                                                                              keys, vals, cap, cnt);
 }
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
                        const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,

@@ -108,11 +108,18 @@ struct RsBufs {
   uint32_t *v[2];
 };
 __device__ inline int rs_cur(const int64_t *par, int p) { return p > 0 ? (int)par[p] : 0; }
+// The digit at shift is the same in every key (bits: OR of the keys, OR of
+// their complements; a bit that varies is set in both).
+__device__ inline bool rs_digit_constant(const unsigned long long *bits, int shift) {
+  return bits && (((bits[0] & bits[1]) >> shift) & 255ull) == 0;
+}
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(RsBufs B, const int64_t *par, int p,
                                                         const unsigned long long *n_dev, int64_t n_host, int shift,
-                                                        int32_t *hist, int nblk, bool full_only) {
+                                                        int32_t *hist, int nblk, bool full_only,
+                                                        const unsigned long long *bits) {
   __shared__ int h[256];
+  if (rs_digit_constant(bits, shift)) return;  // the pass moves nothing and reads no histogram
   const uint64_t *keys = B.k[rs_cur(par, p)];
   const int64_t n = rs_count(n_dev, n_host);
   const int t = threadIdx.x, b = blockIdx.x;
@@ -132,7 +139,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(RsBufs B, const int64_t 
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(RsBufs B, int64_t *par, int p,
                                                            const unsigned long long *n_dev, int64_t n_host, int shift,
-                                                           const int64_t *hoff, int nblk) {
+                                                           const int64_t *hoff, int nblk,
+                                                           const unsigned long long *bits) {
   __shared__ int wcnt[kRsWaves][256];
   __shared__ int woff[kRsWaves][256];
   const int64_t n = rs_count(n_dev, n_host);
@@ -142,6 +150,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(RsBufs B, int64_t *pa
   const uint32_t *sv = B.v[cur];
   uint64_t *dk = B.k[cur ^ 1];
   uint32_t *dv = B.v[cur ^ 1];
+  if (rs_digit_constant(bits, shift)) {
+    if (b == 0 && t == 0) par[p + 1] = cur;
+    return;
+  }
   if (b == 0 && t == 0) par[p + 1] = cur ^ 1;
   for (int k = t; k < kRsWaves * 256; k += kRsThreads) (&wcnt[0][0])[k] = 0;
   __syncthreads();
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(RsBufs B, int64_t *pa
 constexpr int kRsFusedMaxBlocks = 256;
 __global__ __launch_bounds__(kRsThreads) void k_rs_pass(RsBufs B, int64_t *par, int p,
                                                         const unsigned long long *n_dev, int64_t n_host, int shift,
-                                                        const int32_t *hin, int nblk) {
+                                                        const int32_t *hin, int nblk, const unsigned long long *bits) {
   __shared__ int wcnt[kRsWaves][256];
   __shared__ int woff[kRsWaves][256];
   __shared__ int64_t dbase[256];
@@ -213,7 +225,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pass(RsBufs B, int64_t *par, 
   const uint32_t *sv = B.v[cur];
   uint64_t *dk = B.k[cur ^ 1];
   uint32_t *dv = B.v[cur ^ 1];
-  if (n == 0) {
+  if (n == 0 || rs_digit_constant(bits, shift)) {
     if (b == 0 && t == 0) par[p + 1] = cur;
     return;
   }
@@ -452,7 +464,7 @@ int64_t radix_offset_elems(int64_t n_host) {
 
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
-                           int64_t *hoff, hipStream_t st) {
+                           int64_t *hoff, hipStream_t st, const unsigned long long *bits_dev) {
   if (n_host <= 0 || key_bits <= 0) return;
   const int nblk = (int)radix_scratch_blocks(n_host);
   const int64_t h = (int64_t)256 * nblk;
@@ -461,12 +473,12 @@ void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_
   int passes = 0;
   for (int shift = 0; shift < key_bits && passes < kRsMaxPasses; shift += 8, ++passes) {
     k_rs_hist<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hist, nblk,
-                                           nblk <= kRsFusedMaxBlocks);
+                                           nblk <= kRsFusedMaxBlocks, bits_dev);
     if (nblk <= kRsFusedMaxBlocks) {
-      k_rs_pass<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hist, nblk);
+      k_rs_pass<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hist, nblk, bits_dev);
     } else {
       scan_any<int32_t>(hist, hoff, nullptr, h, hoff + h + 1, st);
-      k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hoff, nblk);
+      k_rs_scatter<<<nblk, kRsThreads, 0, st>>>(B, par, passes, n_dev, n_host, shift, hoff, nblk, bits_dev);
     }
   }
   k_rs_copy<<<grid_for(n_host, 256), 256, 0, st>>>(B, par, passes, n_dev, n_host);

@@ -135,6 +135,7 @@ struct Counters {
   unsigned long long n_bracket_ok;  // root searches whose predicted bracket was certified
   unsigned long long work_claimed;  // work-item chunks handed out by the primitive kernel
   unsigned long long search_exhausted;  // root searches stopped by their budget of intervals
+  unsigned long long cp_key_bits[2];    // OR of the check-point keys, OR of their complements
 };
 
 // Narrow-phase candidate record.
@@ -159,11 +160,13 @@ void launch_scan_i32_to_i64(const int32_t *in, int64_t *out, const unsigned long
 // Stable sort of n keys (device count n_dev clamped to n_host, or n_host)
 // by their low key_bits bits, values moved along; tk, tv: n_host scratch;
 // hist: 256 * radix_scratch_blocks(n_host) ints, hoff: radix_offset_elems(n_host) int64.
+// bits_dev (optional, device): the OR of the keys and the OR of their
+// complements; a digit where every key has the same bits is skipped at once.
 int64_t radix_scratch_blocks(int64_t n_host);
 int64_t radix_offset_elems(int64_t n_host);
 void launch_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
                            const unsigned long long *n_dev, int64_t n_host, int key_bits, int32_t *hist,
-                           int64_t *hoff, hipStream_t st);
+                           int64_t *hoff, hipStream_t st, const unsigned long long *bits_dev = nullptr);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 // Up to 8 fills (4- or 8-byte elements) in one launch.
 struct FillJob {
@@ -195,8 +198,10 @@ void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *
 
 // K1
 void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st);
+// Also ORs every written key and its complement into cnt->cp_key_bits.
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
-                    const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, hipStream_t st);
+                    const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, Counters *cnt,
+                    hipStream_t st);
 void launch_cell_pairs(const DevScene &S, const double *ves_box, const int *ves_scene, const uint64_t *keys,
                        const uint32_t *vals, const unsigned long long *n_cp, int64_t n_cp_cap, uint64_t *hash,
                        int64_t hash_cap, Counters *cnt, hipStream_t st);

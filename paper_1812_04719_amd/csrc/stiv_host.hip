@@ -577,13 +577,13 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), P<int64_t>(ctx->cp_cnt), st);
   launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_cp_emit(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
-                 P<int64_t>(ctx->cp_off), P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), ctx->cap_cp, st);
+                 P<int64_t>(ctx->cp_off), P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), ctx->cap_cp, cnt, st);
   const unsigned long long *n_cp = reinterpret_cast<const unsigned long long *>(P<int64_t>(ctx->cp_off) + N);
   int scene_bits = 0;
   while ((1ll << scene_bits) < S.n_scenes) ++scene_bits;
   launch_radix_sort_u64(P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), P<uint64_t>(ctx->cp_tk),
                         P<uint32_t>(ctx->cp_tv), n_cp, ctx->cap_cp, 30 + scene_bits, P<int32_t>(ctx->rs_hist),
-                        P<int64_t>(ctx->rs_off), st);
+                        P<int64_t>(ctx->rs_off), st, cnt->cp_key_bits);
   launch_cell_pairs(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<uint64_t>(ctx->cp_keys),
                     P<uint32_t>(ctx->cp_vals), n_cp, ctx->cap_cp, P<uint64_t>(ctx->hash), hash_cap, cnt, st);
   launch_hash_list(P<uint64_t>(ctx->hash), hash_cap, P<uint64_t>(ctx->uniq), ctx->cap_pairs, P<int32_t>(ctx->cnt_a),

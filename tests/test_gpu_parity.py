@@ -57,6 +57,21 @@ def test_table3_sort(ctx):
     assert [g["data"][i - 1] for i in perm] == g["scattered_data"]
 
 
+@pytest.mark.parametrize("n", [3000, 14400])
+def test_sort_short_keys_constant_digits(ctx, n):
+    """Keys below 2^12 (Morton IDs of a shallow grid): the passes of the high
+    digits move nothing; order and stability as numpy's."""
+    import torch
+    rng = np.random.default_rng(n + 1)
+    k = rng.integers(0, 1 << 12, n, dtype=np.uint64)
+    keys = torch.tensor(k.view(np.int64), device="cuda:0")
+    vals = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    ctx.sort_pairs_u64(keys, vals)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(vals.cpu().numpy(), order)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), k[order])
+
+
 def test_sort_stability_large(ctx):
     import torch
     rng = np.random.default_rng(0)
@@ -69,10 +84,11 @@ def test_sort_stability_large(ctx):
     assert np.array_equal(vals.cpu().numpy(), order)
 
 
-@pytest.mark.parametrize("n", [1, 2047, 2049, 50000, 600000])
+@pytest.mark.parametrize("n", [1, 2047, 2049, 8191, 8193, 16384, 16385, 50000, 600000])
 def test_sort_random_u64(ctx, n):
     """Stable sort of full 64-bit keys with repeats: one launch per pass up to
-    256 tiles of 2048 keys, histogram / scan / scatter launches above."""
+    256 tiles of 2048 keys, histogram / scan / scatter launches above; sizes
+    around the tile and 2^13 / 2^14 boundaries."""
     import torch
     rng = np.random.default_rng(n)
     k = rng.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
