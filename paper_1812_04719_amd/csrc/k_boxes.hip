@@ -127,15 +127,20 @@ __device__ inline void tri_support(const unsigned int *vb, int4 rec, const doubl
 // owned vertex and edge lies in one of its triangles: two patches whose
 // supports do not meet along some diagonal hold no primitive pair with
 // meeting boxes.
+// The two parts can run as two launches (the boxes, then the supports, which
+// read the positions again), so that the supports overlap the vesicle broad
+// phase, which needs only the vesicle boxes.
 // MAXP bounds the patches of any vesicle's topology (LDS is sized for it, so
-// small meshes keep more workgroups resident).
+// small meshes keep more workgroups resident); PARTS selects the parts.
 constexpr int kBoxU = 4;
 constexpr int kTriPerThread = 4;
 
-template <int MAXP>
+template <int MAXP, int PARTS>
 __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, const int64_t *ves_patch_off,
-                                               double *ves_box, double *patch_box, float *patch_dop, bool dop,
-                                               Counters *cnt) {
+                                               double *ves_box, double *patch_box, float *patch_dop, Counters *cnt) {
+  // boxes: vesicle and patch boxes; dop: the supports (FP16 vertex boxes and
+  // their folding)
+  constexpr bool boxes = PARTS & kBoxParts, dop = PARTS & kSupportParts;
   __shared__ unsigned long long pk[MAXP][6];  // lo as key, hi as key
   constexpr int kDopP = MAXP <= 512 ? MAXP : 1;  // supports for meshes of up to 512 patches
   __shared__ unsigned int dk[kDopP][kDopVals];   // the patches' supports as keys
@@ -153,7 +158,8 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
     // anchor of the FP16 vertex boxes: the vesicle's first vertex at t_n
     const double an[3] = {S.x0[base], S.x0[nv_all + base], S.x0[2 * nv_all + base]};
     for (int k = threadIdx.x; k < np; k += blockDim.x) {
-      for (int c = 0; c < 3; ++c) { pk[k][c] = ~0ull; pk[k][3 + c] = 0ull; }
+      if (boxes)
+        for (int c = 0; c < 3; ++c) { pk[k][c] = ~0ull; pk[k][3 + c] = 0ull; }
       if (dop)
         for (int j = 0; j < kDopDirs; ++j) { dk[k][2 * j] = ~0u; dk[k][2 * j + 1] = 0u; }
     }
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
           x0[k][c] = in ? S.x0[c * nv_all + base + i] : 0.0;
           x1[k][c] = in ? S.x1[c * nv_all + base + i] : 0.0;
         }
-        q4[k] = in ? T.vp4[vb + i] : make_int4(-1, -1, -1, -1);
+        q4[k] = (in && boxes) ? T.vp4[vb + i] : make_int4(-1, -1, -1, -1);
       }
 #pragma unroll
       for (int k = 0; k < kBoxU; ++k) {
@@ -193,8 +199,6 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
           lo[c] = fmin(lo[c], l[c]);
           hi[c] = fmax(hi[c], u[c]);
         }
-        const unsigned long long kl[3] = {okey(l[0]), okey(l[1]), okey(l[2])};
-        const unsigned long long ku[3] = {okey(u[0]), okey(u[1]), okey(u[2])};
         if (dop) {
           // the vertex box relative to the anchor, rounded outward to FP16
           unsigned short hv[6];
@@ -206,6 +210,9 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
 #pragma unroll
           for (int w = 0; w < 3; ++w) vbox[3 * i + w] = (unsigned int)hv[2 * w] | ((unsigned int)hv[2 * w + 1] << 16);
         }
+        if (!boxes) continue;
+        const unsigned long long kl[3] = {okey(l[0]), okey(l[1]), okey(l[2])};
+        const unsigned long long ku[3] = {okey(u[0]), okey(u[1]), okey(u[2])};
         const int qs[4] = {q4[k].x, q4[k].y, q4[k].z, q4[k].w};
         if (qs[3] == -2) {  // more than four patches: the full list
           for (int e = T.vp_off[vb + i]; e < T.vp_off[vb + i + 1]; ++e) fold_box(pk, T.vp[e], kl, ku);
@@ -261,6 +268,15 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
         }
       }
     }
+    if (!boxes) {
+      // the supports alone
+      __syncthreads();
+      const int64_t slot0 = ves_patch_off[v];
+      for (int k = threadIdx.x; k < np; k += blockDim.x)
+        for (int j = 0; j < kDopVals; ++j) patch_dop[kDopVals * (slot0 + k) + j] = fkey_inv(dk[k][j]);
+      __syncthreads();
+      continue;
+    }
     for (int c = 0; c < 3; ++c) {
       lo[c] = wave_min(lo[c]);
       hi[c] = wave_max(hi[c]);
@@ -285,8 +301,10 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
           patch_box[6 * (slot0 + k) + c] = okey_inv(pk[k][c]) - h;
           patch_box[6 * (slot0 + k) + 3 + c] = okey_inv(pk[k][3 + c]) + h;
         }
-        for (int j = 0; j < kDopVals; ++j)
-          patch_dop[kDopVals * (slot0 + k) + j] = dop ? fkey_inv(dk[k][j]) : ((j & 1) ? INFINITY : -INFINITY);
+        if (dop)
+          for (int j = 0; j < kDopVals; ++j) patch_dop[kDopVals * (slot0 + k) + j] = fkey_inv(dk[k][j]);
+        else if (PARTS & kNoSupportParts)
+          for (int j = 0; j < kDopVals; ++j) patch_dop[kDopVals * (slot0 + k) + j] = (j & 1) ? INFINITY : -INFINITY;
       }
     __syncthreads();
   }
@@ -317,18 +335,39 @@ __global__ void k_ves_tables(DevScene S, DevTopo T, int64_t *patch_cnt, int *ves
 // supports are written as -inf, +inf, which never cull).
 constexpr int kDopMaxVertices = 4096;
 
-void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
-                  double *patch_box, float *patch_dop, int max_patches, Counters *cnt, hipStream_t st) {
-  int g = S.n_ves < 8192 ? S.n_ves : 8192;
-  if (g < 1) return;
-  const bool dop = T.tri_rec != nullptr && T.max_nv <= kDopMaxVertices && max_patches <= 512;
-  const size_t lds = dop ? sizeof(unsigned int) * 3 * (size_t)T.max_nv : 0;
+bool boxes_have_supports(const DevTopo &T, int max_patches) {
+  return T.tri_rec != nullptr && T.max_nv <= kDopMaxVertices && max_patches <= 512;
+}
+
+template <int PARTS>
+static void launch_parts(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off,
+                         double *ves_box, double *patch_box, float *patch_dop, int max_patches, int grid_max,
+                         Counters *cnt, hipStream_t st) {
+  const int g = S.n_ves < grid_max ? S.n_ves : grid_max;
+  const size_t lds = (PARTS & kSupportParts) ? sizeof(unsigned int) * 3 * (size_t)T.max_nv : 0;
   if (max_patches <= 128)
-    k_boxes<128><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, dop, cnt);
+    k_boxes<128, PARTS><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, cnt);
   else if (max_patches <= 512)
-    k_boxes<512><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, dop, cnt);
+    k_boxes<512, PARTS><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, cnt);
   else
-    k_boxes<kMaxPatchesPerVes><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, dop, cnt);
+    k_boxes<kMaxPatchesPerVes, PARTS><<<g, 256, lds, st>>>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, cnt);
+}
+
+void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
+                  double *patch_box, float *patch_dop, int max_patches, int parts, int grid_max, Counters *cnt,
+                  hipStream_t st) {
+  if (S.n_ves < 1) return;
+  if (parts == kBoxParts)
+    launch_parts<kBoxParts>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, max_patches, grid_max, cnt, st);
+  else if (parts == kSupportParts)
+    launch_parts<kSupportParts>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, max_patches, grid_max, cnt,
+                                st);
+  else if (parts == (kBoxParts | kSupportParts))
+    launch_parts<kBoxParts | kSupportParts>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, max_patches,
+                                            grid_max, cnt, st);
+  else
+    launch_parts<kBoxParts | kNoSupportParts>(S, T, h, ves_patch_off, ves_box, patch_box, patch_dop, max_patches,
+                                              grid_max, cnt, st);
 }
 
 void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st) {

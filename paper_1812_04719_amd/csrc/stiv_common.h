@@ -193,8 +193,15 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st);
 // patch_dop: every patch's face-diagonal supports (kDopVals floats per patch
 // slot).
+// Parts of the box kernel: vesicle and patch boxes; the patches' supports
+// along the face diagonals; or, with the boxes, supports that never cull
+// (for topologies without supports, see boxes_have_supports).  At most
+// grid_max workgroups.
+constexpr int kBoxParts = 1, kSupportParts = 2, kNoSupportParts = 4;
+bool boxes_have_supports(const DevTopo &T, int max_patches);
 void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *ves_patch_off, double *ves_box,
-                  double *patch_box, float *patch_dop, int max_patches, Counters *cnt, hipStream_t st);
+                  double *patch_box, float *patch_dop, int max_patches, int parts, int grid_max, Counters *cnt,
+                  hipStream_t st);
 
 // K1
 void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st);

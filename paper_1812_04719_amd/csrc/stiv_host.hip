@@ -84,6 +84,10 @@ struct stiv_ctx {
   const void *val_ptr[4] = {};
   int64_t val_size[3] = {-1, -1, -1};
   hipEvent_t ev[9] = {};  // ev[8] marks the start, ev[0..7] stage boundaries
+  // a second stream (default priority) on which the patch supports overlap the
+  // vesicle broad phase, joined back into the call's stream by events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   float stage_ms[8] = {};
 };
 
@@ -135,9 +139,15 @@ stiv_status stiv_create(stiv_ctx **out, int dev) {
   }
   for (auto &e : ctx->ev)
     if (hipEventCreate(&e) != hipSuccess) {
-      delete ctx;
+      stiv_destroy(ctx);
       return STIV_E_HIP;
     }
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess) {
+    stiv_destroy(ctx);
+    return STIV_E_HIP;
+  }
   // the device address of stiv_backward_static's scratch, once per device
   void *scratch_addr = nullptr;
   if (backward_static_scratch(dev, &scratch_addr) != hipSuccess) {
@@ -172,6 +182,9 @@ stiv_status stiv_destroy(stiv_ctx *ctx) {
     if (b->p) (void)hipFree(b->p);
   for (auto &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->h_cnt) (void)hipHostFree(ctx->h_cnt);
   delete ctx;
   return STIV_OK;
@@ -547,6 +560,9 @@ stiv_status stiv_reserve(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *
   return arena(ctx, s);
 }
 
+constexpr int kSupportGrid = 384;         // workgroups of the supports beside the broad phase
+constexpr int64_t kSplitMaxVesicles = 4096;  // larger scenes: supports inside the box kernel
+
 static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p, stiv_result *out, hipStream_t st,
                          bool timed) {
   const double h = 0.5 * p->d;
@@ -568,10 +584,26 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   }
   launch_ves_tables(S, T, P<int64_t>(ctx->ves_patch_cnt), P<int>(ctx->ves_scene), st);
   launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
-  // ---- K0 boxes
+  // ---- K0 boxes.  The patches' face-diagonal supports need only the
+  // positions: up to kSplitMaxVesicles vesicles they run on the side stream
+  // after the boxes, beside the vesicle broad phase (latency-bound, it leaves
+  // most compute units idle), on a grid of a few workgroups per compute unit,
+  // and are joined before the patch pairs; larger scenes compute them in the
+  // box kernel (their supports would outlast the broad phase).
+  const bool has_sup = boxes_have_supports(T, ctx->max_patches);
+  const bool supports = has_sup && N <= kSplitMaxVesicles;
   if (timed) (void)hipEventRecord(ctx->ev[0], st);
   launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box),
-               P<float>(ctx->patch_dop), ctx->max_patches, cnt, st);
+               P<float>(ctx->patch_dop), ctx->max_patches,
+               supports ? kBoxParts : (has_sup ? (kBoxParts | kSupportParts) : (kBoxParts | kNoSupportParts)), 8192,
+               cnt, st);
+  if (supports) {
+    (void)hipEventRecord(ctx->fork, st);
+    (void)hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+    launch_boxes(S, T, h, P<int64_t>(ctx->ves_patch_off), P<double>(ctx->ves_box), P<double>(ctx->patch_box),
+                 P<float>(ctx->patch_dop), ctx->max_patches, kSupportParts, kSupportGrid, cnt, ctx->side);
+    (void)hipEventRecord(ctx->join, ctx->side);
+  }
   if (timed) (void)hipEventRecord(ctx->ev[1], st);
   // ---- K1 vesicle broad phase
   launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), P<int64_t>(ctx->cp_cnt), st);
@@ -594,7 +626,8 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   launch_pair_bucket_sort_emit(S, P<int>(ctx->ves_scene), P<int64_t>(ctx->off_a), P<uint64_t>(ctx->sorted), (int)N,
                                P<PairRec>(ctx->pairs), out->pair_ab, out->pair_shift, out->cap_pairs, st);
   if (timed) (void)hipEventRecord(ctx->ev[2], st);
-  // ---- K2 primitive broad phase
+  // ---- K2 primitive broad phase (after the supports)
+  if (supports) (void)hipStreamWaitEvent(st, ctx->join, 0);
   launch_patch_pairs(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, P<double>(ctx->ves_box),
                      P<int64_t>(ctx->ves_patch_off), P<double>(ctx->patch_box), P<float>(ctx->patch_dop),
                      P<WorkRec>(ctx->work), ctx->cap_work, ctx->max_patches, cnt, st);
