@@ -172,8 +172,11 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
       s_part[threadIdx.x] = part;
       __syncthreads();
       if (threadIdx.x == 0) {
+        // the partial sums past the last non-empty run are +0 and would not
+        // change the bits (V_k >= 0)
+        const int nparts = chunk ? (nvt + chunk - 1) / chunk : 0;
         double V = 0.0;
-        for (int k = 0; k < kAggThreads; ++k) V += s_part[k];
+        for (int k = 0; k < nparts; ++k) V += s_part[k];
         pair_V[p] = V;
         pair_hasvt[p] = nvt > 0;
         if (nvt == 0) pair_rows[p] = 0;
