@@ -64,13 +64,10 @@ __global__ void k_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt
   }
 }
 
-// Ascending bitonic sort of (key, idx) pairs in place; n_pow2 >= n is a power of
-// two and entries [n, n_pow2) are padded by the caller with key = ~0.  Inlined
-// at each call, so that a call on the LDS arrays compiles to LDS accesses (a
-// pointer that may be either LDS or global memory makes every access a
-// generic one); GLOBAL adds the fence that the global-memory slices need.
-template <bool GLOBAL>
-__device__ __forceinline__ void bitonic(uint64_t *key, int32_t *idx, int n_pow2) {
+// Ascending bitonic sort of (key, idx) pairs in a global-memory slice (pairs
+// whose bucket does not fit in LDS); n_pow2 >= n is a power of two and entries
+// [n, n_pow2) are padded by the caller with key = ~0.
+__device__ void bitonic_global(uint64_t *key, int32_t *idx, int n_pow2) {
   for (int size = 2; size <= n_pow2; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = threadIdx.x; t < (n_pow2 >> 1); t += blockDim.x) {
@@ -87,8 +84,66 @@ __device__ __forceinline__ void bitonic(uint64_t *key, int32_t *idx, int n_pow2)
           idx[j] = x;
         }
       }
-      if (GLOBAL) __threadfence_block();
+      __threadfence_block();
       __syncthreads();
+    }
+  }
+}
+
+// LDS sort buffers hold one pad entry after every 8, so that the 8 entries
+// a thread exchanges in registers (below) lie in different banks for the
+// threads of a half-wavefront whatever the stride between them.
+__device__ __forceinline__ int kp(int i) { return i + (i >> 3); }
+
+// Compare-exchange: the smaller key to x (the larger with desc).
+__device__ __forceinline__ void cex(uint64_t &x, uint64_t &y, bool desc) {
+  const bool sw = (x > y) != desc;
+  const uint64_t a = sw ? y : x, b = sw ? x : y;
+  x = a;
+  y = b;
+}
+
+// M consecutive stages (strides 2^(lo+M-1) down to 2^lo) of the bitonic merge
+// of `size`: the 2^M entries whose indices differ only in those M bits are
+// exchanged only among themselves, so each thread loads one such group, runs
+// the M stages on it in registers and stores it back.
+template <int M>
+__device__ __forceinline__ void sort_pass(uint64_t *key, int n2, int size, int lo) {
+  const int groups = n2 >> M;
+  for (int t = threadIdx.x; t < groups; t += kAggThreads) {
+    const int b = ((t >> lo) << (lo + M)) | (t & ((1 << lo) - 1));
+    const bool desc = (b & size) != 0;
+    uint64_t v[1 << M];
+#pragma unroll
+    for (int a = 0; a < (1 << M); ++a) v[a] = key[kp(b + (a << lo))];
+#pragma unroll
+    for (int r = M - 1; r >= 0; --r)
+#pragma unroll
+      for (int a = 0; a < (1 << M); ++a)
+        if (!(a & (1 << r))) cex(v[a], v[a | (1 << r)], desc);
+#pragma unroll
+    for (int a = 0; a < (1 << M); ++a) key[kp(b + (a << lo))] = v[a];
+  }
+  __syncthreads();
+}
+
+// Ascending bitonic sort of n2 (a power of two, at most kLdsSort) distinct
+// 64-bit keys in a padded LDS buffer, three stages per pass (one barrier per
+// pass).  The exchanges are those of the plain network, so is the result.
+__device__ void sort_keys_lds(uint64_t *key, int n2) {
+  const int mmax = 3;
+  for (int size = 2; size <= n2; size <<= 1) {
+    int sb = __ffs(size) - 2;  // bit of the first stride, size / 2
+    while (sb >= 0) {
+      const int m = sb + 1 < mmax ? sb + 1 : mmax;
+      const int lo = sb - m + 1;
+      if (m == 3)
+        sort_pass<3>(key, n2, size, lo);
+      else if (m == 2)
+        sort_pass<2>(key, n2, size, lo);
+      else
+        sort_pass<1>(key, n2, size, lo);
+      sb -= m;
     }
   }
 }
@@ -99,64 +154,224 @@ __device__ inline int pow2_ceil(int n) {
   return p;
 }
 
+// Rows of J from the (vertex, entry)-sorted contributions: each thread owns a
+// contiguous chunk of entries, counts the segment starts in it, and after a
+// scan of those counts writes the rows that start in its chunk, adding each
+// segment in entry order (gathers of up to four entries issued together).
+// vtx(e) is the vertex of sorted entry e, con(e) its contribution (contact * 4
+// + role).
+template <class VTX, class CON>
+__device__ __forceinline__ void write_rows(int nj, VTX vtx, CON con, int *s_cnt, const double *__restrict__ ct_grad,
+                                           int32_t *__restrict__ row_vtx, double *__restrict__ row_g,
+                                           int32_t *pair_rows_p) {
+  const int chunk = (nj + kAggThreads - 1) / kAggThreads;
+  const int lo = threadIdx.x * chunk, hi = min(nj, lo + chunk);
+  int starts = 0;
+  for (int e = lo; e < hi; ++e) starts += (e == 0 || vtx(e) != vtx(e - 1));
+  // inclusive scan of the counts: within each wavefront by shuffles, then
+  // the totals of the wavefronts before it
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = starts;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_cnt[wave] = incl;
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) incl += s_cnt[w];
+  int row = incl - starts;
+  for (int e = lo; e < hi; ++e) {
+    const uint64_t gv = vtx(e);
+    if (!(e == 0 || gv != vtx(e - 1))) continue;
+    double g[3] = {0.0, 0.0, 0.0};
+    bool more = true;
+    for (int f0 = e; more; f0 += 4) {
+      int32_t c4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + u;
+        more = more && f < nj && vtx(f) == gv;
+        c4[u] = more ? con(f) : -1;
+      }
+      double v[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c4[u] >= 0)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) v[u][q] = ct_grad[12 * (int64_t)(c4[u] >> 2) + 3 * (c4[u] & 3) + q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c4[u] >= 0)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) g[q] += v[u][q];
+    }
+    row_vtx[row] = (int32_t)gv;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) row_g[3 * row + q] = g[q];
+    ++row;
+  }
+  if (threadIdx.x == kAggThreads - 1) *pair_rows_p = incl;
+  __syncthreads();
+}
+
+// Vesicle pairs with contacts, listed for the sort-aggregate kernel: pairs of
+// at least kBigPair contacts from the front of `order`, the others from its
+// back, so that the workgroups dispatched first take the largest buckets (the
+// largest bucket is that kernel's critical path).  Pairs without contacts get
+// their empty results here.  The order within each list is that of the
+// atomics; it decides only which workgroup takes a pair, not any result.
+constexpr int kBigPair = 128;
+
+__global__ void k_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order,
+                             double *pair_V, int32_t *pair_hasvt, int32_t *pair_rows) {
+  int64_t np = (int64_t)cnt->n_pairs;
+  np = np < pairs_cap ? np : pairs_cap;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // whole wavefronts run every iteration (the appends are wavefront operations)
+  for (int64_t p0 = blockIdx.x * (int64_t)blockDim.x; p0 < np; p0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = p0 + threadIdx.x;
+    int cls = -1;
+    if (p < np) {
+      const int64_t n = pair_off[p + 1] - pair_off[p];
+      if (n == 0) {
+        pair_hasvt[p] = 0;
+        pair_rows[p] = 0;
+        pair_V[p] = 0.0;
+      } else {
+        cls = n >= kBigPair ? 0 : 1;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const unsigned long long m = __ballot(cls == c);
+      if (!m) continue;
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long b = 0;
+      if (lane == leader) b = atomicAdd(&cnt->n_pair_order[c], (unsigned long long)__popcll(m));
+      b = __shfl(b, leader, 64);
+      if (cls == c) {
+        const int64_t slot = (int64_t)(b + __popcll(m & lt));
+        order[c == 0 ? slot : pairs_cap - 1 - slot] = (int32_t)p;
+      }
+    }
+  }
+}
+
+// One workgroup per vesicle pair with contacts (grid-stride over the list of
+// k_pair_order, large buckets first).  Buckets of up to kLdsSort
+// contacts (J entries) are sorted in LDS as single 64-bit keys carrying the
+// entry's position in their low bits; larger ones as (key, index) pairs in a
+// global slice.  Every gather phase issues a thread's loads before its stores.
 __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
-    DevScene S, DevTopo T, const PairRec *pairs, const Counters *cnt, const int64_t *pair_off, const int32_t *perm,
-    const Cand *ct, const double *ct_s, const double *ct_vol, const double *ct_grad, double dt, uint64_t *gkeys,
-    int32_t *gidx, int32_t *out_key, double *out_tau, double *out_s, double *out_vol, double *out_grad,
-    int64_t cap_ct, double *pair_V, int32_t *pair_hasvt, int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp,
+    DevScene S, DevTopo T, const PairRec *__restrict__ pairs, const Counters *__restrict__ cnt,
+    const int32_t *__restrict__ order, const int64_t *__restrict__ pair_off, const int32_t *__restrict__ perm, const Cand *__restrict__ ct,
+    const double *__restrict__ ct_s, const double *__restrict__ ct_vol, const double *__restrict__ ct_grad, double dt,
+    uint64_t *__restrict__ gkeys, int32_t *__restrict__ gidx, int32_t *__restrict__ out_key,
+    double *__restrict__ out_tau, double *__restrict__ out_s, double *__restrict__ out_vol,
+    double *__restrict__ out_grad, int64_t cap_ct, double *__restrict__ pair_V, int32_t *__restrict__ pair_hasvt,
+    int32_t *__restrict__ pair_rows, int32_t *__restrict__ row_vtx_tmp, double *__restrict__ row_g_tmp,
     int64_t pairs_cap) {
-  __shared__ uint64_t skey[kLdsSort];
+  __shared__ uint64_t skey[kLdsSort + kLdsSort / 8];
   __shared__ int32_t sidx[kLdsSort];
+  __shared__ int32_t sord[kLdsSort / 4];
   __shared__ int s_nvt;
   __shared__ double s_part[kAggThreads];
   __shared__ int s_cnt[kAggThreads];
-  int64_t np = (int64_t)cnt->n_pairs;
-  np = np < pairs_cap ? np : pairs_cap;
-  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+  const int64_t n_big = (int64_t)cnt->n_pair_order[0], n_list = n_big + (int64_t)cnt->n_pair_order[1];
+  for (int64_t w = blockIdx.x; w < n_list; w += gridDim.x) {
+    const int64_t p = order[w < n_big ? w : pairs_cap - 1 - (w - n_big)];
     const int64_t off = pair_off[p];
     const int n = (int)(pair_off[p + 1] - off);
-    if (n == 0) {
-      if (threadIdx.x == 0) { pair_hasvt[p] = 0; pair_rows[p] = 0; pair_V[p] = 0.0; }
-      continue;
-    }
-    // ---- sort the pair's contacts by (kind, i, j)
+    // ---- sort the pair's contacts by (kind, i, j); afterwards idx[k] is the
+    // contact of rank k
     const int n2 = pow2_ceil(n);
-    uint64_t *key = skey;
-    int32_t *idx = sidx;
-    if (n2 > kLdsSort) { key = gkeys + 8 * off; idx = gidx + 8 * off; }  // slice of 8*n >= n2 entries
-    for (int k = threadIdx.x; k < n2; k += blockDim.x) {
-      if (k < n) {
-        const int32_t c = perm[off + k];
-        const Cand cd = ct[c];
-        key[k] = ((uint64_t)cd.kind << 42) | ((uint64_t)cd.i << 21) | (uint64_t)cd.j;
-        idx[k] = c;
-      } else {
-        key[k] = ~0ull;
-        idx[k] = -1;
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-    if (n2 <= kLdsSort)
-      bitonic<false>(skey, sidx, n2);
-    else
-      bitonic<true>(key, idx, n2);
+    const bool lds = n2 <= kLdsSort;
+    int32_t *idx = lds ? sidx : gidx + 8 * off;  // global slice of 8*n >= n2 entries
     if (threadIdx.x == 0) s_nvt = 0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    if (lds) {
+      // key (kind, i, j) << 11 | k: distinct, and k < 2048 finds the contact
+      for (int k0 = threadIdx.x; k0 < n2; k0 += 2 * kAggThreads) {
+        int32_t c[2];
+        Cand cd[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = k0 + u * kAggThreads;
+          c[u] = k < n ? perm[off + k] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (c[u] >= 0) cd[u] = ct[c[u]];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = k0 + u * kAggThreads;
+          if (k >= n2) break;
+          skey[kp(k)] = c[u] >= 0 ? (((uint64_t)cd[u].kind << 42 | (uint64_t)cd[u].i << 21 | (uint64_t)cd[u].j) << 11) |
+                                        (uint64_t)k
+                                  : ~0ull;
+          if (k < n) sidx[k] = c[u];
+        }
+      }
+      __syncthreads();
+      sort_keys_lds(skey, n2);
+      // contact of each rank: read all, then overwrite sidx in rank order
+      int32_t cr[kLdsSort / kAggThreads];
+#pragma unroll
+      for (int u = 0; u < kLdsSort / kAggThreads; ++u) {
+        const int k = threadIdx.x + u * kAggThreads;
+        cr[u] = k < n ? sidx[(int)(skey[kp(k)] & 2047u)] : -1;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kLdsSort / kAggThreads; ++u) {
+        const int k = threadIdx.x + u * kAggThreads;
+        if (k < n) sidx[k] = cr[u];
+      }
+      __syncthreads();
+    } else {
+      uint64_t *key = gkeys + 8 * off;
+      for (int k = threadIdx.x; k < n2; k += blockDim.x) {
+        if (k < n) {
+          const int32_t c = perm[off + k];
+          const Cand cd = ct[c];
+          key[k] = ((uint64_t)cd.kind << 42) | ((uint64_t)cd.i << 21) | (uint64_t)cd.j;
+          idx[k] = c;
+        } else {
+          key[k] = ~0ull;
+          idx[k] = -1;
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+      bitonic_global(key, idx, n2);
+    }
+    // contacts in canonical order.  The stores go to the caller's arrays,
+    // which need only the alignment of their element type; the loads come from
+    // the library's own (256-byte aligned) buffers.
+    for (int k = threadIdx.x; k < n; k += kAggThreads) {
       const int32_t c = idx[k];
       const Cand cd = ct[c];
-      const int64_t o = off + k;
+      const double sv = ct_s[c], vv = ct_vol[c];
+      const double2 *gsrc = reinterpret_cast<const double2 *>(ct_grad + 12 * (int64_t)c);
+      double2 gg[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) gg[q] = gsrc[q];
       if (cd.kind < 2) atomicAdd(&s_nvt, 1);
+      const int64_t o = off + k;
       if (o < cap_ct) {
         out_key[4 * o] = (int32_t)p;
         out_key[4 * o + 1] = cd.kind;
         out_key[4 * o + 2] = cd.i;
         out_key[4 * o + 3] = cd.j;
-        out_tau[o] = ct_s[c] * dt;
-        if (out_s) out_s[o] = ct_s[c];
-        out_vol[o] = ct_vol[c];
-        for (int q = 0; q < 12; ++q) out_grad[12 * o + q] = ct_grad[12 * (int64_t)c + q];
+        out_tau[o] = sv * dt;
+        if (out_s) out_s[o] = sv;
+        out_vol[o] = vv;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          out_grad[12 * o + 2 * q] = gg[q].x;
+          out_grad[12 * o + 2 * q + 1] = gg[q].y;
+        }
       }
     }
     __syncthreads();
@@ -184,81 +399,79 @@ __global__ __launch_bounds__(kAggThreads) void k_ct_sort_aggregate(
       __syncthreads();
     }
     if (nvt == 0) continue;
-    // ---- J rows: 4 contributions per VT contact keyed by (global vertex, order)
+    // ---- J rows: 4 contributions per VT contact keyed by (global vertex,
+    // entry), entry e = 4 k + role for the VT contact of rank k (role 0 its
+    // vertex, 1-3 the triangle's corners)
     const PairRec pr = pairs[p];
     const int nj = 4 * nvt;
     const int nj2 = pow2_ceil(nj);
-    uint64_t *jkey = skey;
-    int32_t *jidx = sidx;
-    if (!(nj2 <= kLdsSort && n2 <= kLdsSort)) {
-      // global slices of 8*n >= nj2 entries
-      jkey = gkeys + 8 * off;
-      jidx = gidx + 8 * off;
-    }
-    // Keep the sorted VT contact order aside (the sort buffers are reused
-    // below); the slice of row_vtx_tmp is free until the rows are written.
-    int32_t *ord = row_vtx_tmp + 4 * off;
-    for (int k = threadIdx.x; k < nvt; k += blockDim.x) ord[k] = idx[k];
-    __threadfence_block();
-    __syncthreads();
-    for (int e = threadIdx.x; e < nj2; e += blockDim.x) {
-      if (e < nj) {
-        const int k = e >> 2, role = e & 3;
-        const Cand cd = ct[ord[k]];
-        const int vv = cd.kind ? pr.b : pr.a, vt = cd.kind ? pr.a : pr.b;
-        int64_t gid;
-        if (role == 0) {
-          gid = S.vtx_off[vv] + cd.i;
+    const int64_t voff[2] = {S.vtx_off[pr.a], S.vtx_off[pr.b]};
+    const int64_t toff[2] = {T.tri_off[S.topo_id[pr.a]], T.tri_off[S.topo_id[pr.b]]};
+    if (nj2 <= kLdsSort) {
+      // nvt <= 512: the VT contacts in rank order stay in LDS, and the sort
+      // key (vertex << 24 | e) alone finds each contribution
+      for (int k = threadIdx.x; k < nvt; k += kAggThreads) sord[k] = idx[k];
+      __syncthreads();
+      for (int k = threadIdx.x; k < nj2 / 4; k += kAggThreads) {
+        uint64_t kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+        if (k < nvt) {
+          const Cand cd = ct[sord[k]];
+          const int sv = cd.kind ? 1 : 0, st = 1 - sv;  // kind 0: vertex of a, triangle of b
+          const int *tc = T.tri + 3 * (toff[st] + cd.j);
+          const int t0 = tc[0], t1 = tc[1], t2 = tc[2];
+          const int64_t gid[4] = {voff[sv] + cd.i, voff[st] + t0, voff[st] + t1, voff[st] + t2};
+#pragma unroll
+          for (int role = 0; role < 4; ++role) kk[role] = ((uint64_t)gid[role] << 24) | (uint64_t)(4 * k + role);
+        }
+#pragma unroll
+        for (int role = 0; role < 4; ++role) skey[kp(4 * k + role)] = kk[role];
+      }
+      __syncthreads();
+      sort_keys_lds(skey, nj2);
+      write_rows(
+          nj, [&](int e) { return skey[kp(e)] >> 24; },
+          [&](int e) {
+            const int x = (int)(skey[kp(e)] & 0xffffffu);
+            return sord[x >> 2] * 4 + (x & 3);
+          },
+          s_cnt, ct_grad, row_vtx_tmp + 4 * off, row_g_tmp + 3 * (4 * off), pair_rows + p);
+    } else {
+      // global slices of 8*n >= nj2 entries; the sorted VT order is kept aside
+      // first (the slices are reused), in the row slice, free until the rows
+      // are written
+      uint64_t *jkey = gkeys + 8 * off;
+      int32_t *jidx = gidx + 8 * off;
+      int32_t *ord = row_vtx_tmp + 4 * off;
+      for (int k = threadIdx.x; k < nvt; k += blockDim.x) ord[k] = idx[k];
+      __threadfence_block();
+      __syncthreads();
+      for (int k = threadIdx.x; k < nj2 / 4; k += kAggThreads) {
+        if (k < nvt) {
+          const int32_t c = ord[k];
+          const Cand cd = ct[c];
+          const int sv = cd.kind ? 1 : 0, st = 1 - sv;
+          const int *tc = T.tri + 3 * (toff[st] + cd.j);
+          const int t0 = tc[0], t1 = tc[1], t2 = tc[2];
+          const int64_t gid[4] = {voff[sv] + cd.i, voff[st] + t0, voff[st] + t1, voff[st] + t2};
+#pragma unroll
+          for (int role = 0; role < 4; ++role) {
+            jkey[4 * k + role] = ((uint64_t)gid[role] << 24) | (uint64_t)(4 * k + role);
+            jidx[4 * k + role] = c * 4 + role;
+          }
         } else {
-          const int tt = S.topo_id[vt];
-          gid = S.vtx_off[vt] + T.tri[3 * ((int64_t)T.tri_off[tt] + cd.j) + (role - 1)];
+#pragma unroll
+          for (int role = 0; role < 4; ++role) {
+            jkey[4 * k + role] = ~0ull;
+            jidx[4 * k + role] = -1;
+          }
         }
-        jkey[e] = ((uint64_t)gid << 24) | (uint64_t)e;
-        jidx[e] = ord[k] * 4 + role;
-      } else {
-        jkey[e] = ~0ull;
-        jidx[e] = -1;
       }
-    }
-    __threadfence_block();
-    __syncthreads();
-    if (jkey == skey)
-      bitonic<false>(skey, sidx, nj2);
-    else
-      bitonic<true>(jkey, jidx, nj2);
-    // segments of equal vertex: each thread owns a contiguous chunk of entries,
-    // counts the segment starts in it, and after a scan of those counts writes
-    // the rows that start in its chunk (adding the segment in entry order)
-    {
-      const int chunk = (nj + kAggThreads - 1) / kAggThreads;
-      const int lo = threadIdx.x * chunk, hi = min(nj, lo + chunk);
-      int starts = 0;
-      for (int e = lo; e < hi; ++e) starts += (e == 0 || (jkey[e] >> 24) != (jkey[e - 1] >> 24));
-      s_cnt[threadIdx.x] = starts;
+      __threadfence_block();
       __syncthreads();
-      for (int offs = 1; offs < kAggThreads; offs <<= 1) {
-        const int add = threadIdx.x >= offs ? s_cnt[threadIdx.x - offs] : 0;
-        __syncthreads();
-        s_cnt[threadIdx.x] += add;
-        __syncthreads();
-      }
-      int row = s_cnt[threadIdx.x] - starts;
-      for (int e = lo; e < hi; ++e) {
-        const uint64_t gv = jkey[e] >> 24;
-        if (!(e == 0 || gv != (jkey[e - 1] >> 24))) continue;
-        double g[3] = {0.0, 0.0, 0.0};
-        for (int f = e; f < nj && (jkey[f] >> 24) == gv; ++f) {
-          const int32_t c4 = jidx[f];
-          const int64_t c = c4 >> 2;
-          const int role = c4 & 3;
-          for (int q = 0; q < 3; ++q) g[q] += ct_grad[12 * c + 3 * role + q];
-        }
-        row_vtx_tmp[4 * off + row] = (int32_t)gv;
-        for (int q = 0; q < 3; ++q) row_g_tmp[3 * (4 * off + row) + q] = g[q];
-        ++row;
-      }
-      if (threadIdx.x == kAggThreads - 1) pair_rows[p] = s_cnt[kAggThreads - 1];
-      __syncthreads();
+      bitonic_global(jkey, jidx, nj2);
+      write_rows(
+          nj, [&](int e) { return jkey[e] >> 24; }, [&](int e) { return jidx[e]; }, s_cnt, ct_grad,
+          row_vtx_tmp + 4 * off, row_g_tmp + 3 * (4 * off), pair_rows + p);
     }
   }
 }
@@ -313,14 +526,19 @@ void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, cons
                        int32_t *cursor, int32_t *perm, hipStream_t st) {
   k_ct_scatter<<<g1(ct_cap, 256), 256, 0, st>>>(ct, ct_cap, cnt, pair_off, cursor, perm);
 }
+void launch_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order, double *pair_V,
+                       int32_t *pair_hasvt, int32_t *pair_rows, hipStream_t st) {
+  k_pair_order<<<g1(pairs_cap, 256), 256, 0, st>>>(cnt, pairs_cap, pair_off, order, pair_V, pair_hasvt, pair_rows);
+}
 void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
-                              const Counters *cnt, const int64_t *pair_off, const int32_t *perm, const Cand *ct,
+                              const Counters *cnt, const int32_t *order, const int64_t *pair_off, const int32_t *perm,
+                              const Cand *ct,
                               const double *ct_s, const double *ct_vol, const double *ct_grad, double dt,
                               uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_s,
                               double *out_vol, double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
                               int32_t *pair_rows, int32_t *row_vtx_tmp, double *row_g_tmp, hipStream_t st) {
   k_ct_sort_aggregate<<<g1(pairs_cap, 1), kAggThreads, 0, st>>>(
-      S, T, pairs, cnt, pair_off, perm, ct, ct_s, ct_vol, ct_grad, dt, gkeys, gidx, out_key, out_tau, out_s, out_vol,
+      S, T, pairs, cnt, order, pair_off, perm, ct, ct_s, ct_vol, ct_grad, dt, gkeys, gidx, out_key, out_tau, out_s, out_vol,
       out_grad, cap_ct, pair_V, pair_hasvt, pair_rows, row_vtx_tmp, row_g_tmp, pairs_cap);
 }
 void launch_write_volumes(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, const int64_t *vol_off,

@@ -136,6 +136,7 @@ struct Counters {
   unsigned long long work_claimed;  // work-item chunks handed out by the primitive kernel
   unsigned long long search_exhausted;  // root searches stopped by their budget of intervals
   unsigned long long cp_key_bits[2];    // OR of the check-point keys, OR of their complements
+  unsigned long long n_pair_order[2];   // vesicle pairs with contacts: large buckets, the others
 };
 
 // Narrow-phase candidate record.
@@ -271,8 +272,13 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t step, flo
 void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st);
 void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
                        int32_t *cursor, int32_t *perm, hipStream_t st);
+// Lists the vesicle pairs with contacts in `order` (cap_pairs entries; large
+// buckets first) and writes the empty results of the others.
+void launch_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order, double *pair_V,
+                       int32_t *pair_hasvt, int32_t *pair_rows, hipStream_t st);
 void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
-                              const Counters *cnt, const int64_t *pair_off, const int32_t *perm, const Cand *ct,
+                              const Counters *cnt, const int32_t *order, const int64_t *pair_off, const int32_t *perm,
+                              const Cand *ct,
                               const double *ct_s, const double *ct_vol, const double *ct_grad, double dt,
                               uint64_t *gkeys, int32_t *gidx, int32_t *out_key, double *out_tau, double *out_s,
                               double *out_vol, double *out_grad, int64_t cap_ct, double *pair_V, int32_t *pair_hasvt,
