@@ -270,15 +270,20 @@ __device__ inline bool ov6f(const float *A, const float *B) {
 // m -> round_down(fl(fl(m - h) + sh)) is monotone, so the min over vertices
 // of the rounded vertex bounds is the rounded bound of the min: the same box
 // as rounding the primitive's FP64 box.
+// nvert (1, 2 or 3) is wave-uniform.  All slot loads, then all box loads, are
+// issued together (an edge repeats its second end as the third corner).
 __device__ inline void prim_box32(const float (*vbox)[6], const uint8_t *slot, int nvert, float *out) {
+  if (nvert == 1) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) out[c] = vbox[slot[0]][c];
-  for (int k = 1; k < nvert; ++k)
+    for (int c = 0; c < 6; ++c) out[c] = vbox[slot[0]][c];
+    return;
+  }
+  const int s0 = slot[0], s1 = slot[1], s2 = slot[nvert - 1];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      out[c] = fminf(out[c], vbox[slot[k]][c]);
-      out[3 + c] = fmaxf(out[3 + c], vbox[slot[k]][3 + c]);
-    }
+  for (int c = 0; c < 3; ++c) {
+    out[c] = fminf(fminf(vbox[s0][c], vbox[s1][c]), vbox[s2][c]);
+    out[3 + c] = fmaxf(fmaxf(vbox[s0][3 + c], vbox[s1][3 + c]), vbox[s2][3 + c]);
+  }
 }
 
 template <int TILE>
@@ -654,7 +659,9 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
         }
         nr += __popcll(m);
       }
-      const unsigned long long magic = nr ? ((1ull << 32) + (unsigned long long)nr - 1ull) / (unsigned long long)nr : 0ull;
+      // the sweep's lanes step through t = x * nr + y by 64 = q64 * nr + r64
+      const int q64 = nr ? 64 / nr : 0, r64 = 64 - q64 * nr;
+      const int x_lane = nr ? threadIdx.x / nr : 0, y_lane = threadIdx.x - x_lane * nr;
       for (int l0 = 0; l0 < (nr ? lcount : 0); l0 += 64) {
         const int k = l0 + lane;
         float bx[6];
@@ -672,18 +679,22 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
         }
         const int nl = __popcll(m);
         __syncthreads();
-        // all left x right pairs, 64 per round; t = x * nr + y, with x = t / nr
-        // as (t * ceil(2^32 / nr)) >> 32, exact for t < 2^16 (t <= 64 * 128 here)
+        // all left x right pairs, 64 per round: lane tests pair (x, y) of
+        // t = x * nr + y, and (x, y) advances by 64 each round without a
+        // division (t < nl * nr exactly when x < nl)
         const int tot = nl * nr;
         ntests += (unsigned long long)tot;
+        int xr = x_lane, yr = y_lane;
         // two rounds per iteration, every load of both issued before either
         // ballot (lanes past the end test pair 0 and discard it)
         for (int t0 = 0; t0 < tot; t0 += 128) {
-          const int ta = t0 + lane, tb = t0 + 64 + lane;
-          const bool va = ta < tot, vb = tb < tot;
-          const unsigned int ua = va ? (unsigned int)ta : 0u, ub = vb ? (unsigned int)tb : 0u;
-          const int xa = (int)(((unsigned long long)ua * magic) >> 32), ya = (int)ua - xa * nr;
-          const int xb = (int)(((unsigned long long)ub * magic) >> 32), yb = (int)ub - xb * nr;
+          int xn = xr + q64, yn = yr + r64;
+          if (yn >= nr) { yn -= nr; ++xn; }
+          const bool va = xr < nl, vb = xn < nl;
+          const int xa = va ? xr : 0, ya = va ? yr : 0, xb = vb ? xn : 0, yb = vb ? yn : 0;
+          xr = xn + q64;
+          yr = yn + r64;
+          if (yr >= nr) { yr -= nr; ++xr; }
           const bool ha = va & ov6f_lds(W.lbox[xa], W.rbox[ya]);
           const bool hb = vb & ov6f_lds(W.lbox[xb], W.rbox[yb]);
           const uint32_t ra = ((uint32_t)kind << 16) | ((uint32_t)W.lk[xa] << 8) | (uint32_t)W.rk[ya];
