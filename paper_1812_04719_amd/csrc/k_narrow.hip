@@ -97,6 +97,10 @@ __device__ inline void bracket_features(const Quad &Q, float out[mlp::kIn]) {
   }
 }
 
+// Slot of queue index i (vertex-triangle candidates first, then edge-edge
+// ones, which fill the queue from its back).
+__device__ inline int64_t queue_slot(int64_t i, int64_t n_vt, int64_t cap) { return i < n_vt ? i : cap - 1 - (i - n_vt); }
+
 struct BracketLds {
   mlp::Weights W;
   alignas(16) unsigned short x[256][mlp::kXS];
@@ -111,8 +115,13 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
                                                 double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
                                                 int64_t ct_cap, const void *mlp_packed, float kwidth,
                                                 Counters *cnt) {
-  int64_t nc = (int64_t)cnt->n_hard;
-  nc = nc < hard_cap ? nc : hard_cap;
+  // the queue: vertex-triangle candidates at its front, edge-edge ones at
+  // its back; index i < n_vt is slot i, the others count from the back
+  const unsigned long long vt_ee = cnt->n_hard_vt_ee;
+  int64_t n_vt = (int64_t)(vt_ee & 0xffffffffull), n_ee = (int64_t)(vt_ee >> 32);
+  n_vt = n_vt < hard_cap ? n_vt : hard_cap;
+  n_ee = n_ee < hard_cap - n_vt ? n_ee : hard_cap - n_vt;
+  const int64_t nc = n_vt + n_ee;
   int within = 0, deg = 0, exh = 0, cert = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   extern __shared__ char dyn_lds[];
@@ -133,8 +142,9 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
   if (!LEARNED) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 < nc) {
-      cn = hard[i0];
-      load_geo(geo, hard_cap, i0, cn.kind == 2, Qn);
+      const int64_t q = queue_slot(i0, n_vt, hard_cap);
+      cn = hard[q];
+      load_geo(geo, hard_cap, q, cn.kind == 2, Qn);
     }
   }
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {
@@ -142,15 +152,17 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
     int hit = 0;
     double s = 0.0, V = 0.0, g[12];
     if (LEARNED && i < nc) {
-      cn = hard[i];
-      load_geo(geo, hard_cap, i, cn.kind == 2, Qn);
+      const int64_t q = queue_slot(i, n_vt, hard_cap);
+      cn = hard[q];
+      load_geo(geo, hard_cap, q, cn.kind == 2, Qn);
     }
     const Cand c = cn;
     const Quad Q = Qn;
     for (int k = 0; k < 12; ++k) g[k] = 0.0;
     if (!LEARNED && i + stride < nc) {
-      cn = hard[i + stride];
-      load_geo(geo, hard_cap, i + stride, cn.kind == 2, Qn);
+      const int64_t q = queue_slot(i + stride, n_vt, hard_cap);
+      cn = hard[q];
+      load_geo(geo, hard_cap, q, cn.kind == 2, Qn);
     }
     if (LEARNED) {
       {

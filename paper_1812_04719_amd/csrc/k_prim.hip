@@ -293,22 +293,38 @@ __device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, in
 
 // Queue the listed candidates of the current item (W.queued[0 .. nq)) for
 // the root search: keys with global primitive ids, and the FP64 geometry from
-// LDS.  One atomic for all of them.  All 64 lanes take part.
+// LDS.  Vertex-triangle candidates fill the queue from its front, edge-edge
+// ones from its back (so the root-search wavefronts are mostly of one kind,
+// and those of edge-edge candidates skip the volume code); one atomic on the
+// packed pair of counts for all of them.  All 64 lanes take part.
 template <int TILE>
 __device__ void flush_queued(WaveLds<TILE> &W, int p, Cand *hard, double *geo, int64_t hard_cap, Counters *cnt,
                              int nq) {
   using Lay = BlobLayout<TILE>;
   const int lane = threadIdx.x;
+  const unsigned long long lt = lanemask_lt();
+  int n_ee = 0;
+  for (int r0 = 0; r0 < nq; r0 += 64)
+    n_ee += __popcll(__ballot(r0 + lane < nq && ((W.queued[r0 + lane] >> 16) & 3u) == 2u));
   unsigned long long b = 0;
-  if (lane == 0) b = atomicAdd(&cnt->n_hard, (unsigned long long)nq);
+  if (lane == 0)
+    b = atomicAdd(&cnt->n_hard_vt_ee, ((unsigned long long)n_ee << 32) | (unsigned long long)(nq - n_ee));
   b = __shfl(b, 0, 64);
+  unsigned long long b_vt = b & 0xffffffffull, b_ee = b >> 32;
   for (int r0 = 0; r0 < nq; r0 += 64) {
     const int k = r0 + lane;
-    if (k >= nq) break;
-    const uint32_t hv = W.queued[k];
+    const uint32_t hv = k < nq ? W.queued[k] : 0u;
     const int kind = (int)((hv >> 16) & 3u), kl = (int)((hv >> 8) & 0xffu), kr = (int)(hv & 0xffu);
     const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
     const bool ee = kind == 2;
+    const unsigned long long m_ee = __ballot(k < nq && ee), m_vt = __ballot(k < nq && !ee);
+    const unsigned long long r_ee = b_ee + __popcll(m_ee & lt), r_vt = b_vt + __popcll(m_vt & lt);
+    b_ee += __popcll(m_ee);
+    b_vt += __popcll(m_vt);
+    if (k >= nq) break;
+    // rank r from the back is slot hard_cap - 1 - r
+    if ((int64_t)(ee ? r_ee : r_vt) >= hard_cap) continue;
+    const unsigned long long slot = ee ? (unsigned long long)(hard_cap - 1) - r_ee : r_vt;
     int slots[4];
     if (ee) {
       const uint8_t *el = blob_bytes(W, sl, Lay::eslot), *er = blob_bytes(W, sr, Lay::eslot);
@@ -319,8 +335,6 @@ __device__ void flush_queued(WaveLds<TILE> &W, int p, Cand *hard, double *geo, i
       slots[0] = vl[kl];
       slots[1] = tr[3 * kr]; slots[2] = tr[3 * kr + 1]; slots[3] = tr[3 * kr + 2];
     }
-    const unsigned long long slot = b + (unsigned long long)k;
-    if ((int64_t)slot >= hard_cap) continue;
     Cand c;
     c.pair = p;
     c.kind = kind;

@@ -125,7 +125,8 @@ struct Counters {
   unsigned long long n_work;       // patch-pair work items
   unsigned long long n_pre;        // FP32 pre-candidates (superset of the exact candidates)
   unsigned long long n_cand_vt, n_cand_ee;  // exact FP64 candidates
-  unsigned long long n_hard;       // candidates whose F changes sign on [0,1] (root search)
+  unsigned long long n_hard_vt_ee;  // root-search queue: vertex-triangle (low 32 bits) and edge-edge
+                                    // (high 32 bits) candidates, from its front and from its back
   unsigned long long n_cand_list;  // candidates written to the optional list
   unsigned long long n_ct, n_ct_vt, n_ct_ee;
   unsigned long long n_vol, n_jrow;
@@ -138,6 +139,11 @@ struct Counters {
   unsigned long long cp_key_bits[2];    // OR of the check-point keys, OR of their complements
   unsigned long long n_pair_order[2];   // vesicle pairs with contacts: large buckets, the others
 };
+
+// Candidates queued for the root search (both kinds).
+__host__ __device__ inline unsigned long long hard_total(unsigned long long vt_ee) {
+  return (vt_ee & 0xffffffffull) + (vt_ee >> 32);
+}
 
 // Narrow-phase candidate record.
 struct Cand {

@@ -675,7 +675,7 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
 static stiv_status read_counts(stiv_ctx *ctx, const stiv_params *p, stiv_result *out, bool *internal_overflow) {
   const Counters &c = *ctx->h_cnt;
   *internal_overflow = (int64_t)c.n_cp > ctx->cap_cp || (int64_t)c.n_pairs > ctx->cap_pairs || c.hash_overflow ||
-                       (int64_t)c.n_work > ctx->cap_work || (int64_t)c.n_hard > ctx->cap_cand ||
+                       (int64_t)c.n_work > ctx->cap_work || (int64_t)hard_total(c.n_hard_vt_ee) > ctx->cap_cand ||
                        (int64_t)c.n_ct > ctx->cap_ct ||
                        ((p->flags & STIV_EMIT_CANDIDATES) && (int64_t)c.n_cand_list > ctx->cap_list);
   if (c.nonfinite) return fail(ctx, STIV_E_NUMERIC, "a position is NaN or infinite");
@@ -744,7 +744,11 @@ stiv_status stiv_detect(stiv_ctx *ctx, const stiv_scene *s, const stiv_params *p
       grow = true;
     }
     if ((int64_t)c.n_work > ctx->cap_work) { ctx->cap_work = (int64_t)c.n_work + c.n_work / 4 + 1024; grow = true; }
-    if ((int64_t)c.n_hard > ctx->cap_cand) { ctx->cap_cand = (int64_t)c.n_hard + c.n_hard / 4 + 1024; grow = true; }
+    if ((int64_t)hard_total(c.n_hard_vt_ee) > ctx->cap_cand) {
+      const int64_t nh = (int64_t)hard_total(c.n_hard_vt_ee);
+      ctx->cap_cand = nh + nh / 4 + 1024;
+      grow = true;
+    }
     if ((p->flags & STIV_EMIT_CANDIDATES) && (int64_t)c.n_cand_list > ctx->cap_list) {
       ctx->cap_list = (int64_t)c.n_cand_list + c.n_cand_list / 4 + 1024;
       grow = true;
@@ -940,7 +944,7 @@ stiv_status stiv_get_stats(stiv_ctx *ctx, int64_t *vals, int n) {
   const Counters &c = *ctx->h_cnt;
   const int64_t v[10] = {(int64_t)c.n_cp,      (int64_t)c.n_pairs,   (int64_t)c.n_work,
                          (int64_t)c.n_pre,     (int64_t)c.n_cand_vt, (int64_t)c.n_cand_ee,
-                         (int64_t)c.n_hard,    (int64_t)c.n_ct,      (int64_t)c.n_tests,
+                         (int64_t)hard_total(c.n_hard_vt_ee), (int64_t)c.n_ct,      (int64_t)c.n_tests,
                          (int64_t)c.n_bracket_ok};
   for (int k = 0; k < n && k < 10; ++k) vals[k] = v[k];
   return STIV_OK;
