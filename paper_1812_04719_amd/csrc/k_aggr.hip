@@ -2,10 +2,10 @@
 // the vertex-triangle volumes V_k; Sec. 3.3.2: the Jacobian J = dV/dX1 is
 // stored per (volume, vertex)).
 //
-// Contacts arrive in arbitrary order from the narrow phase.  They are
-// bucketed by vesicle pair (count, scan, scatter), then one workgroup per
-// pair sorts its bucket by (kind, i, j) with a bitonic network in LDS (in a
-// global scratch slice when the bucket is larger than LDS), writes the
+// Contacts arrive in arbitrary order from the narrow phase, which also counts
+// them per vesicle pair.  They are bucketed by pair (scan, scatter), then one
+// workgroup per pair sorts its bucket by (kind, i, j) with a bitonic network
+// in LDS (in a global scratch slice when the bucket is larger than LDS), writes the
 // contacts in canonical order, sums V in that order, and forms the J rows by
 // sorting the 4 per-contact vertex contributions by (vertex, contact order)
 // and adding each run in order.  Sums therefore follow one fixed order and
@@ -40,16 +40,6 @@ __device__ inline int wave_grouped_add(int32_t *ctr, int key) {
     todo &= ~grp;
   }
   return mine;
-}
-
-__global__ void k_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt) {
-  int64_t n = (int64_t)cnt->n_ct;
-  n = n < ct_cap ? n : ct_cap;
-  // whole wavefronts run every iteration (the grouped add is a wavefront operation)
-  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    (void)wave_grouped_add(pair_cnt, i < n ? ct[i].pair : -1);
-  }
 }
 
 __global__ void k_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
@@ -519,9 +509,6 @@ int g1(int64_t n, int t) {
 
 }  // namespace
 
-void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st) {
-  k_ct_pair_count<<<g1(ct_cap, 256), 256, 0, st>>>(ct, ct_cap, cnt, pair_cnt);
-}
 void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
                        int32_t *cursor, int32_t *perm, hipStream_t st) {
   k_ct_scatter<<<g1(ct_cap, 256), 256, 0, st>>>(ct, ct_cap, cnt, pair_off, cursor, perm);

@@ -97,6 +97,21 @@ __device__ inline void bracket_features(const Quad &Q, float out[mlp::kIn]) {
   }
 }
 
+// Adds each lane's 1 to cnt[key] with one atomic per distinct key of the
+// wavefront (lanes with key < 0 take no part): the contacts per vesicle pair
+// that the aggregation buckets by.
+__device__ inline void wave_count(int32_t *ctr, int key) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int k0 = __shfl(key, leader, 64);
+    const unsigned long long grp = __ballot(key == k0) & todo;
+    if (lane == leader) atomicAdd(&ctr[k0], __popcll(grp));
+    todo &= ~grp;
+  }
+}
+
 // Slot of queue index i (vertex-triangle candidates first, then edge-edge
 // ones, which fill the queue from its back).
 __device__ inline int64_t queue_slot(int64_t i, int64_t n_vt, int64_t cap) { return i < n_vt ? i : cap - 1 - (i - n_vt); }
@@ -113,8 +128,8 @@ template <int N, bool LEARNED>
 __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *geo, int64_t hard_cap, double d,
                                                 double eps,
                                                 double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                                                int64_t ct_cap, const void *mlp_packed, float kwidth,
-                                                Counters *cnt) {
+                                                int64_t ct_cap, int32_t *pair_cnt, const void *mlp_packed,
+                                                float kwidth, Counters *cnt) {
   // the queue: vertex-triangle candidates at its front, edge-edge ones at
   // its back; index i < n_vt is slot i, the others count from the back
   const unsigned long long vt_ee = cnt->n_hard_vt_ee;
@@ -221,8 +236,10 @@ __global__ __launch_bounds__(256) void k_narrow(const Cand *hard, const double *
       if (nh - nee_w) atomicAdd(&cnt->n_ct_vt, (unsigned long long)(nh - nee_w));
     }
     slot0 = __shfl(slot0, leader, 64);
+    const unsigned long long slot = slot0 + __popcll(m & lanemask_lt());
+    // the stored contacts, counted per vesicle pair
+    wave_count(pair_cnt, hit && (int64_t)slot < ct_cap ? c.pair : -1);
     if (hit) {
-      const unsigned long long slot = slot0 + __popcll(m & lanemask_lt());
       if ((int64_t)slot < ct_cap) {
         ct[slot] = c;
         ct_s[slot] = s;
@@ -248,25 +265,25 @@ static int grid_for(int64_t n, int max_blocks) {
 
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard,
                    const double *hard_geo, int64_t hard_cap, double d, double eps, double dt, Cand *ct, double *ct_s,
-                   double *ct_vol, double *ct_grad, int64_t ct_cap, const void *mlp_packed, float kwidth,
-                   Counters *cnt, hipStream_t st) {
+                   double *ct_vol, double *ct_grad, int64_t ct_cap, int32_t *pair_cnt, const void *mlp_packed,
+                   float kwidth, Counters *cnt, hipStream_t st) {
   (void)S; (void)T; (void)pairs;
   const int g = grid_for(hard_cap, blocks);
   const size_t lds = sizeof(BracketLds);
   if (mlp_packed) {
     if (d == 0.0)
       k_narrow<3, true><<<g, 256, lds, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
-                                            mlp_packed, kwidth, cnt);
+                                            pair_cnt, mlp_packed, kwidth, cnt);
     else
       k_narrow<6, true><<<g, 256, lds, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
-                                            mlp_packed, kwidth, cnt);
+                                            pair_cnt, mlp_packed, kwidth, cnt);
   } else {
     if (d == 0.0)
       k_narrow<3, false><<<g, 256, 0, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
-                                           nullptr, 0.0f, cnt);
+                                           pair_cnt, nullptr, 0.0f, cnt);
     else
       k_narrow<6, false><<<g, 256, 0, st>>>(hard, hard_geo, hard_cap, d, eps, dt, ct, ct_s, ct_vol, ct_grad, ct_cap,
-                                           nullptr, 0.0f, cnt);
+                                           pair_cnt, nullptr, 0.0f, cnt);
   }
 }
 

@@ -243,7 +243,8 @@ void launch_prim_cand(int tile, int blocks, const DevScene &S, const DevTopo &T,
 void launch_narrow(int blocks, const DevScene &S, const DevTopo &T, const PairRec *pairs, const Cand *hard,
                    const double *hard_geo, int64_t hard_cap,
                    double d, double eps, double dt, Cand *ct, double *ct_s, double *ct_vol, double *ct_grad,
-                   int64_t ct_cap, const void *mlp_packed, float kwidth, Counters *cnt, hipStream_t st);
+                   int64_t ct_cap, int32_t *pair_cnt, const void *mlp_packed, float kwidth, Counters *cnt,
+                   hipStream_t st);
 
 // LCP matrix assembly (Alg. 3)
 void launch_lcp_layout(const int *vtx_off, int n_ves, const int32_t *j_vtx, int64_t n_jrow, int32_t *flag,
@@ -275,7 +276,6 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t step, flo
                  hipStream_t st);
 
 // K5
-void launch_ct_pair_count(const Cand *ct, int64_t ct_cap, const Counters *cnt, int32_t *pair_cnt, hipStream_t st);
 void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
                        int32_t *cursor, int32_t *perm, hipStream_t st);
 // Lists the vesicle pairs with contacts in `order` (cap_pairs entries; large

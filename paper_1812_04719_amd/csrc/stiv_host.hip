@@ -642,10 +642,11 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
                 ctx->cap_cand, p->d, p->eps,
                 p->dt,
                 P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol), P<double>(ctx->ct_grad), ctx->cap_ct,
-                (p->flags & STIV_LEARNED_BRACKET) ? ctx->toi_packed.p : nullptr, ctx->toi_kwidth, cnt, st);
+                P<int32_t>(ctx->pair_cnt), (p->flags & STIV_LEARNED_BRACKET) ? ctx->toi_packed.p : nullptr,
+                ctx->toi_kwidth, cnt, st);
   if (timed) (void)hipEventRecord(ctx->ev[5], st);
   // ---- K5 aggregation
-  launch_ct_pair_count(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int32_t>(ctx->pair_cnt), st);
+  // (the root search counted the contacts of each pair into pair_cnt)
   const unsigned long long *n_pairs_dev = &cnt->n_pairs;
   launch_scan_i32_to_i64(P<int32_t>(ctx->pair_cnt), P<int64_t>(ctx->pair_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
   launch_ct_scatter(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int64_t>(ctx->pair_off), P<int32_t>(ctx->pair_cursor),
