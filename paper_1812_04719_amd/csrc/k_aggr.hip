@@ -42,11 +42,12 @@ __device__ inline int wave_grouped_add(int32_t *ctr, int key) {
   return mine;
 }
 
-__global__ void k_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
-                             int32_t *cursor, int32_t *perm) {
+// Bucketing: contact i goes to its pair's bucket (workgroup `blk` of `nblk`).
+__device__ void ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
+                           int32_t *cursor, int32_t *perm, int blk, int nblk) {
   int64_t n = (int64_t)cnt->n_ct;
   n = n < ct_cap ? n : ct_cap;
-  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i0 = blk * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)nblk * blockDim.x) {
     const int64_t i = i0 + threadIdx.x;
     const int p = i < n ? ct[i].pair : -1;
     const int pos = wave_grouped_add(cursor, p);
@@ -213,14 +214,14 @@ __device__ __forceinline__ void write_rows(int nj, VTX vtx, CON con, int *s_cnt,
 // atomics; it decides only which workgroup takes a pair, not any result.
 constexpr int kBigPair = 128;
 
-__global__ void k_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order,
-                             double *pair_V, int32_t *pair_hasvt, int32_t *pair_rows) {
+__device__ void pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order,
+                           double *pair_V, int32_t *pair_hasvt, int32_t *pair_rows, int blk, int nblk) {
   int64_t np = (int64_t)cnt->n_pairs;
   np = np < pairs_cap ? np : pairs_cap;
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   // whole wavefronts run every iteration (the appends are wavefront operations)
-  for (int64_t p0 = blockIdx.x * (int64_t)blockDim.x; p0 < np; p0 += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t p0 = blk * (int64_t)blockDim.x; p0 < np; p0 += (int64_t)nblk * blockDim.x) {
     const int64_t p = p0 + threadIdx.x;
     int cls = -1;
     if (p < np) {
@@ -249,8 +250,20 @@ __global__ void k_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pa
   }
 }
 
+// Both steps after the scan of the per-pair counts, in one launch: the first
+// n_scatter workgroups bucket the contacts, the others list the pairs.
+__global__ void k_ct_scatter_order(const Cand *ct, int64_t ct_cap, Counters *cnt, const int64_t *pair_off,
+                                   int32_t *cursor, int32_t *perm, int64_t pairs_cap, int32_t *order, double *pair_V,
+                                   int32_t *pair_hasvt, int32_t *pair_rows, int n_scatter) {
+  if ((int)blockIdx.x < n_scatter)
+    ct_scatter(ct, ct_cap, cnt, pair_off, cursor, perm, blockIdx.x, n_scatter);
+  else
+    pair_order(cnt, pairs_cap, pair_off, order, pair_V, pair_hasvt, pair_rows, blockIdx.x - n_scatter,
+               gridDim.x - n_scatter);
+}
+
 // One workgroup per vesicle pair with contacts (grid-stride over the list of
-// k_pair_order, large buckets first).  Buckets of up to kLdsSort
+// pair_order, large buckets first).  Buckets of up to kLdsSort
 // contacts (J entries) are sorted in LDS as single 64-bit keys carrying the
 // entry's position in their low bits; larger ones as (key, index) pairs in a
 // global slice.  Every gather phase issues a thread's loads before its stores.
@@ -509,13 +522,12 @@ int g1(int64_t n, int t) {
 
 }  // namespace
 
-void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
-                       int32_t *cursor, int32_t *perm, hipStream_t st) {
-  k_ct_scatter<<<g1(ct_cap, 256), 256, 0, st>>>(ct, ct_cap, cnt, pair_off, cursor, perm);
-}
-void launch_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order, double *pair_V,
-                       int32_t *pair_hasvt, int32_t *pair_rows, hipStream_t st) {
-  k_pair_order<<<g1(pairs_cap, 256), 256, 0, st>>>(cnt, pairs_cap, pair_off, order, pair_V, pair_hasvt, pair_rows);
+void launch_ct_scatter_order(const Cand *ct, int64_t ct_cap, Counters *cnt, const int64_t *pair_off,
+                             int32_t *cursor, int32_t *perm, int64_t pairs_cap, int32_t *order, double *pair_V,
+                             int32_t *pair_hasvt, int32_t *pair_rows, hipStream_t st) {
+  const int ns = g1(ct_cap, 256), no = g1(pairs_cap, 256);
+  k_ct_scatter_order<<<ns + no, 256, 0, st>>>(ct, ct_cap, cnt, pair_off, cursor, perm, pairs_cap, order, pair_V,
+                                              pair_hasvt, pair_rows, ns);
 }
 void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                               const Counters *cnt, const int32_t *order, const int64_t *pair_off, const int32_t *perm,

@@ -276,12 +276,12 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t step, flo
                  hipStream_t st);
 
 // K5
-void launch_ct_scatter(const Cand *ct, int64_t ct_cap, const Counters *cnt, const int64_t *pair_off,
-                       int32_t *cursor, int32_t *perm, hipStream_t st);
-// Lists the vesicle pairs with contacts in `order` (cap_pairs entries; large
-// buckets first) and writes the empty results of the others.
-void launch_pair_order(Counters *cnt, int64_t pairs_cap, const int64_t *pair_off, int32_t *order, double *pair_V,
-                       int32_t *pair_hasvt, int32_t *pair_rows, hipStream_t st);
+// Buckets the contacts by vesicle pair (perm), and lists the pairs with
+// contacts in `order` (cap_pairs entries; large buckets first) while writing
+// the empty results of the others.
+void launch_ct_scatter_order(const Cand *ct, int64_t ct_cap, Counters *cnt, const int64_t *pair_off,
+                             int32_t *cursor, int32_t *perm, int64_t pairs_cap, int32_t *order, double *pair_V,
+                             int32_t *pair_hasvt, int32_t *pair_rows, hipStream_t st);
 void launch_ct_sort_aggregate(const DevScene &S, const DevTopo &T, const PairRec *pairs, int64_t pairs_cap,
                               const Counters *cnt, const int32_t *order, const int64_t *pair_off, const int32_t *perm,
                               const Cand *ct,

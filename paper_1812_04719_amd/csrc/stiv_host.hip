@@ -649,11 +649,10 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   // (the root search counted the contacts of each pair into pair_cnt)
   const unsigned long long *n_pairs_dev = &cnt->n_pairs;
   launch_scan_i32_to_i64(P<int32_t>(ctx->pair_cnt), P<int64_t>(ctx->pair_off), n_pairs_dev, ctx->cap_pairs, P<int64_t>(ctx->scan_tmp), st);
-  launch_ct_scatter(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int64_t>(ctx->pair_off), P<int32_t>(ctx->pair_cursor),
-                    P<int32_t>(ctx->perm), st);
   // the per-pair counts are consumed by the scan: their buffer holds the list of pairs with contacts
-  launch_pair_order(cnt, ctx->cap_pairs, P<int64_t>(ctx->pair_off), P<int32_t>(ctx->pair_cnt), P<double>(ctx->pair_V),
-                    P<int32_t>(ctx->pair_hasvt), P<int32_t>(ctx->pair_rows), st);
+  launch_ct_scatter_order(P<Cand>(ctx->ct), ctx->cap_ct, cnt, P<int64_t>(ctx->pair_off), P<int32_t>(ctx->pair_cursor),
+                          P<int32_t>(ctx->perm), ctx->cap_pairs, P<int32_t>(ctx->pair_cnt), P<double>(ctx->pair_V),
+                          P<int32_t>(ctx->pair_hasvt), P<int32_t>(ctx->pair_rows), st);
   launch_ct_sort_aggregate(S, T, P<PairRec>(ctx->pairs), ctx->cap_pairs, cnt, P<int32_t>(ctx->pair_cnt),
                            P<int64_t>(ctx->pair_off),
                            P<int32_t>(ctx->perm), P<Cand>(ctx->ct), P<double>(ctx->ct_s), P<double>(ctx->ct_vol),
