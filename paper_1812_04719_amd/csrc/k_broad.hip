@@ -148,11 +148,14 @@ __device__ inline uint32_t axis_cell(const SceneGrid &g, int c, double lo, doubl
 }
 
 // One workgroup per scene: the scene's grid (Alg. 1, first steps), then the
-// number of check points of each of its vesicles' boxes.
+// number of check points of each of its vesicles' boxes.  With cp_off (a
+// single scene) the workgroup also scans the counts into the check points'
+// offsets (cp_off[n] = their number), which saves the scan's launch.
 constexpr int kGridU = 4;
 __global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *box, SceneGrid *grid,
-                                                    int64_t *cp_cnt) {
+                                                    int64_t *cp_cnt, int64_t *cp_off) {
   __shared__ double sh_sum[256], sh_lo[3][256], sh_hi[3][256];
+  __shared__ int64_t sh_wave[4];
   __shared__ SceneGrid sg;
   for (int sc = blockIdx.x; sc < S.n_scenes; sc += gridDim.x) {
     const int v0 = S.scene_off[sc], v1 = S.scene_off[sc + 1];
@@ -237,6 +240,33 @@ __global__ __launch_bounds__(256) void k_scene_grid(DevScene S, const double *bo
       }
     }
     __syncthreads();
+    if (cp_off) {
+      // exclusive scan: each thread a contiguous run of vesicles, the runs'
+      // sums scanned within each wavefront by shuffles, then across them
+      const int n = v1 - v0;
+      const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+      const int lo = v0 + (int)threadIdx.x * chunk, hi = lo + chunk < v1 ? lo + chunk : v1;
+      int64_t run = 0;
+      for (int v = lo; v < hi; ++v) run += cp_cnt[v];
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      int64_t incl = run;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63) sh_wave[wave] = incl;
+      __syncthreads();
+      for (int w = 0; w < wave; ++w) incl += sh_wave[w];
+      int64_t at = incl - run;
+      for (int v = lo; v < hi; ++v) {
+        const int64_t c = cp_cnt[v];
+        cp_off[v] = at;
+        at += c;
+      }
+      if (threadIdx.x == blockDim.x - 1) cp_off[v1] = incl;
+      __syncthreads();
+    }
   }
 }
 
@@ -457,10 +487,11 @@ int grid1d(int64_t n, int threads, int maxg = 2048) {
 
 }  // namespace
 
-void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st) {
+void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, int64_t *cp_off,
+                       hipStream_t st) {
   int g = S.n_scenes < 1024 ? S.n_scenes : 1024;
   if (g < 1) return;
-  k_scene_grid<<<g, 256, 0, st>>>(S, ves_box, grid, cp_cnt);
+  k_scene_grid<<<g, 256, 0, st>>>(S, ves_box, grid, cp_cnt, S.n_scenes == 1 ? cp_off : nullptr);
 }
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
                     const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, Counters *cnt,

@@ -211,7 +211,10 @@ void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *
                   hipStream_t st);
 
 // K1
-void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, hipStream_t st);
+// With a single scene, also the check points' offsets (cp_off, the scan of
+// cp_cnt); otherwise cp_off is left to launch_scan_i64.
+void launch_scene_grid(const DevScene &S, const double *ves_box, SceneGrid *grid, int64_t *cp_cnt, int64_t *cp_off,
+                       hipStream_t st);
 // Also ORs every written key and its complement into cnt->cp_key_bits.
 void launch_cp_emit(const DevScene &S, const double *ves_box, const int *ves_scene, const SceneGrid *grid,
                     const int64_t *cp_off, uint64_t *keys, uint32_t *vals, int64_t cap, Counters *cnt,

@@ -606,8 +606,10 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
   }
   if (timed) (void)hipEventRecord(ctx->ev[1], st);
   // ---- K1 vesicle broad phase
-  launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), P<int64_t>(ctx->cp_cnt), st);
-  launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
+  launch_scene_grid(S, P<double>(ctx->ves_box), P<SceneGrid>(ctx->grid), P<int64_t>(ctx->cp_cnt),
+                    P<int64_t>(ctx->cp_off), st);
+  if (S.n_scenes != 1)
+    launch_scan_i64(P<int64_t>(ctx->cp_cnt), P<int64_t>(ctx->cp_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
   launch_cp_emit(S, P<double>(ctx->ves_box), P<int>(ctx->ves_scene), P<SceneGrid>(ctx->grid),
                  P<int64_t>(ctx->cp_off), P<uint64_t>(ctx->cp_keys), P<uint32_t>(ctx->cp_vals), ctx->cap_cp, cnt, st);
   const unsigned long long *n_cp = reinterpret_cast<const unsigned long long *>(P<int64_t>(ctx->cp_off) + N);
