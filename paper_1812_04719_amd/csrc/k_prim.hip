@@ -112,52 +112,55 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
     const int na = (int)(ves_patch_off[pr.a + 1] - pa0), nb = (int)(ves_patch_off[pr.b + 1] - pb0);
     if (threadIdx.x == 0) { nA = 0; nB = 0; }
     __syncthreads();
-    // compaction: a ballot per wavefront and one LDS atomic for its survivors
-    for (int k0 = 0; k0 < na; k0 += blockDim.x) {
+    // compaction: a ballot per wavefront and one LDS atomic for its survivors.
+    // Both vesicles' patches in one pass (A's, then B's), each thread loading
+    // its patch's box and supports before any test: a pair waits for one
+    // round of loads instead of four (A's boxes, A's supports, B's, B's).
+    const double shd[kDopDirs] = {pr.sh[0] + pr.sh[1], pr.sh[0] - pr.sh[1], pr.sh[0] + pr.sh[2],
+                                  pr.sh[0] - pr.sh[2], pr.sh[1] + pr.sh[2], pr.sh[1] - pr.sh[2]};
+    for (int k0 = 0; k0 < na + nb; k0 += blockDim.x) {
       const int k = k0 + threadIdx.x;
+      const bool inA = k < na, inB = !inA && k < na + nb;
+      const int kk = inA ? k : k - na;
       double P[6];
+      float D[kDopVals];
       bool keep = false;
-      if (k < na) {
-        for (int c = 0; c < 6; ++c) P[c] = patch_box[6 * (pa0 + k) + c];
-        keep = ov6(P, boxB);
+      if (inA || inB) {
+        const int64_t slot = inA ? pa0 + kk : pb0 + kk;
+        for (int c = 0; c < 6; ++c) P[c] = patch_box[6 * slot + c];
+        if (kDop)
+          for (int j = 0; j < kDopVals; ++j) D[j] = patch_dop[kDopVals * slot + j];
+        if (inB)
+          for (int c = 0; c < 3; ++c) {
+            P[c] += pr.sh[c];
+            P[3 + c] += pr.sh[c];
+          }
+        const bool kA = ov6(P, boxB), kB = ov6(P, boxA);
+        keep = inA ? kA : kB;
       }
-      const int q = wave_slot(&nA, keep);
-      if (keep) {
+      const int qa = wave_slot(&nA, keep && inA);
+      const int qb = wave_slot(&nB, keep && inB);
+      if (keep && inA) {
         for (int c = 0; c < 3; ++c) {
-          bA[q][c] = __double2float_rd(P[c]);
-          bA[q][3 + c] = __double2float_ru(P[3 + c]);
+          bA[qa][c] = __double2float_rd(P[c]);
+          bA[qa][3 + c] = __double2float_ru(P[3 + c]);
         }
         if (kDop)
-          for (int j = 0; j < kDopVals; ++j) dA[q][j] = patch_dop[kDopVals * (pa0 + k) + j];
-        iA[q] = (short)k;
+          for (int j = 0; j < kDopVals; ++j) dA[qa][j] = D[j];
+        iA[qa] = (short)kk;
       }
-    }
-    for (int k0 = 0; k0 < nb; k0 += blockDim.x) {
-      const int k = k0 + threadIdx.x;
-      double Q[6];
-      bool keep = false;
-      if (k < nb) {
+      if (keep && inB) {
         for (int c = 0; c < 3; ++c) {
-          Q[c] = patch_box[6 * (pb0 + k) + c] + pr.sh[c];
-          Q[3 + c] = patch_box[6 * (pb0 + k) + 3 + c] + pr.sh[c];
-        }
-        keep = ov6(Q, boxA);
-      }
-      const int q = wave_slot(&nB, keep);
-      if (keep) {
-        for (int c = 0; c < 3; ++c) {
-          bB[q][c] = __double2float_rd(Q[c]);
-          bB[q][3 + c] = __double2float_ru(Q[3 + c]);
+          bB[qb][c] = __double2float_rd(P[c]);
+          bB[qb][3 + c] = __double2float_ru(P[3 + c]);
         }
         // B's supports shifted by the image: (1,1,0).sh, (1,-1,0).sh, ...
-        const double shd[kDopDirs] = {pr.sh[0] + pr.sh[1], pr.sh[0] - pr.sh[1], pr.sh[0] + pr.sh[2],
-                                      pr.sh[0] - pr.sh[2], pr.sh[1] + pr.sh[2], pr.sh[1] - pr.sh[2]};
         if (kDop)
           for (int j = 0; j < kDopDirs; ++j) {
-            dB[q][2 * j] = __double2float_rd((double)patch_dop[kDopVals * (pb0 + k) + 2 * j] + shd[j]);
-            dB[q][2 * j + 1] = __double2float_ru((double)patch_dop[kDopVals * (pb0 + k) + 2 * j + 1] + shd[j]);
+            dB[qb][2 * j] = __double2float_rd((double)D[2 * j] + shd[j]);
+            dB[qb][2 * j + 1] = __double2float_ru((double)D[2 * j + 1] + shd[j]);
           }
-        iB[q] = (short)k;
+        iB[qb] = (short)kk;
       }
     }
     __syncthreads();
