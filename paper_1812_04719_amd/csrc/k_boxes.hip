@@ -326,6 +326,49 @@ __global__ void k_ves_tables(DevScene S, DevTopo T, int64_t *patch_cnt, int *ves
 
 
 
+// The same tables for up to kVesTablesOne vesicles in one workgroup, which
+// also scans the patch counts into the vesicles' first patch slots
+// (patch_off[n] = all slots): one launch instead of two.
+constexpr int kVesTablesOne = 8192;
+__global__ __launch_bounds__(1024) void k_ves_tables_one(DevScene S, DevTopo T, int64_t *patch_cnt, int *ves_scene,
+                                                         int64_t *patch_off) {
+  __shared__ int64_t sh_wave[16];
+  const int n = S.n_ves;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = (int)threadIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  int64_t run = 0;
+  for (int v = lo; v < hi; ++v) {
+    const int t = S.topo_id[v];
+    const int64_t c = T.patch_off[t + 1] - T.patch_off[t];
+    patch_cnt[v] = c;
+    run += c;
+    int a = 0, b = S.n_scenes;  // invariant: scene_off[a] <= v < scene_off[b]
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (S.scene_off[mid] <= v) a = mid; else b = mid;
+    }
+    ves_scene[v] = a;
+  }
+  // exclusive scan of the runs: shuffles within each wavefront, then the
+  // totals of the wavefronts before it
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t incl = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) sh_wave[wave] = incl;
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) incl += sh_wave[w];
+  int64_t at = incl - run;
+  for (int v = lo; v < hi; ++v) {
+    patch_off[v] = at;
+    at += patch_cnt[v];
+  }
+  if (threadIdx.x == 1023) patch_off[n] = incl;
+}
+
 }  // namespace
 
 // The FP16 vertex boxes for the patch supports (12 bytes per vertex) fit in
@@ -370,11 +413,16 @@ void launch_boxes(const DevScene &S, const DevTopo &T, double h, const int64_t *
                                               grid_max, cnt, st);
 }
 
-void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st) {
+bool launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, int64_t *patch_off,
+                       hipStream_t st) {
+  if (S.n_ves <= kVesTablesOne) {
+    k_ves_tables_one<<<1, 1024, 0, st>>>(S, T, patch_cnt, ves_scene, patch_off);
+    return true;
+  }
   int g = (S.n_ves + 255) / 256;
-  if (g < 1) return;
   if (g > 1024) g = 1024;
   k_ves_tables<<<g, 256, 0, st>>>(S, T, patch_cnt, ves_scene);
+  return false;
 }
 
 }  // namespace stiv

@@ -197,7 +197,11 @@ void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // K0
-void launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, hipStream_t st);
+// Per vesicle: its patch count and scene index; for scenes of up to a few
+// thousand vesicles also the scan of the counts into patch_off (returns
+// true), which is otherwise left to launch_scan_i64.
+bool launch_ves_tables(const DevScene &S, const DevTopo &T, int64_t *patch_cnt, int *ves_scene, int64_t *patch_off,
+                       hipStream_t st);
 // patch_dop: every patch's face-diagonal supports (kDopVals floats per patch
 // slot).
 // Parts of the box kernel: vesicle and patch boxes; the patches' supports

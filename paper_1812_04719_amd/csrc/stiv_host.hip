@@ -582,8 +582,10 @@ static void run_pipeline(stiv_ctx *ctx, const DevScene &S, const stiv_params *p,
     J.add(P<int32_t>(ctx->pair_cursor), 0ull, ctx->cap_pairs + 1, 4);
     launch_fill_multi(J, st);
   }
-  launch_ves_tables(S, T, P<int64_t>(ctx->ves_patch_cnt), P<int>(ctx->ves_scene), st);
-  launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp), st);
+  if (!launch_ves_tables(S, T, P<int64_t>(ctx->ves_patch_cnt), P<int>(ctx->ves_scene), P<int64_t>(ctx->ves_patch_off),
+                         st))
+    launch_scan_i64(P<int64_t>(ctx->ves_patch_cnt), P<int64_t>(ctx->ves_patch_off), nullptr, N, P<int64_t>(ctx->scan_tmp),
+                    st);
   // ---- K0 boxes.  The patches' face-diagonal supports need only the
   // positions: up to kSplitMaxVesicles vesicles they run on the side stream
   // after the boxes, beside the vesicle broad phase (latency-bound, it leaves
