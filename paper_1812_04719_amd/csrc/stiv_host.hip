@@ -245,12 +245,15 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
     for (int k = 0; k < 3 * NT; ++k) vref[T3[k]] = 1;
     for (int v = 0; v < NV; ++v)
       if (!vref[v]) return fail(ctx, STIV_E_ARG, "set_topology: vertex not on any triangle");
-    // greedy breadth-first patches of up to `tile` neighbouring triangles; a
-    // triangle is not added when the patch would exceed its vertex or edge
-    // capacity for this patch size
+    // greedy breadth-first patches of up to 7/8 of `tile` neighbouring
+    // triangles (a triangle is not added when the patch would exceed its
+    // vertex or edge capacity for this patch size); the growth leaves small
+    // islands behind, which are then merged into a neighbouring patch that
+    // still has room (up to `tile` triangles within the capacities)
     int cap_ref = TileCaps<64>::ref, cap_edge = TileCaps<64>::owne;
     if (ctx->tile == 16) { cap_ref = TileCaps<16>::ref; cap_edge = TileCaps<16>::owne; }
     if (ctx->tile == 32) { cap_ref = TileCaps<32>::ref; cap_edge = TileCaps<32>::owne; }
+    const int grow = ctx->tile - ctx->tile / 8;
     std::vector<int> tpatch(NT, -1);
     std::vector<std::vector<int>> patches;
     for (int seed = 0; seed < NT; ++seed) {
@@ -259,7 +262,7 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
       std::vector<int> verts, edges;
       size_t qh = 0;
       tpatch[seed] = (int)patches.size();
-      while (qh < queue.size() && (int)members.size() < ctx->tile) {
+      while (qh < queue.size() && (int)members.size() < grow) {
         int k = queue[qh++];
         std::vector<int> nv2 = verts, ne2 = edges;
         for (int r = 0; r < 3; ++r) {
@@ -283,6 +286,55 @@ stiv_status stiv_set_topology(stiv_ctx *ctx, const stiv_topology *tp) {
       for (size_t q = qh; q < queue.size(); ++q) tpatch[queue[q]] = -1;  // release unvisited
       for (int k : members) tpatch[k] = (int)patches.size();
       patches.push_back(members);
+    }
+    {
+      // islands of fewer than tile / 4 triangles join the smallest
+      // edge-adjacent patch that can take them, until none can
+      auto fits = [&](const std::vector<int> &tris) {
+        if ((int)tris.size() > ctx->tile) return false;
+        std::vector<int> vs, es;
+        for (int k : tris)
+          for (int r = 0; r < 3; ++r) {
+            vs.push_back(T3[3 * k + r]);
+            es.push_back(tri_edges[3 * k + r]);
+          }
+        std::sort(vs.begin(), vs.end());
+        std::sort(es.begin(), es.end());
+        const int nv = (int)(std::unique(vs.begin(), vs.end()) - vs.begin());
+        const int ne = (int)(std::unique(es.begin(), es.end()) - es.begin());
+        return nv <= cap_ref && ne <= cap_edge;
+      };
+      for (bool changed = true; changed;) {
+        changed = false;
+        for (size_t f = 0; f < patches.size(); ++f) {
+          if (patches[f].empty() || (int)patches[f].size() >= ctx->tile / 4) continue;
+          std::vector<int> nb;
+          for (int k : patches[f])
+            for (int r = 0; r < 3; ++r)
+              for (int k2 : edge_tris[tri_edges[3 * k + r]])
+                if (tpatch[k2] != (int)f) nb.push_back(tpatch[k2]);
+          std::sort(nb.begin(), nb.end());
+          nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+          std::stable_sort(nb.begin(), nb.end(),
+                           [&](int a, int b) { return patches[a].size() < patches[b].size(); });
+          for (int g : nb) {
+            std::vector<int> tris = patches[g];
+            tris.insert(tris.end(), patches[f].begin(), patches[f].end());
+            if (!fits(tris)) continue;
+            for (int k : patches[f]) tpatch[k] = g;
+            patches[g].swap(tris);
+            patches[f].clear();
+            changed = true;
+            break;
+          }
+        }
+      }
+      std::vector<std::vector<int>> kept;
+      for (auto &pt : patches)
+        if (!pt.empty()) kept.push_back(std::move(pt));
+      patches.swap(kept);
+      for (size_t pi = 0; pi < patches.size(); ++pi)
+        for (int k : patches[pi]) tpatch[k] = (int)pi;
     }
     const int np = (int)patches.size();
     if (np > kMaxPatchesPerVes) return fail(ctx, STIV_E_ARG, "set_topology: mesh too large for the patch table");
