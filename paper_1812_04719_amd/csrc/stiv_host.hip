@@ -61,7 +61,8 @@ struct stiv_ctx {
   std::vector<int> h_npatch;  // patches per topology
   int max_patches = 0;
   int tile = 64;            // triangles per patch (16, 32 or 64)
-  int prim_blocks = 8192;   // workgroups of the primitive-candidate kernel
+  int prim_blocks = 4096;   // workgroups of the primitive-candidate kernel (1440 vesicles: 2048 1.25 ms
+                            // per step, 4096 1.21, 8192 1.23, 16384 1.29)
   int narrow_blocks = 8192; // upper bound on workgroups of the root-search kernel
   // arena
   Buf counters, ves_box, ves_scene, grid, cp_cnt, cp_off, cp_keys, cp_vals, cp_tk, cp_tv, hash, uniq, sorted,
