@@ -167,8 +167,11 @@ stiv_status stiv_set_patch_size(stiv_ctx *ctx, int tri_per_patch);
 /* Tuning options (results never depend on them): STIV_OPT_PATCH_TRI
  * (16/32/64, as stiv_set_patch_size), STIV_OPT_PRIM_BLOCKS and
  * STIV_OPT_NARROW_BLOCKS (workgroups of the persistent primitive and
- * root-search kernels, 256..65536). */
-enum { STIV_OPT_PATCH_TRI = 1, STIV_OPT_PRIM_BLOCKS = 2, STIV_OPT_NARROW_BLOCKS = 3 };
+ * root-search kernels, 256..65536), STIV_OPT_QUEUE_CAPACITY (the number of
+ * candidates the root-search queue holds before it grows, 64..2^31; detect
+ * grows it and runs again when a step needs more, so a small value only
+ * exercises that path). */
+enum { STIV_OPT_PATCH_TRI = 1, STIV_OPT_PRIM_BLOCKS = 2, STIV_OPT_NARROW_BLOCKS = 3, STIV_OPT_QUEUE_CAPACITY = 4 };
 stiv_status stiv_set_option(stiv_ctx *ctx, int option, int64_t value);
 
 /* Pre-size the scratch arena for scenes of this shape (optional; detect

@@ -892,6 +892,11 @@ stiv_status stiv_set_option(stiv_ctx *ctx, int option, int64_t value) {
       if (value < 256 || value > 65536) return fail(ctx, STIV_E_ARG, "narrow blocks out of range [256, 65536]");
       ctx->narrow_blocks = (int)value;
       return STIV_OK;
+    case STIV_OPT_QUEUE_CAPACITY:
+      if (value < 64 || value > (int64_t)INT32_MAX)
+        return fail(ctx, STIV_E_ARG, "queue capacity out of range [64, 2^31)");
+      ctx->cap_cand = value;  // the buffers only grow: a smaller capacity uses part of them
+      return STIV_OK;
     default:
       return fail(ctx, STIV_E_ARG, "unknown option");
   }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libstiv.so")
 
 STIV_OK, STIV_E_ARG, STIV_E_CAPACITY, STIV_E_HIP, STIV_E_NUMERIC, STIV_E_STATE = 0, -1, -2, -3, -4, -5
 STIV_EMIT_CANDIDATES, STIV_LEARNED_BRACKET = 1, 2
-STIV_OPT_PATCH_TRI, STIV_OPT_PRIM_BLOCKS, STIV_OPT_NARROW_BLOCKS = 1, 2, 3
+STIV_OPT_PATCH_TRI, STIV_OPT_PRIM_BLOCKS, STIV_OPT_NARROW_BLOCKS, STIV_OPT_QUEUE_CAPACITY = 1, 2, 3, 4
 _STATUS = {0: "STIV_OK", -1: "STIV_E_ARG", -2: "STIV_E_CAPACITY", -3: "STIV_E_HIP", -4: "STIV_E_NUMERIC",
            -5: "STIV_E_STATE"}
 

@@ -218,6 +218,24 @@ def test_capacity_retry(ctx):
     parity.compare(res, o, sc, sc.dt, sc.eps)
 
 
+def test_queue_growth(ctx):
+    """A root-search queue far smaller than the step needs (vertex-triangle candidates fill it from
+    its front, edge-edge ones from its back, so both ends overrun each other): detect grows it,
+    runs again and returns the oracle's sets."""
+    from paper_1812_04719_amd import stiv
+    sc = S.make_config(2)
+    ctx.set_option(stiv.STIV_OPT_QUEUE_CAPACITY, 64)
+    try:
+        g = run_gpu(ctx, sc, emit=False)
+        searches = ctx.stats()["root_searches"]
+    finally:
+        ctx.set_option(stiv.STIV_OPT_QUEUE_CAPACITY, 1 << 20)
+    assert searches > 64, searches
+    assert int(g["n_ct_vt"]) > 0 and int(g["n_ct_ee"]) > 0
+    o = oracle.detect(sc)
+    parity.compare(g, o, sc, sc.dt, sc.eps)
+
+
 @pytest.mark.parametrize("tile", [16, 32, 64])
 def test_patch_size_does_not_change_results(ctx, tile):
     """The patch tiling is a performance choice: every size gives the oracle's sets."""
