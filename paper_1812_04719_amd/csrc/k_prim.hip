@@ -263,6 +263,19 @@ struct WaveLds {
   alignas(16) int blob[2][Lay::stage];  // header, slot and id arrays of the two patch blobs
 };
 
+// FP32 values at or below (above) x: the nearest float moved down (up) by
+// 2^-22 of its magnitude, at least two units in its last place, plus 1e-30
+// for values near zero.  Both maps are monotone in x, and cheaper than a
+// conversion with a directed rounding.
+__device__ inline float f32_down(double x) {
+  const float f = (float)x;
+  return f - (fabsf(f) * 2.384185791015625e-07f + 1e-30f);
+}
+__device__ inline float f32_up(double x) {
+  const float f = (float)x;
+  return f + (fabsf(f) * 2.384185791015625e-07f + 1e-30f);
+}
+
 // Overlap of two FP32 boxes in registers (branch-free).
 __device__ inline bool ov6f(const float *A, const float *B) {
   return (A[0] <= B[3]) & (B[0] <= A[3]) & (A[1] <= B[4]) & (B[1] <= A[4]) & (A[2] <= B[5]) & (B[2] <= A[5]);
@@ -270,7 +283,7 @@ __device__ inline bool ov6f(const float *A, const float *B) {
 
 // FP64 box of a primitive (min - h + sh, max + h + sh), rounded outward to
 // FP32, as the min / max of its vertices' FP32 boxes.  The map
-// m -> round_down(fl(fl(m - h) + sh)) is monotone, so the min over vertices
+// m -> f32_down(fl(fl(m - h) + sh)) is monotone, so the min over vertices
 // of the rounded vertex bounds is the rounded bound of the min: the same box
 // as rounding the primitive's FP64 box.
 // nvert (1, 2 or 3) is wave-uniform.  All slot loads, then all box loads, are
@@ -294,7 +307,8 @@ __device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, in
   return reinterpret_cast<const uint8_t *>(&W.blob[side][off]);
 }
 
-// Queue the listed candidates of the current item (W.queued[0 .. nq)) for
+// Queue the listed candidates of the current item (W.queued[0 .. nq), n_ee of
+// them edge-edge) for
 // the root search: keys with global primitive ids, and the FP64 geometry from
 // LDS.  Vertex-triangle candidates fill the queue from its front, edge-edge
 // ones from its back (so the root-search wavefronts are mostly of one kind,
@@ -302,13 +316,10 @@ __device__ inline const uint8_t *blob_bytes(const WaveLds<TILE> &W, int side, in
 // packed pair of counts for all of them.  All 64 lanes take part.
 template <int TILE>
 __device__ void flush_queued(WaveLds<TILE> &W, int p, Cand *hard, double *geo, int64_t hard_cap, Counters *cnt,
-                             int nq) {
+                             int nq, int n_ee) {
   using Lay = BlobLayout<TILE>;
   const int lane = threadIdx.x;
   const unsigned long long lt = lanemask_lt();
-  int n_ee = 0;
-  for (int r0 = 0; r0 < nq; r0 += 64)
-    n_ee += __popcll(__ballot(r0 + lane < nq && ((W.queued[r0 + lane] >> 16) & 3u) == 2u));
   unsigned long long b = 0;
   if (lane == 0)
     b = atomicAdd(&cnt->n_hard_vt_ee, ((unsigned long long)n_ee << 32) | (unsigned long long)(nq - n_ee));
@@ -365,7 +376,7 @@ __device__ void flush_queued(WaveLds<TILE> &W, int p, Cand *hard, double *geo, i
 template <int N, int TILE>
 __device__ void process_hits(WaveLds<TILE> &W, int p, double d, Cand *hard, double *geo, int64_t hard_cap,
                              Cand *list, int64_t list_cap, Counters *cnt, unsigned long long &nvt,
-                             unsigned long long &nee, int nh, int &nq) {
+                             unsigned long long &nee, int nh, int &nq, int &nq_ee) {
   using Lay = BlobLayout<TILE>;
   const int lane = threadIdx.x;
   const double h = 0.5 * d;
@@ -435,6 +446,7 @@ __device__ void process_hits(WaveLds<TILE> &W, int p, double d, Cand *hard, doub
     const unsigned long long mh = __ballot(need);
     if (need) W.queued[nq + __popcll(mh & lanemask_lt())] = hv;
     nq += __popcll(mh);
+    nq_ee += __popcll(__ballot(need && kind == 2));
     if (list) {
       // the optional candidate list (a diagnostic output): one atomic per round
       const unsigned long long mc = __ballot(is_cand);
@@ -457,8 +469,9 @@ __device__ void process_hits(WaveLds<TILE> &W, int p, double d, Cand *hard, doub
     }
     if (nq > kQueueBuf - 64) {  // rare: a long list is queued before the item ends
       __syncthreads();
-      flush_queued<TILE>(W, p, hard, geo, hard_cap, cnt, nq);
+      flush_queued<TILE>(W, p, hard, geo, hard_cap, cnt, nq, nq_ee);
       nq = 0;
+      nq_ee = 0;
       __syncthreads();
     }
   }
@@ -613,14 +626,14 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
         for (int c = 0; c < 3; ++c) {
           const double a = F.pos[side][c], b = F.pos[side][3 + c];
           const double sc = side ? W.sh[c] : 0.0;
-          W.vbox[side][lane][c] = __double2float_rd((fmin(a, b) - h) + sc);
-          W.vbox[side][lane][3 + c] = __double2float_ru((fmax(a, b) + h) + sc);
+          W.vbox[side][lane][c] = f32_down((fmin(a, b) - h) + sc);
+          W.vbox[side][lane][3 + c] = f32_up((fmax(a, b) + h) + sc);
         }
       }
     }
     // the two patch boxes in FP32 (wave-uniform).  The FP64 patch box is
     // fl(m - h) with m the exact minimum (maximum) over the patch's vertices,
-    // and x -> round_down(fl(fl(x - h) + s)) is monotone, so this equals the
+    // and x -> f32_down(fl(fl(x - h) + s)) is monotone, so this equals the
     // union of the vertex boxes above.
     float pb[2][6];
     {
@@ -628,7 +641,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
       if (lane < 12) {
         const int c = lane % 6;
         const double x = F.pbox + (lane >= 6 ? W.sh[c % 3] : 0.0);
-        v = c < 3 ? __double2float_rd(x) : __double2float_ru(x);
+        v = c < 3 ? f32_down(x) : f32_up(x);
       }
 #pragma unroll
       for (int side = 0; side < 2; ++side)
@@ -646,7 +659,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     const int wr_after = load_workrec(work, w_after, nw, lane);
     __syncthreads();
     int nh = 0;  // buffered hits (wave-uniform)
-    int nq = 0;  // listed candidates of this item (wave-uniform)
+    int nq = 0, nq_ee = 0;  // listed candidates of this item, and its edge-edge ones (wave-uniform)
     for (int kind = 0; kind < 3; ++kind) {
       if (kind == 1 && more) load_positions<TILE>(F, S, wr_next, lane, same0_next);
       const int sl = (kind == 1) ? 1 : 0, sr = 1 - sl;
@@ -722,7 +735,7 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
           if (hb) W.hits[nh + __popcll(mb & lanemask_lt())] = rb;
           nh += __popcll(mb);
           if (nh > kHitBuf - 128) {
-            process_hits<N, TILE>(W, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh, nq);
+            process_hits<N, TILE>(W, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh, nq, nq_ee);
             npre += (unsigned long long)nh;
             nh = 0;
           }
@@ -732,10 +745,10 @@ __global__ __launch_bounds__(64) void k_prim_cand(DevScene S, DevTopo T, const P
     }
     // the hits refer to this item's LDS data: finish them before the next item
     if (nh) {
-      process_hits<N, TILE>(W, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh, nq);
+      process_hits<N, TILE>(W, p, d, hard, geo, hard_cap, list, list_cap, cnt, nvt, nee, nh, nq, nq_ee);
       npre += (unsigned long long)nh;
     }
-    if (nq) flush_queued<TILE>(W, p, hard, geo, hard_cap, cnt, nq);
+    if (nq) flush_queued<TILE>(W, p, hard, geo, hard_cap, cnt, nq, nq_ee);
     w = w_next;
     w_next = w_after;
     wr_cur = wr_next;
