@@ -38,15 +38,18 @@ __device__ inline double okey_inv(unsigned long long k) {
 // Folds vertex bounds (keys) into a patch's LDS box.  The box only shrinks
 // toward its final value, so a vertex that does not beat the value read now
 // cannot beat the final one: its atomic is skipped (most vertices of a patch
-// are not extreme, and neighbouring lanes often hit the same patch).
+// are not extreme, and neighbouring lanes often hit the same patch).  Any
+// earlier value is looser than the current one, so the six reads are plain
+// loads, which the compiler may pair into wider ones.
 __device__ inline void fold_box(unsigned long long (*pk)[6], int q, const unsigned long long kl[3],
                                 const unsigned long long ku[3]) {
+  unsigned long long cur[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) cur[c] = pk[q][c];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const unsigned long long lo = __hip_atomic_load(&pk[q][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const unsigned long long hi = __hip_atomic_load(&pk[q][3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (kl[c] < lo) atomicMin(&pk[q][c], kl[c]);
-    if (ku[c] > hi) atomicMax(&pk[q][3 + c], ku[c]);
+    if (kl[c] < cur[c]) atomicMin(&pk[q][c], kl[c]);
+    if (ku[c] > cur[3 + c]) atomicMax(&pk[q][3 + c], ku[c]);
   }
 }
 
@@ -246,10 +249,9 @@ __global__ __launch_bounds__(256) void k_boxes(DevScene S, DevTopo T, double h, 
           if (pu != cur) {  // end of a run of one patch: fold it (skipping what cannot improve)
 #pragma unroll
             for (int j = 0; j < kDopDirs; ++j) {
+              // plain reads: an earlier value is looser (see fold_box)
               const unsigned int kd = fkey(acc[2 * j]), ku = fkey(acc[2 * j + 1]);
-              const unsigned int cd = __hip_atomic_load(&dk[cur][2 * j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-              const unsigned int cu =
-                  __hip_atomic_load(&dk[cur][2 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              const unsigned int cd = dk[cur][2 * j], cu = dk[cur][2 * j + 1];
               if (kd < cd) atomicMin(&dk[cur][2 * j], kd);
               if (ku > cu) atomicMax(&dk[cur][2 * j + 1], ku);
               acc[2 * j] = INFINITY;
