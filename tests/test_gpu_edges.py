@@ -1,6 +1,7 @@
 """Edge cases of the GPU path against the oracle: empty and single-vesicle
-scenes, separated bodies, a static scene starting within d, a finer mesh,
-and the error for a periodic box too small for the image-shift range."""
+scenes, separated bodies, a static scene starting within d, one vesicle pair
+with thousands of contacts, a finer mesh, and the error for a periodic box
+too small for the image-shift range."""
 import numpy as np
 import pytest
 
@@ -66,6 +67,19 @@ def test_static_scene_within_d(ctx):
     assert g["n_ct_vt"] > 0
     assert np.all(g["ct_tau"] == 0.0)
     assert g["n_initially_within_d"] > 0
+
+
+@pytest.mark.parametrize("n, contacts, paths", [
+    (14, 1624, "contacts and J entries sorted in LDS, 2048 keys each (the largest LDS buckets)"),
+    (16, 2115, "contacts sorted in a global slice, J entries in LDS"),
+    (18, 2657, "contacts and J entries sorted in global slices"),
+])
+def test_one_pair_large_buckets(ctx, n, contacts, paths):
+    """Two n x n grids closing through each other: one vesicle pair holds thousands of contacts,
+    so the aggregation takes its paths for large buckets (named in `paths`)."""
+    sc = T.translating_planes(gap=0.05, closing=0.1, d=0.01, n=n)
+    g, o = _check(ctx, sc, emit=False)
+    assert int(g["n_pairs"]) == 1 and int(g["n_ct_vt"]) + int(g["n_ct_ee"]) == contacts, paths
 
 
 def test_finer_mesh_two_spheres(ctx):
