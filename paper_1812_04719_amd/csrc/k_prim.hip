@@ -72,6 +72,48 @@ __device__ inline bool dop_meet(const float *A, const float *B) {
   return ok;
 }
 
+// A vesicle pair's header is spread over the lanes of each wavefront, so
+// the next pair's can be fetched while this pair is worked on, with one
+// vector load per level, and read back with lane reads.  Level 1
+// (pair_word): lane l < 6 holds 64-bit word l of the PairRec (lane 0: a, b;
+// lanes 3-5: the image shift).  Level 2, 64-bit words (head_word): lanes 0-5
+// A's box, 6-11 B's box (unshifted), 12-15 the patch-table offsets of A,
+// A+1, B, B+1; 32-bit words (head_int): lanes 0-1 the vertex offsets of A
+// and B, 2-3 their topology ids.  (Separate registers for the two widths:
+// a 32-bit load merged into a 64-bit register would be waited for on the
+// spot.)
+__device__ inline uint64_t pair_word(const PairRec *pairs, int64_t p, int lane) {
+  uint64_t v = 0;
+  if (lane < 6) v = reinterpret_cast<const uint64_t *>(pairs + p)[lane];
+  return v;
+}
+
+__device__ inline uint64_t head_word(const double *ves_box, const int64_t *ves_patch_off, uint64_t ab, int lane) {
+  const int a = (int)(uint32_t)ab, b = (int)(uint32_t)(ab >> 32);
+  uint64_t v = 0;
+  if (lane < 12)
+    v = (uint64_t)__double_as_longlong(ves_box[6 * (int64_t)(lane < 6 ? a : b) + lane % 6]);
+  else if (lane < 16)
+    v = (uint64_t)ves_patch_off[(lane < 14 ? a : b) + (lane & 1)];
+  return v;
+}
+
+__device__ inline int head_int(const DevScene &S, uint64_t ab, int lane) {
+  const int v = (lane & 1) ? (int)(uint32_t)(ab >> 32) : (int)(uint32_t)ab;
+  int r = 0;
+  if (lane < 2)
+    r = S.vtx_off[v];
+  else if (lane < 4)
+    r = S.topo_id[v];
+  return r;
+}
+
+__device__ inline uint64_t lane_word(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // One workgroup per vesicle pair.  Each side's patch boxes that meet the
 // other vesicle's box are staged in LDS as FP32 boxes rounded outward (a
 // conservative filter: the primitive kernel applies the exact test later),
@@ -98,26 +140,40 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
   int64_t np = (int64_t)cnt->n_pairs;
   np = np < pairs_cap ? np : pairs_cap;
   if (threadIdx.x == 0) nbuf = 0;
-  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
-    const PairRec pr = pairs[p];
-    double boxA[6], boxB[6];
-    for (int c = 0; c < 6; ++c) boxA[c] = ves_box[6 * (int64_t)pr.a + c];
+  const int lane = threadIdx.x & 63;
+  int64_t p = blockIdx.x;
+  uint64_t prw = 0, hdw = 0;  // this pair's header (see pair_word, head_word, head_int)
+  int hdi = 0;
+  if (p < np) {
+    prw = pair_word(pairs, p, lane);
+    const uint64_t ab = lane_word(prw, 0);
+    hdw = head_word(ves_box, ves_patch_off, ab, lane);
+    hdi = head_int(S, ab, lane);
+  }
+  for (; p < np; p += gridDim.x) {
+    double sh[3], boxA[6], boxB[6];
+    for (int c = 0; c < 3; ++c) sh[c] = __longlong_as_double((long long)lane_word(prw, 3 + c));
+    for (int c = 0; c < 6; ++c) boxA[c] = __longlong_as_double((long long)lane_word(hdw, c));
     for (int c = 0; c < 3; ++c) {
-      boxB[c] = ves_box[6 * (int64_t)pr.b + c] + pr.sh[c];
-      boxB[3 + c] = ves_box[6 * (int64_t)pr.b + 3 + c] + pr.sh[c];
+      boxB[c] = __longlong_as_double((long long)lane_word(hdw, 6 + c)) + sh[c];
+      boxB[3 + c] = __longlong_as_double((long long)lane_word(hdw, 9 + c)) + sh[c];
     }
-    const int64_t pa0 = ves_patch_off[pr.a], pb0 = ves_patch_off[pr.b];
-    const int ptA = T.patch_off[S.topo_id[pr.a]], ptB = T.patch_off[S.topo_id[pr.b]];
-    const int vbA = S.vtx_off[pr.a], vbB = S.vtx_off[pr.b];
-    const int na = (int)(ves_patch_off[pr.a + 1] - pa0), nb = (int)(ves_patch_off[pr.b + 1] - pb0);
+    const int64_t pa0 = (int64_t)lane_word(hdw, 12), pb0 = (int64_t)lane_word(hdw, 14);
+    const int na = (int)((int64_t)lane_word(hdw, 13) - pa0), nb = (int)((int64_t)lane_word(hdw, 15) - pb0);
+    const int vbA = __builtin_amdgcn_readlane(hdi, 0), vbB = __builtin_amdgcn_readlane(hdi, 1);
+    const int ptA_v = T.patch_off[__builtin_amdgcn_readlane(hdi, 2)];
+    const int ptB_v = T.patch_off[__builtin_amdgcn_readlane(hdi, 3)];
+    // the next pair's record, in flight during this pair's patch loads
+    const int64_t pn = p + gridDim.x;
+    const uint64_t prw_n = pn < np ? pair_word(pairs, pn, lane) : 0;
     if (threadIdx.x == 0) { nA = 0; nB = 0; }
     __syncthreads();
     // compaction: a ballot per wavefront and one LDS atomic for its survivors.
     // Both vesicles' patches in one pass (A's, then B's), each thread loading
     // its patch's box and supports before any test: a pair waits for one
     // round of loads instead of four (A's boxes, A's supports, B's, B's).
-    const double shd[kDopDirs] = {pr.sh[0] + pr.sh[1], pr.sh[0] - pr.sh[1], pr.sh[0] + pr.sh[2],
-                                  pr.sh[0] - pr.sh[2], pr.sh[1] + pr.sh[2], pr.sh[1] - pr.sh[2]};
+    const double shd[kDopDirs] = {sh[0] + sh[1], sh[0] - sh[1], sh[0] + sh[2],
+                                  sh[0] - sh[2], sh[1] + sh[2], sh[1] - sh[2]};
     for (int k0 = 0; k0 < na + nb; k0 += blockDim.x) {
       const int k = k0 + threadIdx.x;
       const bool inA = k < na, inB = !inA && k < na + nb;
@@ -132,8 +188,8 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
           for (int j = 0; j < kDopVals; ++j) D[j] = patch_dop[kDopVals * slot + j];
         if (inB)
           for (int c = 0; c < 3; ++c) {
-            P[c] += pr.sh[c];
-            P[3 + c] += pr.sh[c];
+            P[c] += sh[c];
+            P[3 + c] += sh[c];
           }
         const bool kA = ov6(P, boxB), kB = ov6(P, boxA);
         keep = inA ? kA : kB;
@@ -162,6 +218,21 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
           }
         iB[qb] = (short)kk;
       }
+      // one pass covers both sides when 2 MAXP <= kPPThreads (the launch's
+      // workgroup size): no loop back edge, across which the next pair's
+      // loads in flight would be waited for before this pair's patch loads
+      if (2 * MAXP <= kPPThreads) break;
+    }
+    // taken to scalars here, before the next pair's loads are issued: a later
+    // use would wait for those too (loads complete in issue order)
+    const int ptA = __builtin_amdgcn_readfirstlane(ptA_v), ptB = __builtin_amdgcn_readfirstlane(ptB_v);
+    // the next pair's header, in flight during this pair's patch-pair tests
+    uint64_t hdw_n = 0;
+    int hdi_n = 0;
+    if (pn < np) {
+      const uint64_t ab = lane_word(prw_n, 0);
+      hdw_n = head_word(ves_box, ves_patch_off, ab, lane);
+      hdi_n = head_int(S, ab, lane);
     }
     __syncthreads();
     const int ma = nA, mb = nB;
@@ -196,6 +267,9 @@ __global__ __launch_bounds__(kPPThreads) void k_patch_pairs(DevScene S, DevTopo 
         __syncthreads();
       }
     }
+    prw = prw_n;
+    hdw = hdw_n;
+    hdi = hdi_n;
     __syncthreads();
   }
   __syncthreads();
